@@ -1,0 +1,260 @@
+"""Pins of the FP64 oracle against what mathematics fixes independently of the oracle's own code.
+
+Closed forms of exp(A) 1 (eq. 4) for complete, regular, complete-bipartite, star, path and empty
+graphs; exact rational Taylor sums on tiny graphs; two independent library routes (eigendecomposition
+vs Pade expm, scipy's expm_multiply); invariants (symmetry, permutation equivariance, disjoint
+union, shift invariance); Lanczos special cases (exactness when the Krylov space closes, breakdown).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import dense, taylor, tridiag, lanczos
+from tests import graphs_small as gs
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+# ---------------------------------------------------------------- closed forms (eq. 4)
+
+def closed_complete(n):
+    return np.full(n, math.exp(n - 1))
+
+
+def closed_regular(n, r):
+    return np.full(n, math.exp(r))
+
+
+def closed_bipartite(p, q):
+    a = math.sqrt(p * q)
+    side_p = math.cosh(a) + q * math.sinh(a) / a
+    side_q = math.cosh(a) + p * math.sinh(a) / a
+    return np.concatenate([np.full(p, side_p), np.full(q, side_q)])
+
+
+def closed_path(n):
+    k = np.arange(1, n + 1)
+    i = np.arange(1, n + 1)
+    U = np.sqrt(2.0 / (n + 1)) * np.sin(np.pi * np.outer(i, k) / (n + 1))  # columns = eigenvectors
+    lam = 2.0 * np.cos(np.pi * k / (n + 1))
+    return U @ (np.exp(lam) * (U.T @ np.ones(n)))
+
+
+CLOSED = [
+    ("K5", lambda: gs.complete(5), lambda: closed_complete(5)),
+    ("K37", lambda: gs.complete(37), lambda: closed_complete(37)),
+    ("C9", lambda: gs.cycle(9), lambda: closed_regular(9, 2)),
+    ("C40", lambda: gs.cycle(40), lambda: closed_regular(40, 2)),
+    ("K3_7", lambda: gs.bipartite(3, 7), lambda: closed_bipartite(3, 7)),
+    ("star12", lambda: gs.bipartite(1, 11), lambda: closed_bipartite(1, 11)),
+    ("P17", lambda: gs.path(17), lambda: closed_path(17)),
+    ("empty6", lambda: np.zeros((6, 6)), lambda: np.ones(6)),
+]
+
+
+def test_star_closed_form_matches_its_two_line_statement():
+    # hub: cosh a + a sinh a, leaves: cosh a + sinh(a)/a with a = sqrt(n - 1)
+    n = 12
+    a = math.sqrt(n - 1)
+    v = closed_bipartite(1, n - 1)
+    assert abs(v[0] - (math.cosh(a) + a * math.sinh(a))) < 1e-12 * v[0]
+    assert abs(v[1] - (math.cosh(a) + math.sinh(a) / a)) < 1e-12 * v[1]
+
+
+@pytest.mark.parametrize("name,mk,closed", CLOSED, ids=[c[0] for c in CLOSED])
+def test_dense_routes_closed_forms(name, mk, closed):
+    A = mk()
+    assert rel(dense.ebtc_eigh(A), closed()) < 1e-13
+    # scaling-and-squaring carries about u * ||A|| * (number of squarings) of rounding
+    assert rel(dense.ebtc_pade(A), closed()) < 1e-14 * max(10.0, np.abs(A).sum(axis=1).max()) * 10
+    s, lmax = dense.ebtc_eigh(A, shift=True)
+    assert rel(np.exp(lmax) * s, closed()) < 1e-13
+
+
+@pytest.mark.parametrize("name,mk,closed", CLOSED, ids=[c[0] for c in CLOSED])
+def test_lanczos_closed_forms(name, mk, closed):
+    A = sp.csr_matrix(mk())
+    res = lanczos.lanczos_expv(A, m=20)
+    assert rel(np.exp(res.theta) * res.u, closed()) < 1e-13
+
+
+@pytest.mark.parametrize("A,steps", [
+    (gs.complete(9), 1), (gs.cycle(11), 1), (np.zeros((5, 5)), 1), (gs.bipartite(3, 7), 2), (gs.bipartite(1, 9), 2),
+], ids=["K9", "C11", "empty", "K3_7", "star10"])
+def test_lanczos_breakdown_steps(A, steps):
+    res = lanczos.lanczos_expv(sp.csr_matrix(A), m=20)
+    assert res.m_used == steps
+    assert res.flags & lanczos.FLAG_BREAKDOWN
+
+
+def test_empty_graph_alpha_beta_zero():
+    res = lanczos.lanczos_expv(sp.csr_matrix(np.zeros((4, 4))), m=5)
+    assert res.alpha.tolist() == [0.0] and res.beta.tolist() == [0.0] and res.theta == 0.0
+    assert np.allclose(res.u, 1.0, rtol=0, atol=1e-15)
+
+
+def test_path_symmetric_krylov_space_closes():
+    # 1 lies in the reflection-symmetric subspace (dimension ceil(n/2)), so Lanczos ends there, exact.
+    n = 15
+    res = lanczos.lanczos_expv(sp.csr_matrix(gs.path(n)), m=40)
+    assert res.m_used == (n + 1) // 2
+    assert rel(np.exp(res.theta) * res.u, closed_path(n)) < 1e-13
+
+
+# ---------------------------------------------------------------- brute force: exact Taylor series
+
+@pytest.mark.parametrize("seed", range(6))
+def test_taylor_exact_vs_eigh(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(3, 11))
+    A = gs.random_graph(n, 0.45, seed)
+    exact = np.array([float(x) for x in taylor.ebtc_taylor_exact(A)])
+    assert rel(dense.ebtc_eigh(A), exact) < 1e-14
+    assert rel(dense.ebtc_pade(A), exact) < 1e-12
+
+
+def test_taylor_exact_closed_form_K4():
+    exact = taylor.ebtc_taylor_exact(gs.complete(4))
+    assert abs(float(exact[0]) - math.exp(3)) < 1e-14 * math.exp(3)
+
+
+# ---------------------------------------------------------------- two library routes, invariants
+
+@pytest.mark.parametrize("seed", range(4))
+def test_eigh_vs_pade_random(seed):
+    A = gs.random_graph(120, 0.08, seed, weighted=bool(seed % 2))
+    assert rel(dense.ebtc_eigh(A), dense.ebtc_pade(A)) < 1e-12
+
+
+def test_symmetry_rows_equal_columns():
+    A = gs.random_graph(60, 0.1, 7, weighted=True)
+    E = sla.expm(A)
+    assert np.max(np.abs(E - E.T)) < 1e-12 * np.max(np.abs(E))
+    assert rel(np.ones(60) @ E, dense.ebtc_eigh(A)) < 1e-12
+
+
+def test_subgraph_centrality_is_diagonal():
+    A = gs.random_graph(50, 0.15, 3)
+    assert rel(dense.subgraph_centrality(A), np.diag(sla.expm(A))) < 1e-12
+
+
+def test_permutation_equivariance():
+    A = gs.random_graph(80, 0.1, 11)
+    perm = np.random.default_rng(5).permutation(80)
+    P = np.eye(80)[perm]
+    s = dense.ebtc_eigh(A)
+    sp_ = dense.ebtc_eigh(P @ A @ P.T)
+    assert rel(sp_, P @ s) < 1e-12
+    r1 = lanczos.lanczos_expv(sp.csr_matrix(A), m=30)
+    r2 = lanczos.lanczos_expv(sp.csr_matrix(P @ A @ P.T), m=30)
+    assert rel(np.exp(r2.theta) * r2.u, P @ (np.exp(r1.theta) * r1.u)) < 1e-12
+
+
+def test_disjoint_union_is_concatenation():
+    A = gs.random_graph(30, 0.2, 1)
+    B = gs.random_graph(20, 0.3, 2)
+    U = sla.block_diag(A, B)
+    assert rel(dense.ebtc_eigh(U), np.concatenate([dense.ebtc_eigh(A), dense.ebtc_eigh(B)])) < 1e-12
+    res = lanczos.lanczos_expv(sp.csr_matrix(U), m=50)
+    assert rel(np.exp(res.theta) * res.u, dense.ebtc_eigh(U)) < 1e-12
+
+
+# ---------------------------------------------------------------- the small exponential
+
+def test_tridiag_two_by_two_closed_form():
+    a, c, b = 1.3, -0.4, 0.7
+    mean, half = (a + c) / 2, math.sqrt(((a - c) / 2) ** 2 + b * b)
+    # exp([[a,b],[b,c]]) e1 = e^mean [cosh h + (a-c)/(2h) sinh h, b/h sinh h]
+    ref = math.exp(mean) * np.array([math.cosh(half) + (a - c) / (2 * half) * math.sinh(half),
+                                     b / half * math.sinh(half)])
+    y, theta = tridiag.expv_e1([a, c], [b])
+    assert abs(theta - (mean + half)) < 1e-15
+    assert rel(np.exp(theta) * y, ref) < 1e-14
+
+
+@pytest.mark.parametrize("kind", ["random", "clustered", "split", "one"])
+def test_tridiag_vs_pade(kind):
+    rng = np.random.default_rng(42)
+    k = 1 if kind == "one" else 30
+    a = rng.normal(0, 4, k)
+    b = np.abs(rng.normal(0, 2, max(k - 1, 0)))
+    if kind == "clustered":
+        a = np.full(k, 3.0) + 1e-9 * rng.normal(size=k)
+        b = np.full(k - 1, 1e-7)
+    if kind == "split":
+        b[10] = 0.0
+    y, theta = tridiag.expv_e1(a, b)
+    T = tridiag.tridiag_dense(a, b)
+    ref = sla.expm(T - theta * np.eye(k))[:, 0]
+    assert rel(y, ref) < 1e-13
+    assert abs(theta - np.linalg.eigvalsh(T)[-1]) < 1e-12 * max(1.0, abs(theta))
+
+
+# ---------------------------------------------------------------- Lanczos vs the plain definition
+
+@pytest.mark.parametrize("seed", range(3))
+def test_lanczos_vs_dense_c0_shape(seed):
+    A = gs.random_graph(200, 0.1, 20 + seed)
+    res = lanczos.lanczos_expv(sp.csr_matrix(A), m=20)
+    s, lmax = dense.ebtc_eigh(A, shift=True)
+    assert abs(res.theta - lmax) < 1e-10
+    assert rel(res.u * np.exp(res.theta - lmax), s) < 1e-12
+
+
+def test_lanczos_vs_expm_multiply_large():
+    from fixtures import graphs as G
+    n = 20000
+    keys = G.er_keys(n, 20.0 / (n - 1), G.rng_for(99, 0, 1))
+    rp, ci = G.csr_from_keys(keys, n)
+    A = dense.csr_to_scipy(n, rp, ci)
+    res = lanczos.lanczos_expv(A, m=30)
+    ref = spla.expm_multiply(A - res.theta * sp.identity(n, format="csr"), np.ones(n))
+    assert rel(res.u, ref) < 1e-11
+
+
+def test_lanczos_basis_orthonormal_and_relation():
+    A = sp.csr_matrix(gs.random_graph(300, 0.05, 8))
+    res = lanczos.lanczos_expv(A, m=25, keep_basis=True)
+    V = res.V
+    assert np.max(np.abs(V.T @ V - np.eye(V.shape[1]))) < 1e-13
+    T = tridiag.tridiag_dense(res.alpha, res.beta[:-1])
+    R = A @ V - V @ T
+    # residual lives only in the last column, with norm beta_{m-1}
+    assert np.max(np.abs(R[:, :-1])) < 1e-12
+    assert abs(np.linalg.norm(R[:, -1]) - res.beta[-1]) < 1e-12
+
+
+def test_reorth_once_vs_twice_fp64():
+    A = sp.csr_matrix(gs.random_graph(400, 0.04, 9))
+    r1 = lanczos.lanczos_expv(A, m=30, reorth=1)
+    r2 = lanczos.lanczos_expv(A, m=30, reorth=2)
+    assert rel(r1.u, r2.u) < 1e-12 and abs(r1.theta - r2.theta) < 1e-12
+
+
+def test_shift_off_gives_same_product():
+    A = sp.csr_matrix(gs.random_graph(100, 0.05, 10))
+    r_on = lanczos.lanczos_expv(A, m=20)
+    r_off = lanczos.lanczos_expv(A, m=20, shift=False)
+    assert r_off.theta == 0.0
+    assert rel(r_off.u, np.exp(r_on.theta) * r_on.u) < 1e-13
+
+
+def test_adaptive_stop_and_cap():
+    A = sp.csr_matrix(gs.random_graph(500, 0.03, 12))
+    s, lmax = dense.ebtc_eigh(A.toarray(), shift=True)
+    r = lanczos.lanczos_expv(A, m=0, tol=1e-6, m_max=60)
+    assert r.est < 1e-6 and not (r.flags & lanczos.FLAG_CAPPED)
+    assert rel(r.u * np.exp(r.theta - lmax), s) < 1e-5
+    r_cap = lanczos.lanczos_expv(A, m=0, tol=1e-14, m_max=3)
+    assert r_cap.m_used == 3 and (r_cap.flags & lanczos.FLAG_CAPPED)
+    # the estimate is monotone enough to stop earlier for a looser tolerance
+    r_loose = lanczos.lanczos_expv(A, m=0, tol=1e-3, m_max=60)
+    assert r_loose.m_used < r.m_used
