@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Throughput of the Krylov exp(A)·1 communicability path on one MI355X.
+
+One step = the whole hot path over one batch already resident in HBM: all Lanczos solves of every
+realization (batched schedule, replayed hipGraph), the realization sum with per-graph log-scale and
+the top-K selection. Default workload: ER n=1e5, degree 20, 64 realizations, 50-node target, FP32,
+m=30 (the batched-realizations configuration).
+
+Prints ONE JSON line on stdout (progress goes to stderr):
+  value          graph-realizations/s (batched form), whole job on one GPU
+  plain          the per-realization loop on the same batch, and the batched/plain factor
+  roofline       dominant kernel (SpMV + dot partials): algorithmic bytes per launch / average launch
+                 time, both measured live with HIP events on the launch stream, against 8 TB/s
+  cpu_baseline   the FP64 oracle timed on this host's cores over the same workload
+  parity         GPU scores vs the oracle (normwise and top-2K error, top-K set match)
+
+    python bench.py [--steps K] [--warmup W] [--config 1] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "graph-realizations/s for Krylov exp(A)·1 + achieved HBM GB/s; batched vs plain"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_spmv_dots.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1409_5000_amd", "csrc", f) for f in ("k_lanczos.hip", "internal.h")]
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------- algorithmic byte model (per launch)
+# n rows, z stored entries, j = step, es = vector/value element bytes; every array element touched
+# once per launch (the gathered vector counted once: n elements).
+
+def spmv_dots_bytes(n, z, j, es, has_val):
+    return 4 * (n + 1) + z * (4 + (es if has_val else 0)) + n * es + (j + 1) * n * es + n * es
+
+
+def update_bytes(n, j, es):
+    return n * es + (j + 1) * n * es + n * es
+
+
+def combine_bytes(n, k, es):
+    return (k + 1) * n * es
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(achieved_bytes_per_launch: float):
+    """HBM bytes per spmv_dots launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workers", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (realizations and graphs "
+              "are independent, so a multi-GPU run would shard them; this build runs on one GPU).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from fixtures import configs as C
+    from paper_1409_5000_amd import api
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    try:
+        P = len(os.sched_getaffinity(0))
+    except AttributeError:
+        P = os.cpu_count() or 1
+    P = min(P, 16)
+    workers = args.workers or P
+
+    w = C.workload(args.config)
+    t0 = time.time()
+    hb = C.build_parallel(w, workers=workers)
+    log(f"generated {w.name}: R={hb.R} nnz={hb.nnz_off[-1]} in {time.time() - t0:.1f}s")
+    m, tol, m_max = w.m, (w.tol or 1e-6), (w.m_max or 60)
+    b = api.Batch.from_host(hb)
+    es = 8 if w.dtype == "f64" else 4
+    has_val = hb.values is not None
+    K = hb.K
+
+    run = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=True, diag=True)
+
+    def step(r):
+        out = r.launch()
+        b.topk(out.scores, K)
+
+    for _ in range(args.warmup):
+        step(run)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} done")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step(run)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = 1000.0 * wall / args.steps
+    value = hb.R * args.steps / wall
+    log(f"batched: {ms_per_step:.3f} ms/step, {value:.1f} realizations/s (events {gpu_ms / args.steps:.3f} ms/step)")
+    gpu_scores = run.scores.double().cpu().numpy()
+    gpu_ls = run.log_scale.cpu().numpy()
+
+    # plain per-realization loop on the same batch
+    runp = b.run(m=m, tol=tol, m_max=m_max, schedule="plain", hipgraph=False, diag=False)
+    step(runp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.plain_steps):
+        step(runp)
+    torch.cuda.synchronize()
+    plain_wall = time.perf_counter() - t0
+    plain_value = hb.R * args.plain_steps / plain_wall
+    log(f"plain: {1000 * plain_wall / args.plain_steps:.3f} ms/step, {plain_value:.1f} realizations/s")
+
+    # per-kernel durations with HIP events around each launch (eager batched sequence)
+    rune = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=False, diag=True)
+    rune.profile()
+    phases = rune.profile()
+    d = rune.launch().diag_numpy()
+    torch.cuda.synchronize()
+    m_used = d["m_used"]
+    sd_bytes = 0.0
+    up_bytes = 0.0
+    for r in range(hb.R):
+        n, rp, ci, _ = hb.csr(r)
+        z = ci.size
+        for j in range(int(m_used[r])):
+            sd_bytes += spmv_dots_bytes(n, z, j, es, has_val)
+            up_bytes += update_bytes(n, j, es)
+    sd_ms, sd_launches = phases["spmv_dots"]
+    up_ms, up_launches = phases["update"]
+    dominant = max(phases, key=lambda p: phases[p][0])
+    achieved = sd_bytes / (sd_ms * 1e-3) / 1e9
+    per_launch = sd_bytes / max(1, sd_launches)
+    traffic = load_traffic(per_launch)
+    total_alg = sd_bytes + up_bytes + sum(combine_bytes(int(hb.n[hb.graph_of[r]]), int(m_used[r]), es)
+                                          for r in range(hb.R))
+    log("phases (ms, launches): " + ", ".join(f"{p}={v[0]:.3f}/{v[1]}" for p, v in phases.items()))
+    log(f"spmv_dots: {achieved:.0f} GB/s algorithmic; update: {up_bytes / (up_ms * 1e-3) / 1e9:.0f} GB/s")
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "graph-realizations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": w.dtype,
+        "data": "synthetic (seeded ER/WS/BA realizations with an embedded target, generated on the host)",
+        "config": {"workload": w.name, "graphs": int(hb.n.size), "realizations": hb.R,
+                   "n": [int(x) for x in hb.n], "nnz_total": int(hb.nnz_off[-1]), "m": m,
+                   "adaptive_tol": w.tol if m == 0 else None, "reorth": 1, "K": [int(x) for x in K[:4]],
+                   "schedule": "batched, hipGraph replay", "parallelism": "1 GPU"},
+        "plain": {"value": round(plain_value, 2), "ms_per_step": round(1000 * plain_wall / args.plain_steps, 3),
+                  "batched_over_plain": round(value / plain_value, 2)},
+        "effective_GBps_whole_path": round(total_alg * args.steps / wall / 1e9, 1),
+        "roofline": {"bound": "hbm", "kernel": "k_spmv_dots (SpMV + dot partials)", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "alg_bytes_per_launch": round(per_launch),
+                     "avg_launch_ms": round(sd_ms / max(1, sd_launches), 5), "dominant_phase": dominant,
+                     "phase_ms": {p: round(v[0], 4) for p, v in phases.items()}},
+        "cpu_baseline": None,
+        "parity": None,
+    }
+
+    if not args.no_cpu_baseline:
+        from oracle import scores as oscores
+        t0 = time.perf_counter()
+        ref = oscores.batch_scores(hb, m=m, tol=w.tol, m_max=m_max, workers=P)
+        cpu_wall = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": round(hb.R / cpu_wall, 3), "unit": "graph-realizations/s", "cores": P,
+                                  "kind": "oracle",
+                                  "sample": f"all {hb.R} realizations of {w.name}, FP64 Lanczos (CGS2), "
+                                            f"{P} single-threaded worker processes, {cpu_wall:.1f}s wall"}
+        errs = []
+        top_ok = True
+        idx_all, _ = b.topk(run.scores, K)
+        idx_all = idx_all.cpu().numpy()
+        off = 0
+        for g, gsc in enumerate(ref):
+            sl = b.graph_slice(g)
+            s_hat = gpu_scores[sl] * np.exp(gpu_ls[g] - gsc.log_scale)
+            en = float(np.max(np.abs(s_hat - gsc.s)) / np.max(np.abs(gsc.s)))
+            kk = int(K[g])
+            top2 = oscores.topk(gsc.s, min(2 * kk, gsc.s.size))
+            et = float(np.max(np.abs(s_hat[top2] - gsc.s[top2]) / np.abs(gsc.s[top2])))
+            errs.append((en, et))
+            top_ok &= set(idx_all[off:off + kk].tolist()) == set(oscores.topk(gsc.s, kk).tolist())
+            off += kk
+        result["parity"] = {"err_norm_max": max(e[0] for e in errs), "err_top_max": max(e[1] for e in errs),
+                            "topk_sets_identical": bool(top_ok), "tolerance": 1e-5 if w.dtype == "f32" else 1e-12}
+        log(f"oracle: {cpu_wall:.1f}s on {P} cores; parity {result['parity']}")
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -205,3 +205,31 @@ def build(w: Workload, with_values: bool = True, realizations: int | None = None
         N = spec.N if realizations is None else min(spec.N, realizations)
         parts.append((spec, d.targets, [realization(w.ci, g, k, d) for k in range(N)]))
     return assemble(parts, w.dtype, with_values)
+
+
+def _gen_one(args):
+    ci, g, k, draw = args
+    return realization(ci, g, k, draw)
+
+
+def build_parallel(w: Workload, workers: int = 8, with_values: bool = True,
+                   realizations: int | None = None) -> HostBatch:
+    """build() with the realizations generated by a process pool (same seeds, same result)."""
+    import multiprocessing as mp
+    draws = [draw_graph(w.ci, g, spec) for g, spec in enumerate(w.graphs)]
+    jobs = []
+    for g, (spec, d) in enumerate(zip(w.graphs, draws)):
+        N = spec.N if realizations is None else min(spec.N, realizations)
+        jobs += [(w.ci, g, k, d) for k in range(N)]
+    if workers > 1 and len(jobs) > 1:
+        with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
+            out = pool.map(_gen_one, jobs, chunksize=1)
+    else:
+        out = [_gen_one(j) for j in jobs]
+    parts = []
+    i = 0
+    for g, (spec, d) in enumerate(zip(w.graphs, draws)):
+        N = spec.N if realizations is None else min(spec.N, realizations)
+        parts.append((spec, d.targets, out[i:i + N]))
+        i += N
+    return assemble(parts, w.dtype, with_values)

@@ -1,0 +1,199 @@
+/*
+ * ebtc.h -- C ABI of the MI355X (gfx950) Estrada-Benzi total-communicability library.
+ *
+ * What the library computes (Fioriti & Chinnici, arXiv 1409.5000, "Identification algorithm"):
+ *   for each graph g with realizations A_{g,1..N_g} on the same n_g nodes,
+ *     EBTC_{g,k} = exp(A_{g,k}) 1                      eq. (4), row sums of the matrix exponential,
+ *                                                      by an m-step Lanczos (Krylov) approximation
+ *     S_g        = sum_k EBTC_{g,k}                     eq. (5), plain sum over realizations
+ *     top-K(S_g)                                       the K largest summed scores are the candidate
+ *                                                      target nodes ("The total communicability")
+ *   To keep exp(A) finite the sum is returned in scaled form: S_g = e^{Sigma_g} * S~_g with one FP64
+ *   log-scale Sigma_g per graph (Sigma_g = max_k theta*_k, theta*_k the largest Ritz value).
+ *
+ * Conventions
+ *   - Every call returns an int status (EBTC_OK = 0). Arguments are checked before anything is
+ *     enqueued, so a failing call has no side effect and leaves every output untouched;
+ *     ebtc_last_error() then holds a thread-local message.
+ *   - "device" pointers are HIP device allocations on the current device; "host" pointers are
+ *     ordinary host memory. The library never allocates device memory: the caller passes a workspace
+ *     whose size ebtc_plan() reports. Device pointers in a batch are borrowed and must outlive it.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream). Calls that take a stream
+ *     are asynchronous on it unless stated otherwise.
+ *   - Conditions found on the device never fail a call; they set ebtc_diag.flags.
+ *   - A batch is not thread-safe; distinct batches are. Two calls that share a workspace race.
+ */
+#ifndef EBTC_H
+#define EBTC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EBTC_VERSION_MAJOR 0
+#define EBTC_VERSION_MINOR 1
+#define EBTC_M_LIMIT 64      /* largest Krylov dimension (fixed m or adaptive cap) */
+#define EBTC_TOPK_LIMIT 4096 /* largest K per graph in ebtc_topk */
+
+enum ebtc_status {
+  EBTC_OK = 0,
+  EBTC_EINVAL = 1,        /* bad argument: NULL where not allowed, size or option out of range   */
+  EBTC_EBADGRAPH = 2,     /* inconsistent batch description, or ebtc_validate found a bad graph  */
+  EBTC_EWORKSPACE = 3,    /* workspace (or checkpoint) smaller than ebtc_plan reported           */
+  EBTC_EHIP = 4,          /* a HIP runtime call failed                                           */
+  EBTC_ENOTSUPPORTED = 5  /* well-formed request outside what this library implements            */
+};
+
+enum ebtc_dtype { EBTC_F32 = 0, EBTC_F64 = 1 };
+
+enum ebtc_schedule {
+  EBTC_SCHED_AUTO = 0,     /* library picks (batched)                                              */
+  EBTC_SCHED_PLAIN = 1,    /* one realization at a time: about 2m + 4 kernel launches per realization */
+  EBTC_SCHED_BATCHED = 2   /* all realizations of all graphs advance together, one launch per
+                              Lanczos phase, optionally replayed from a captured hipGraph          */
+};
+
+enum ebtc_flags {
+  EBTC_FLAG_BREAKDOWN = 1, /* Krylov space closed early (beta_j ~ 0): result exact, informational */
+  EBTC_FLAG_CAPPED = 2,    /* adaptive mode reached m_max before the estimate met tol             */
+  EBTC_FLAG_NONFINITE = 4  /* a non-finite value appeared (e.g. overflow with shift = 0)          */
+};
+
+typedef struct ebtc_batch ebtc_batch; /* opaque */
+
+/*
+ * A batch: G graphs, graph g has n_g nodes and N_g realizations; R = sum_g N_g realizations in
+ * graph order (all realizations of graph 0, then graph 1, ...). Each realization is a CSR matrix of
+ * a simple undirected graph ("Signal processing on graphs": symmetric 0/1 adjacency), stored
+ * symmetrically (both (i,j) and (j,i)), columns sorted within a row, no self-loops.
+ */
+typedef struct {
+  int32_t dtype;               /* EBTC_F32 or EBTC_F64: type of values, vectors and scores          */
+  int32_t num_graphs;          /* G >= 1                                                           */
+  int64_t num_realizations;    /* R = sum_g graph_nreal[g]                                         */
+  const int32_t* graph_n;      /* host [G]: n_g >= 1                                               */
+  const int32_t* graph_nreal;  /* host [G]: N_g >= 1                                               */
+  const int64_t* rowptr_off;   /* host [R]: realization r's row pointers are row_ptr[rowptr_off[r] ..
+                                  rowptr_off[r] + n_g], local (first entry 0, last = its nnz)       */
+  const int64_t* nnz_off;      /* host [R+1]: realization r's entries are [nnz_off[r], nnz_off[r+1])
+                                  of col_idx / values; nnz_off[0] = 0, non-decreasing               */
+  const int32_t* row_ptr;      /* device int32                                                     */
+  const int32_t* col_idx;      /* device int32, local node ids in [0, n_g)                         */
+  const void* values;          /* device, dtype, one weight per stored entry; NULL = all ones      */
+} ebtc_batch_desc;
+
+typedef struct {
+  int32_t m;             /* fixed Krylov dimension 1..EBTC_M_LIMIT; 0 = adaptive                  */
+  int32_t m_max;         /* adaptive cap 1..EBTC_M_LIMIT                                          */
+  double tol;            /* adaptive stop: Saad's relative estimate beta_j |y_j| / ||y|| < tol     */
+  int32_t reorth;        /* classical Gram-Schmidt passes per step against the whole basis: 1 or 2 */
+  int32_t schedule;      /* enum ebtc_schedule                                                    */
+  int32_t use_hipgraph;  /* batched schedule: capture the launch sequence once, replay it after    */
+  int32_t shift;         /* 1 (default): factor out theta*; 0: theta* = 0 (overflow-prone, tests)  */
+  int32_t lanes_per_row; /* SpMV lanes per CSR row: 0 = auto, else 4, 8, 16 or 32                 */
+  int32_t hub_threshold; /* rows with more entries are reduced by a whole workgroup; 0 = auto     */
+} ebtc_opts;
+
+/* Per-realization diagnostics (device array [R], written by ebtc_scores). */
+typedef struct {
+  int32_t m_used;  /* Lanczos steps taken (size of T)                                              */
+  int32_t flags;   /* enum ebtc_flags                                                              */
+  double theta;    /* theta*: the largest Ritz value, the realization's log-scale                  */
+  double est;      /* Saad's relative error estimate at the last step (0 after a breakdown)        */
+} ebtc_diag;
+
+/* ---------------------------------------------------------------- library information            */
+int ebtc_version(int* major, int* minor);
+const char* ebtc_status_str(int status);
+/* Message of the last failing call on this thread ("" if none). Valid until the next call. */
+const char* ebtc_last_error(void);
+/* Fills defaults: m = 30, m_max = 60, tol = 1e-6, reorth = 1, schedule AUTO, hipgraph on, shift on. */
+void ebtc_default_opts(ebtc_opts* opts);
+
+/* ---------------------------------------------------------------- batch                          */
+/* Host-only. Copies the host arrays of `desc`, checks counts and offsets (n_g >= 1, N_g >= 1,
+ * R = sum N_g, nnz_off non-decreasing from 0, each realization's nnz < 2^31, dtype known) and
+ * records the borrowed device pointers. EBTC_EINVAL for NULL or out-of-range fields,
+ * EBTC_EBADGRAPH for inconsistent offsets. The O(nnz) structural check is ebtc_validate. */
+int ebtc_batch_create(const ebtc_batch_desc* desc, ebtc_batch** out);
+/* Frees host-side state (and captured graphs). NULL-safe. Never frees caller memory. */
+void ebtc_batch_destroy(ebtc_batch* batch);
+
+/* Host-only. Workspace bytes ebtc_scores needs for `opts` (all realizations resident), and the
+ * checkpoint bytes ebtc_scores_backward needs (0 if not requested). Also validates opts. */
+int ebtc_plan(ebtc_batch* batch, const ebtc_opts* opts, size_t* ws_bytes, size_t* ckpt_bytes);
+
+/* ---------------------------------------------------------------- forward                        */
+/* Scaled summed scores, eq. (4)-(5), asynchronous on `stream`.
+ *   ws, ws_bytes   device workspace of at least the planned size (contents need no initialisation)
+ *   scores_out     device [sum_g n_g] of dtype: S~_g for graph 0, then graph 1, ...
+ *   log_scale_out  device [G] double: Sigma_g; the summed score is e^{Sigma_g} S~_g
+ *   ckpt_out       device checkpoint of the planned size for ebtc_scores_backward, or NULL
+ *   diag_out       device [R] ebtc_diag, or NULL
+ * Lanczos: start vector 1/sqrt(n), full reorthogonalisation against the whole basis, FP64
+ * tridiagonal exponential; breakdown (beta_j <= 64 eps max(|alpha|, beta)) ends a realization early.
+ * Realizations of a graph are summed in k order with FP64 weights e^{theta*_k - Sigma_g}. */
+int ebtc_scores(ebtc_batch* batch, const ebtc_opts* opts, void* ws, size_t ws_bytes, void* scores_out,
+                double* log_scale_out, void* ckpt_out, ebtc_diag* diag_out, void* stream);
+
+/* ---------------------------------------------------------------- selection                      */
+/* Device workspace bytes for ebtc_topk (host-only). */
+int ebtc_topk_ws_bytes(ebtc_batch* batch, size_t* ws_bytes);
+/* K_g largest entries of each graph's score block ("The total communicability": the largest
+ * values are the candidates), asynchronous on `stream`.
+ *   scores       device [sum_g n_g] of dtype (as written by ebtc_scores)
+ *   k_per_graph  host [G], 0 <= K_g <= min(n_g, EBTC_TOPK_LIMIT)
+ *   idx_out      device int32 [sum_g K_g]: graph 0's K_0 ids, then graph 1's ...; each block sorted
+ *                by descending score, equal scores by ascending node id
+ *   val_out      device [sum_g K_g] of dtype, or NULL
+ * NaN scores are not supported (ordering undefined). */
+int ebtc_topk(ebtc_batch* batch, const void* scores, const int32_t* k_per_graph, int32_t* idx_out,
+              void* val_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- component entry points         */
+/* y = A x for one CSR matrix (the Krylov step's product), asynchronous. Same CSR rules as a batch;
+ * values NULL = all ones; x, y device [n] of dtype, distinct. lanes_per_row / hub_threshold as in
+ * ebtc_opts. */
+int ebtc_spmv(int32_t dtype, int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const void* values,
+              const void* x, void* y, int32_t lanes_per_row, int32_t hub_threshold, void* stream);
+
+/* For `count` symmetric tridiagonal matrices of size k (1 <= k <= EBTC_M_LIMIT), FP64, asynchronous:
+ * theta_out[c] = largest eigenvalue (0 when shift == 0) and y_out[c*k ..] = exp(T_c - theta I) e1.
+ *   alpha  device [count*k] diagonals;  beta device [count*k] off-diagonals (entry i couples rows
+ *   i and i+1; entry k-1 of each matrix is ignored). */
+int ebtc_tridiag_expv(int32_t count, int32_t k, const double* alpha, const double* beta, double* y_out,
+                      double* theta_out, int32_t shift, void* stream);
+
+/* ---------------------------------------------------------------- measurement                    */
+enum ebtc_phase {
+  EBTC_PHASE_START = 0,      /* start vector and state initialisation                           */
+  EBTC_PHASE_SPMV_DOTS = 1,  /* w = A v_j and the partial dots <v_i, w>                         */
+  EBTC_PHASE_DOTS_AGAIN = 2, /* second Gram-Schmidt pass: dots (reorth = 2 only)                */
+  EBTC_PHASE_UPDATE = 3,     /* Gram-Schmidt update, norm, breakdown test                       */
+  EBTC_PHASE_TRIDIAG = 4,    /* FP64 tridiagonal exponential (final and adaptive checks)        */
+  EBTC_PHASE_COMBINE = 5,    /* u = beta0 V y                                                    */
+  EBTC_PHASE_SUM = 6,        /* realization sum with per-graph log-scale                        */
+  EBTC_PHASE_COUNT = 7
+};
+/* Measurement only: runs ebtc_scores' batched launch sequence once, eagerly (no hipGraph), with a
+ * HIP event recorded on `stream` before and after every kernel launch, then synchronises the
+ * stream. Outputs are those of ebtc_scores (ckpt and diag not written).
+ *   phase_ms        host [EBTC_PHASE_COUNT]: summed kernel milliseconds per phase (overwritten)
+ *   phase_launches  host [EBTC_PHASE_COUNT]: number of launches per phase (overwritten) */
+int ebtc_profile_phases(ebtc_batch* batch, const ebtc_opts* opts, void* ws, size_t ws_bytes, void* scores_out,
+                        double* log_scale_out, double* phase_ms, int64_t* phase_launches, void* stream);
+
+/* ---------------------------------------------------------------- checking                       */
+/* Synchronous structural check of every realization on the device: columns in [0, n), strictly
+ * increasing within a row (no duplicates), no self-loops, symmetric pattern, row_ptr monotone from 0.
+ * *first_bad = index of the first bad realization, or -1. ws: device, >= ebtc_validate_ws_bytes. */
+int ebtc_validate_ws_bytes(ebtc_batch* batch, size_t* ws_bytes);
+int ebtc_validate(ebtc_batch* batch, void* ws, size_t ws_bytes, int64_t* first_bad, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EBTC_H */

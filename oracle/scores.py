@@ -40,8 +40,12 @@ def realization_result(batch, r: int, m: int, tol: float, m_max: int, shift: boo
     return lanczos.lanczos_expv(A, m=m, tol=tol, m_max=m_max, shift=shift, reorth=reorth)
 
 
+_SHARED = {}  # the batch, inherited by forked worker processes instead of being pickled per job
+
+
 def _one(args):
-    batch, r, m, tol, m_max, shift, reorth = args
+    r, m, tol, m_max, shift, reorth = args
+    batch = _SHARED["batch"]
     try:
         from threadpoolctl import threadpool_limits
         with threadpool_limits(1):
@@ -63,13 +67,17 @@ def realization_sum(results: list) -> tuple[np.ndarray, float]:
 def batch_scores(batch, m: int = 0, tol: float = 0.0, m_max: int = 60, shift: bool = True, reorth: int = 2,
                  workers: int = 1, realizations: list | None = None) -> list[GraphScores]:
     rs = list(range(batch.R)) if realizations is None else list(realizations)
-    jobs = [(batch, r, m, tol, m_max, shift, reorth) for r in rs]
-    if workers > 1 and len(jobs) > 1:
-        import multiprocessing as mp
-        with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
-            res = pool.map(_one, jobs, chunksize=1)
-    else:
-        res = [_one(j) for j in jobs]
+    jobs = [(r, m, tol, m_max, shift, reorth) for r in rs]
+    _SHARED["batch"] = batch
+    try:
+        if workers > 1 and len(jobs) > 1:
+            import multiprocessing as mp
+            with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
+                res = pool.map(_one, jobs, chunksize=1)
+        else:
+            res = [_one(j) for j in jobs]
+    finally:
+        _SHARED.pop("batch", None)
     by_graph: dict[int, list] = {}
     for r, x in zip(rs, res):
         by_graph.setdefault(int(batch.graph_of[r]), []).append(x)

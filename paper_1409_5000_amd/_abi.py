@@ -1,0 +1,105 @@
+"""ctypes declarations of the C ABI in include/ebtc.h (argument marshalling only).
+
+The library is libebtc.so next to this file, built by paper_1409_5000_amd.build. Importing the
+binding never falls back to anything else: if the library is missing the import fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libebtc.so")
+
+EBTC_OK, EBTC_EINVAL, EBTC_EBADGRAPH, EBTC_EWORKSPACE, EBTC_EHIP, EBTC_ENOTSUPPORTED = range(6)
+EBTC_F32, EBTC_F64 = 0, 1
+SCHED_AUTO, SCHED_PLAIN, SCHED_BATCHED = 0, 1, 2
+FLAG_BREAKDOWN, FLAG_CAPPED, FLAG_NONFINITE = 1, 2, 4
+M_LIMIT = 64
+TOPK_LIMIT = 4096
+CKPT_DOUBLES = 2 * M_LIMIT + 4
+
+EXPORTED = [
+    "ebtc_version", "ebtc_status_str", "ebtc_last_error", "ebtc_default_opts", "ebtc_batch_create",
+    "ebtc_batch_destroy", "ebtc_plan", "ebtc_scores", "ebtc_topk_ws_bytes", "ebtc_topk", "ebtc_spmv",
+    "ebtc_tridiag_expv", "ebtc_validate_ws_bytes", "ebtc_validate", "ebtc_profile_phases",
+]
+PHASES = ["start", "spmv_dots", "dots_again", "update", "tridiag", "combine", "sum"]
+
+
+class BatchDesc(ctypes.Structure):
+    _fields_ = [
+        ("dtype", c_int32), ("num_graphs", c_int32), ("num_realizations", c_int64),
+        ("graph_n", POINTER(c_int32)), ("graph_nreal", POINTER(c_int32)),
+        ("rowptr_off", POINTER(c_int64)), ("nnz_off", POINTER(c_int64)),
+        ("row_ptr", c_void_p), ("col_idx", c_void_p), ("values", c_void_p),
+    ]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("m", c_int32), ("m_max", c_int32), ("tol", c_double), ("reorth", c_int32), ("schedule", c_int32),
+        ("use_hipgraph", c_int32), ("shift", c_int32), ("lanes_per_row", c_int32), ("hub_threshold", c_int32),
+    ]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("m_used", c_int32), ("flags", c_int32), ("theta", c_double), ("est", c_double)]
+
+
+class EbtcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ebtc status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1409_5000_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz = c_void_p, c_size_t
+    sig = {
+        "ebtc_version": (c_int, [POINTER(c_int), POINTER(c_int)]),
+        "ebtc_status_str": (c_char_p, [c_int]),
+        "ebtc_last_error": (c_char_p, []),
+        "ebtc_default_opts": (None, [POINTER(Opts)]),
+        "ebtc_batch_create": (c_int, [POINTER(BatchDesc), POINTER(vp)]),
+        "ebtc_batch_destroy": (None, [vp]),
+        "ebtc_plan": (c_int, [vp, POINTER(Opts), POINTER(sz), POINTER(sz)]),
+        "ebtc_scores": (c_int, [vp, POINTER(Opts), vp, sz, vp, vp, vp, vp, vp]),
+        "ebtc_topk_ws_bytes": (c_int, [vp, POINTER(sz)]),
+        "ebtc_topk": (c_int, [vp, vp, POINTER(c_int32), vp, vp, vp, sz, vp]),
+        "ebtc_spmv": (c_int, [c_int32, c_int32, vp, vp, vp, vp, vp, c_int32, c_int32, vp]),
+        "ebtc_tridiag_expv": (c_int, [c_int32, c_int32, vp, vp, vp, vp, c_int32, vp]),
+        "ebtc_validate_ws_bytes": (c_int, [vp, POINTER(sz)]),
+        "ebtc_validate": (c_int, [vp, vp, sz, POINTER(c_int64), vp]),
+        "ebtc_profile_phases": (c_int, [vp, POINTER(Opts), vp, sz, vp, vp, POINTER(c_double), POINTER(c_int64), vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def check(status: int) -> None:
+    if status != EBTC_OK:
+        raise EbtcError(status, lib().ebtc_last_error().decode())
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib().ebtc_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o

@@ -1,0 +1,191 @@
+"""Python face of the EBTC library: device batches, summed communicability scores, top-K.
+
+Everything computational runs in the HIP library through the C ABI (paper_1409_5000_amd._abi);
+this module only allocates device memory with torch, marshals pointers and picks the stream.
+
+    b = Batch.from_host(host_batch)                 # CSR realizations copied to the GPU
+    out = b.scores(m=30)                             # S~ per graph (scaled), log-scales, diagnostics
+    idx, val = b.topk(out.scores, k=[50])            # candidate target nodes per graph
+
+The summed score of graph g (eq. (5) of the paper: the plain sum over realizations of
+exp(A_k) 1, eq. (4)) is exp(log_scale[g]) * scores[g-block].
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+_DT = {"f32": (A.EBTC_F32, torch.float32, np.float32), "f64": (A.EBTC_F64, torch.float64, np.float64)}
+_SCHED = {"auto": A.SCHED_AUTO, "plain": A.SCHED_PLAIN, "batched": A.SCHED_BATCHED}
+
+
+def _vp(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def current_stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_opts(m: int = 30, tol: float = 1e-6, m_max: int = 60, reorth: int = 1, schedule: str = "batched",
+              hipgraph: bool = True, shift: bool = True, lanes: int = 0, hub: int = 0) -> A.Opts:
+    return A.default_opts(m=m, tol=tol, m_max=m_max, reorth=reorth, schedule=_SCHED[schedule],
+                          use_hipgraph=int(hipgraph), shift=int(shift), lanes_per_row=lanes, hub_threshold=hub)
+
+
+@dataclass
+class ScoreResult:
+    scores: torch.Tensor     # [sum_g n_g] dtype: S~ per graph, concatenated
+    log_scale: torch.Tensor  # [G] float64: Sigma_g
+    diag: torch.Tensor | None  # [R, 3] float64 view: (m_used, flags, theta, est) via diag_numpy()
+    ckpt: torch.Tensor | None
+    raw_diag: torch.Tensor | None = None
+
+    def diag_numpy(self) -> np.ndarray:
+        """Structured host copy of the per-realization diagnostics."""
+        if self.raw_diag is None:
+            return None
+        host = self.raw_diag.cpu().numpy().tobytes()
+        return np.frombuffer(host, dtype=np.dtype([("m_used", "<i4"), ("flags", "<i4"), ("theta", "<f8"),
+                                                   ("est", "<f8")]))
+
+
+class Run:
+    """Workspace and output buffers for repeated ebtc_scores calls with fixed options.
+
+    Reusing a Run keeps every device pointer fixed, so the batched schedule replays its captured
+    hipGraph instead of re-capturing it."""
+
+    def __init__(self, batch: "Batch", opts: A.Opts, diag: bool = True, ckpt: bool = False):
+        self.batch = batch
+        self.opts = opts
+        ws = ctypes.c_size_t()
+        ck = ctypes.c_size_t()
+        A.check(A.lib().ebtc_plan(batch.handle, ctypes.byref(opts), ctypes.byref(ws), ctypes.byref(ck)))
+        dev = batch.device
+        self.ws_bytes = ws.value
+        self.ws = torch.empty(max(1, ws.value), dtype=torch.uint8, device=dev)
+        self.scores = torch.empty(batch.total_scores, dtype=batch.tdtype, device=dev)
+        self.log_scale = torch.empty(batch.G, dtype=torch.float64, device=dev)
+        self.raw_diag = torch.empty(batch.R * ctypes.sizeof(A.Diag), dtype=torch.uint8, device=dev) if diag else None
+        self.ckpt = torch.empty(max(1, ck.value) // 8, dtype=torch.float64, device=dev) if ckpt else None
+
+    def launch(self) -> ScoreResult:
+        A.check(A.lib().ebtc_scores(self.batch.handle, ctypes.byref(self.opts), _vp(self.ws), self.ws_bytes,
+                                    _vp(self.scores), _vp(self.log_scale), _vp(self.ckpt), _vp(self.raw_diag),
+                                    current_stream()))
+        return ScoreResult(self.scores, self.log_scale, None, self.ckpt, self.raw_diag)
+
+
+    def profile(self) -> dict:
+        """Eager run with a HIP event pair around every launch: {phase: (total_ms, launches)}."""
+        ms = (ctypes.c_double * len(A.PHASES))()
+        cnt = (ctypes.c_int64 * len(A.PHASES))()
+        A.check(A.lib().ebtc_profile_phases(self.batch.handle, ctypes.byref(self.opts), _vp(self.ws), self.ws_bytes,
+                                            _vp(self.scores), _vp(self.log_scale), ms, cnt, current_stream()))
+        return {p: (ms[i], cnt[i]) for i, p in enumerate(A.PHASES)}
+
+
+class Batch:
+    """G graphs x N_g realizations as device CSR arrays (borrowed by the native batch handle)."""
+
+    def __init__(self, graph_n, graph_nreal, rowptr_off, nnz_off, row_ptr, col_idx, values=None, dtype: str = "f32",
+                 device: str = "cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the EBTC library needs a GPU")
+        self.dtype = dtype
+        self.code, self.tdtype, self.ndtype = _DT[dtype]
+        self.device = torch.device(device)
+        self.graph_n = np.ascontiguousarray(graph_n, dtype=np.int32)
+        self.graph_nreal = np.ascontiguousarray(graph_nreal, dtype=np.int32)
+        self.rowptr_off = np.ascontiguousarray(rowptr_off, dtype=np.int64)
+        self.nnz_off = np.ascontiguousarray(nnz_off, dtype=np.int64)
+        self.G = int(self.graph_n.size)
+        self.R = int(self.rowptr_off.size)
+        self.total_scores = int(self.graph_n.sum())
+        self.row_ptr = torch.as_tensor(np.ascontiguousarray(row_ptr, dtype=np.int32)).to(self.device)
+        self.col_idx = torch.as_tensor(np.ascontiguousarray(col_idx, dtype=np.int32)).to(self.device)
+        self.values = None if values is None else torch.as_tensor(
+            np.ascontiguousarray(values, dtype=self.ndtype)).to(self.device)
+        i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+        desc = A.BatchDesc(
+            self.code, self.G, self.R,
+            self.graph_n.ctypes.data_as(i32p), self.graph_nreal.ctypes.data_as(i32p),
+            self.rowptr_off.ctypes.data_as(i64p), self.nnz_off.ctypes.data_as(i64p),
+            self.row_ptr.data_ptr(), self.col_idx.data_ptr(), 0 if self.values is None else self.values.data_ptr())
+        h = ctypes.c_void_p()
+        A.check(A.lib().ebtc_batch_create(ctypes.byref(desc), ctypes.byref(h)))
+        self.handle = h
+        self.score_off = np.concatenate([[0], np.cumsum(self.graph_n.astype(np.int64))])
+
+    @classmethod
+    def from_host(cls, hb, device: str = "cuda", with_values: bool | None = None) -> "Batch":
+        """From a host batch object (fields n, nreal, rowptr_off, nnz_off, row_ptr, col_idx, values, dtype)."""
+        dtype = "f64" if np.dtype(hb.dtype) == np.float64 else "f32"
+        vals = hb.values if (with_values is None or with_values) else None
+        return cls(hb.n, hb.nreal, hb.rowptr_off, hb.nnz_off, hb.row_ptr, hb.col_idx, vals, dtype, device)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            A.lib().ebtc_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def graph_slice(self, g: int) -> slice:
+        return slice(int(self.score_off[g]), int(self.score_off[g + 1]))
+
+    def run(self, diag: bool = True, ckpt: bool = False, **kw) -> Run:
+        return Run(self, make_opts(**kw), diag=diag, ckpt=ckpt)
+
+    def scores(self, diag: bool = True, ckpt: bool = False, **kw) -> ScoreResult:
+        """Fresh output buffers on every call (see Run for repeated calls)."""
+        return self.run(diag=diag, ckpt=ckpt, **kw).launch()
+
+    def topk(self, scores: torch.Tensor, k) -> tuple[torch.Tensor, torch.Tensor]:
+        kv = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.int32), (self.G,)))
+        ws = ctypes.c_size_t()
+        A.check(A.lib().ebtc_topk_ws_bytes(self.handle, ctypes.byref(ws)))
+        wst = torch.empty(max(1, ws.value), dtype=torch.uint8, device=self.device)
+        tot = int(kv.sum())
+        idx = torch.empty(max(1, tot), dtype=torch.int32, device=self.device)
+        val = torch.empty(max(1, tot), dtype=self.tdtype, device=self.device)
+        A.check(A.lib().ebtc_topk(self.handle, _vp(scores), kv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  _vp(idx), _vp(val), _vp(wst), ws.value, current_stream()))
+        return idx[:tot], val[:tot]
+
+    def validate(self) -> int:
+        ws = ctypes.c_size_t()
+        A.check(A.lib().ebtc_validate_ws_bytes(self.handle, ctypes.byref(ws)))
+        wst = torch.empty(max(1, ws.value), dtype=torch.uint8, device=self.device)
+        bad = ctypes.c_int64()
+        A.check(A.lib().ebtc_validate(self.handle, _vp(wst), ws.value, ctypes.byref(bad), current_stream()))
+        return int(bad.value)
+
+
+def spmv(row_ptr: torch.Tensor, col_idx: torch.Tensor, values: torch.Tensor | None, x: torch.Tensor,
+         lanes: int = 0, hub: int = 0) -> torch.Tensor:
+    """y = A x for one CSR matrix on the device (the Krylov step's product)."""
+    code = A.EBTC_F64 if x.dtype == torch.float64 else A.EBTC_F32
+    y = torch.empty_like(x)
+    A.check(A.lib().ebtc_spmv(code, x.numel(), _vp(row_ptr), _vp(col_idx), _vp(values), _vp(x), _vp(y), lanes, hub,
+                              current_stream()))
+    return y
+
+
+def tridiag_expv(alpha: torch.Tensor, beta: torch.Tensor, shift: bool = True) -> tuple[torch.Tensor, torch.Tensor]:
+    """For a [count, k] stack of FP64 tridiagonals: (y = exp(T - theta I) e1 [count, k], theta [count])."""
+    count, k = alpha.shape
+    y = torch.empty_like(alpha)
+    th = torch.empty(count, dtype=torch.float64, device=alpha.device)
+    A.check(A.lib().ebtc_tridiag_expv(count, k, _vp(alpha), _vp(beta), _vp(y), _vp(th), int(shift), current_stream()))
+    return y, th

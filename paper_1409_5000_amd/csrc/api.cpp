@@ -1,0 +1,623 @@
+// Host side of the EBTC C ABI: argument checks, workspace layout, launch sequences, hipGraph cache.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace ebtc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define EBTC_HIP(call)                                                                          \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess) return fail(EBTC_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  int m_slots = 0;
+  size_t off_tasks = 0, off_graphs = 0, off_blkmap = 0, off_state = 0, off_part = 0, off_npart = 0, off_V = 0,
+         off_W = 0, off_U = 0;
+  size_t total = 0;
+  int64_t total_blocks = 0;
+};
+
+struct ExecKey {
+  void* ws;
+  void* scores;
+  double* log_scale;
+  void* ckpt;
+  ebtc_diag* diag;
+  int m, m_max, reorth, shift, lanes, hub;
+  double tol;
+  bool operator==(const ExecKey& o) const {
+    return ws == o.ws && scores == o.scores && log_scale == o.log_scale && ckpt == o.ckpt && diag == o.diag &&
+           m == o.m && m_max == o.m_max && reorth == o.reorth && shift == o.shift && lanes == o.lanes &&
+           hub == o.hub && tol == o.tol;
+  }
+};
+
+struct ExecEntry {
+  ExecKey key;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+int elem_size(int dtype) { return dtype == EBTC_F64 ? 8 : 4; }
+
+}  // namespace
+
+struct ebtc_batch {
+  int dtype = EBTC_F32;
+  int32_t G = 0;
+  int64_t R = 0;
+  std::vector<int32_t> n, nreal, first;
+  std::vector<int64_t> rowptr_off, nnz_off, score_off;
+  const int32_t* row_ptr = nullptr;
+  const int32_t* col_idx = nullptr;
+  const void* values = nullptr;
+  int64_t total_scores = 0;  // sum_g n_g
+  int64_t total_rows = 0;    // sum_r n_r
+  int32_t n_max = 0;
+  double mean_degree = 0.0;
+  std::vector<Task> tasks;          // host staging of the device task table (kept alive for async copies)
+  std::vector<GraphInfo> graphs;
+  std::vector<int64_t> nnz_r;       // per-realization entry counts (validation upload)
+  std::vector<int32_t> topk_k;
+  std::vector<int64_t> topk_off;
+  std::vector<ExecEntry> execs;
+  hipStream_t capture_stream = nullptr;
+};
+
+namespace {
+
+int check_opts(const ebtc_opts* o) {
+  if (!o) return fail(EBTC_EINVAL, "opts is NULL");
+  if (o->m < 0 || o->m > EBTC_M_LIMIT) return fail(EBTC_EINVAL, "m must be in [0, 64] (0 = adaptive)");
+  if (o->m == 0 && (o->m_max < 1 || o->m_max > EBTC_M_LIMIT)) return fail(EBTC_EINVAL, "m_max must be in [1, 64]");
+  if (o->m == 0 && !(o->tol > 0.0)) return fail(EBTC_EINVAL, "adaptive mode needs tol > 0");
+  if (o->reorth != 1 && o->reorth != 2) return fail(EBTC_EINVAL, "reorth must be 1 or 2");
+  if (o->schedule < EBTC_SCHED_AUTO || o->schedule > EBTC_SCHED_BATCHED) return fail(EBTC_EINVAL, "unknown schedule");
+  if (o->lanes_per_row != 0 && o->lanes_per_row != 4 && o->lanes_per_row != 8 && o->lanes_per_row != 16 &&
+      o->lanes_per_row != 32)
+    return fail(EBTC_EINVAL, "lanes_per_row must be 0, 4, 8, 16 or 32");
+  if (o->hub_threshold < 0) return fail(EBTC_EINVAL, "hub_threshold must be >= 0");
+  return EBTC_OK;
+}
+
+int auto_lanes(double mean_degree) {
+  if (mean_degree < 6.0) return 4;
+  if (mean_degree < 20.0) return 8;
+  if (mean_degree < 48.0) return 16;
+  return 32;
+}
+
+Layout make_layout(const ebtc_batch* b, const ebtc_opts* o) {
+  Layout L;
+  L.m_slots = (o->m > 0 ? o->m : o->m_max) + 1;
+  const size_t es = elem_size(b->dtype);
+  int64_t blocks = 0;
+  int64_t rows = 0;
+  for (int32_t g = 0; g < b->G; ++g) {
+    const int64_t nb = (b->n[g] + kRowsPerBlock - 1) / kRowsPerBlock;
+    blocks += nb * b->nreal[g];
+    rows += (int64_t)b->n[g] * b->nreal[g];
+  }
+  L.total_blocks = blocks;
+  size_t off = 0;
+  L.off_tasks = off;
+  off = align_up(off + sizeof(Task) * b->R);
+  L.off_graphs = off;
+  off = align_up(off + sizeof(GraphInfo) * b->G);
+  L.off_blkmap = off;
+  off = align_up(off + sizeof(int32_t) * blocks);
+  L.off_state = off;
+  off = align_up(off + sizeof(RState) * b->R);
+  L.off_part = off;
+  off = align_up(off + sizeof(double) * kPartStride * blocks);
+  L.off_npart = off;
+  off = align_up(off + sizeof(double) * blocks);
+  L.off_V = off;
+  off = align_up(off + es * (size_t)L.m_slots * rows);
+  L.off_W = off;
+  off = align_up(off + es * rows);
+  L.off_U = off;
+  off = align_up(off + es * rows);
+  L.total = off;
+  return L;
+}
+
+void fill_tables(ebtc_batch* b, const Layout& L) {
+  b->tasks.resize(b->R);
+  int64_t vec = 0, row = 0, part = 0;
+  int32_t blk = 0;
+  int64_t r = 0;
+  for (int32_t g = 0; g < b->G; ++g) {
+    for (int32_t k = 0; k < b->nreal[g]; ++k, ++r) {
+      Task& t = b->tasks[r];
+      const int32_t n = b->n[g];
+      const int32_t nb = (n + kRowsPerBlock - 1) / kRowsPerBlock;
+      t.rowptr_off = b->rowptr_off[r];
+      t.nnz_off = b->nnz_off[r];
+      t.vec_off = vec;
+      t.w_off = row;
+      t.u_off = row;
+      t.part_off = part;
+      t.n = n;
+      t.graph = g;
+      t.nblk = nb;
+      t.blk_begin = blk;
+      vec += (int64_t)L.m_slots * n;
+      row += n;
+      part += (int64_t)nb * kPartStride;
+      blk += nb;
+    }
+  }
+}
+
+int upload_tables(ebtc_batch* b, char* ws, const Layout& L, hipStream_t s) {
+  fill_tables(b, L);
+  EBTC_HIP(hipMemcpyAsync(ws + L.off_tasks, b->tasks.data(), sizeof(Task) * b->R, hipMemcpyHostToDevice, s));
+  EBTC_HIP(hipMemcpyAsync(ws + L.off_graphs, b->graphs.data(), sizeof(GraphInfo) * b->G, hipMemcpyHostToDevice, s));
+  return EBTC_OK;
+}
+
+LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, int hub) {
+  LzArgs a{};
+  a.row_ptr = b->row_ptr;
+  a.col_idx = b->col_idx;
+  a.values = b->values;
+  a.tasks = (const Task*)(ws + L.off_tasks);
+  a.blkmap = (const int32_t*)(ws + L.off_blkmap);
+  a.single_task = 0;
+  a.hub_threshold = hub;
+  a.state = (RState*)(ws + L.off_state);
+  a.V = ws + L.off_V;
+  a.W = ws + L.off_W;
+  a.U = ws + L.off_U;
+  a.part = (double*)(ws + L.off_part);
+  a.npart = (double*)(ws + L.off_npart);
+  a.m_fixed = o->m;
+  a.m_max = o->m > 0 ? o->m : o->m_max;
+  a.eps = b->dtype == EBTC_F64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+  return a;
+}
+
+// Optional per-launch event recording (ebtc_profile_phases).
+struct Prof {
+  struct Rec {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  hipStream_t s;
+  int before(int phase) {
+    Rec r{phase, nullptr, nullptr};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return EBTC_EHIP;
+    recs.push_back(r);
+    return hipEventRecord(r.a, s) == hipSuccess ? EBTC_OK : EBTC_EHIP;
+  }
+  int after() { return hipEventRecord(recs.back().b, s) == hipSuccess ? EBTC_OK : EBTC_EHIP; }
+  ~Prof() {
+    for (auto& r : recs) {
+      if (r.a) (void)hipEventDestroy(r.a);
+      if (r.b) (void)hipEventDestroy(r.b);
+    }
+  }
+};
+
+#define EBTC_LAUNCH(call)                                                                              \
+  do {                                                                                                 \
+    hipError_t e_ = (call);                                                                            \
+    if (e_ != hipSuccess) return fail(EBTC_EHIP, std::string("launch ") + #call + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define EBTC_PHASE(prof, phase, call)                                                   \
+  do {                                                                                  \
+    if (prof && prof->before(phase)) return fail(EBTC_EHIP, "event record failed");    \
+    EBTC_LAUNCH(call);                                                                  \
+    if (prof && prof->after()) return fail(EBTC_EHIP, "event record failed");          \
+  } while (0)
+
+// Lanczos steps for the launches described by (a, nblocks); a.blkmap / a.single_task select the scope.
+int run_steps(const ebtc_batch* b, const ebtc_opts* o, const LzArgs& a, int64_t nblocks, int64_t first,
+              int64_t count, int lanes, hipStream_t s, Prof* prof) {
+  const bool has_val = b->values != nullptr;
+  const int steps = o->m > 0 ? o->m : o->m_max;
+  EBTC_PHASE(prof, EBTC_PHASE_START, launch_start(b->dtype, a, nblocks, s));
+  for (int j = 0; j < steps; ++j) {
+    EBTC_PHASE(prof, EBTC_PHASE_SPMV_DOTS, launch_spmv_dots(b->dtype, has_val, lanes, j, a, nblocks, s));
+    if (o->reorth == 2) {
+      EBTC_PHASE(prof, EBTC_PHASE_UPDATE, launch_update(b->dtype, j, true, false, false, a, nblocks, s));
+      EBTC_PHASE(prof, EBTC_PHASE_DOTS_AGAIN, launch_dots_again(b->dtype, j, a, nblocks, s));
+      EBTC_PHASE(prof, EBTC_PHASE_UPDATE, launch_update(b->dtype, j, false, true, true, a, nblocks, s));
+    } else {
+      EBTC_PHASE(prof, EBTC_PHASE_UPDATE, launch_update(b->dtype, j, true, true, false, a, nblocks, s));
+    }
+    if (o->m == 0)
+      EBTC_PHASE(prof, EBTC_PHASE_TRIDIAG,
+                 launch_tridiag_state(a, first, count, 1, j, steps, o->shift, o->tol, nullptr, nullptr, s));
+  }
+  return EBTC_OK;
+}
+
+int enqueue_batched(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, void* scores, double* log_scale,
+                    void* ckpt, ebtc_diag* diag, int lanes, int hub, hipStream_t s, Prof* prof = nullptr) {
+  LzArgs a = make_args(b, o, ws, L, hub);
+  a.diag = diag;
+  EBTC_LAUNCH(launch_blkmap(a.tasks, b->R, (int32_t*)(ws + L.off_blkmap), s));
+  int rc = run_steps(b, o, a, L.total_blocks, 0, b->R, lanes, s, prof);
+  if (rc) return rc;
+  const int steps = o->m > 0 ? o->m : o->m_max;
+  EBTC_PHASE(prof, EBTC_PHASE_TRIDIAG,
+             launch_tridiag_state(a, 0, b->R, 0, 0, steps, o->shift, o->tol, diag, (double*)ckpt, s));
+  EBTC_PHASE(prof, EBTC_PHASE_COMBINE, launch_combine(b->dtype, a, L.total_blocks, s));
+  const int32_t maxblk = (b->n_max + kRowsPerBlock - 1) / kRowsPerBlock;
+  EBTC_PHASE(prof, EBTC_PHASE_SUM, launch_sum(b->dtype, (const GraphInfo*)(ws + L.off_graphs), b->G, maxblk, a.tasks,
+                                              a.state, a.U, scores, log_scale, s));
+  return EBTC_OK;
+}
+
+int enqueue_plain(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, void* scores, double* log_scale,
+                  void* ckpt, ebtc_diag* diag, int lanes, int hub, hipStream_t s) {
+  LzArgs a = make_args(b, o, ws, L, hub);
+  a.blkmap = nullptr;
+  a.diag = diag;
+  for (int64_t r = 0; r < b->R; ++r) {
+    a.single_task = (int32_t)r;
+    const int64_t nb = b->tasks[r].nblk;
+    int rc = run_steps(b, o, a, nb, r, 1, lanes, s, nullptr);
+    if (rc) return rc;
+    EBTC_LAUNCH(launch_tridiag_state(a, r, 1, 0, 0, o->m > 0 ? o->m : o->m_max, o->shift, o->tol, diag,
+                                     (double*)ckpt, s));
+    EBTC_LAUNCH(launch_combine(b->dtype, a, nb, s));
+  }
+  const int32_t maxblk = (b->n_max + kRowsPerBlock - 1) / kRowsPerBlock;
+  EBTC_LAUNCH(launch_sum(b->dtype, (const GraphInfo*)(ws + L.off_graphs), b->G, maxblk, a.tasks, a.state, a.U, scores,
+                         log_scale, s));
+  return EBTC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ebtc_version(int* major, int* minor) {
+  if (!major || !minor) return fail(EBTC_EINVAL, "NULL output pointer");
+  *major = EBTC_VERSION_MAJOR;
+  *minor = EBTC_VERSION_MINOR;
+  return EBTC_OK;
+}
+
+const char* ebtc_status_str(int status) {
+  switch (status) {
+    case EBTC_OK: return "ok";
+    case EBTC_EINVAL: return "invalid argument";
+    case EBTC_EBADGRAPH: return "bad graph batch";
+    case EBTC_EWORKSPACE: return "workspace too small";
+    case EBTC_EHIP: return "HIP runtime error";
+    case EBTC_ENOTSUPPORTED: return "not supported";
+    default: return "unknown status";
+  }
+}
+
+const char* ebtc_last_error(void) { return g_err.c_str(); }
+
+void ebtc_default_opts(ebtc_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->m = 30;
+  o->m_max = 60;
+  o->tol = 1e-6;
+  o->reorth = 1;
+  o->schedule = EBTC_SCHED_AUTO;
+  o->use_hipgraph = 1;
+  o->shift = 1;
+  o->lanes_per_row = 0;
+  o->hub_threshold = 0;
+}
+
+int ebtc_batch_create(const ebtc_batch_desc* d, ebtc_batch** out) {
+  g_err.clear();
+  if (!d || !out) return fail(EBTC_EINVAL, "NULL descriptor or output");
+  if (d->dtype != EBTC_F32 && d->dtype != EBTC_F64) return fail(EBTC_EINVAL, "dtype must be EBTC_F32 or EBTC_F64");
+  if (d->num_graphs < 1) return fail(EBTC_EINVAL, "num_graphs must be >= 1");
+  if (d->num_realizations < 1 || d->num_realizations >= (int64_t)1 << 31)
+    return fail(EBTC_EINVAL, "num_realizations must be in [1, 2^31)");
+  if (!d->graph_n || !d->graph_nreal || !d->rowptr_off || !d->nnz_off)
+    return fail(EBTC_EINVAL, "NULL host array in the descriptor");
+  if (!d->row_ptr || !d->col_idx) return fail(EBTC_EINVAL, "NULL device row_ptr or col_idx");
+  ebtc_batch* b = new ebtc_batch();
+  b->dtype = d->dtype;
+  b->G = d->num_graphs;
+  b->R = d->num_realizations;
+  b->n.assign(d->graph_n, d->graph_n + b->G);
+  b->nreal.assign(d->graph_nreal, d->graph_nreal + b->G);
+  b->rowptr_off.assign(d->rowptr_off, d->rowptr_off + b->R);
+  b->nnz_off.assign(d->nnz_off, d->nnz_off + b->R + 1);
+  b->row_ptr = d->row_ptr;
+  b->col_idx = d->col_idx;
+  b->values = d->values;
+  int64_t sum_real = 0, blocks = 0;
+  b->first.resize(b->G);
+  b->score_off.resize(b->G + 1);
+  b->score_off[0] = 0;
+  for (int32_t g = 0; g < b->G; ++g) {
+    if (b->n[g] < 1) {
+      delete b;
+      return fail(EBTC_EINVAL, "graph " + std::to_string(g) + ": n must be >= 1");
+    }
+    if (b->nreal[g] < 1) {
+      delete b;
+      return fail(EBTC_EINVAL, "graph " + std::to_string(g) + ": realizations must be >= 1");
+    }
+    b->first[g] = (int32_t)sum_real;
+    sum_real += b->nreal[g];
+    b->score_off[g + 1] = b->score_off[g] + b->n[g];
+    b->n_max = std::max(b->n_max, b->n[g]);
+    b->total_rows += (int64_t)b->n[g] * b->nreal[g];
+    blocks += (int64_t)((b->n[g] + kRowsPerBlock - 1) / kRowsPerBlock) * b->nreal[g];
+  }
+  if (sum_real != b->R) {
+    delete b;
+    return fail(EBTC_EBADGRAPH, "num_realizations differs from the sum of graph_nreal");
+  }
+  if (blocks >= (int64_t)1 << 31) {
+    delete b;
+    return fail(EBTC_ENOTSUPPORTED, "too many row blocks for one launch");
+  }
+  if (b->nnz_off[0] != 0) {
+    delete b;
+    return fail(EBTC_EBADGRAPH, "nnz_off[0] must be 0");
+  }
+  b->nnz_r.resize(b->R);
+  int64_t r = 0;
+  for (int32_t g = 0; g < b->G; ++g) {
+    for (int32_t k = 0; k < b->nreal[g]; ++k, ++r) {
+      const int64_t z = b->nnz_off[r + 1] - b->nnz_off[r];
+      if (z < 0 || z >= (int64_t)1 << 31) {
+        delete b;
+        return fail(EBTC_EBADGRAPH, "realization " + std::to_string(r) + ": entry count out of range");
+      }
+      if (b->rowptr_off[r] < 0) {
+        delete b;
+        return fail(EBTC_EBADGRAPH, "realization " + std::to_string(r) + ": negative rowptr_off");
+      }
+      b->nnz_r[r] = z;
+    }
+  }
+  b->total_scores = b->score_off[b->G];
+  b->mean_degree = b->total_rows > 0 ? (double)b->nnz_off[b->R] / (double)b->total_rows : 0.0;
+  b->graphs.resize(b->G);
+  for (int32_t g = 0; g < b->G; ++g) {
+    b->graphs[g].score_off = b->score_off[g];
+    b->graphs[g].n = b->n[g];
+    b->graphs[g].first = b->first[g];
+    b->graphs[g].count = b->nreal[g];
+    b->graphs[g].pad = 0;
+  }
+  *out = b;
+  return EBTC_OK;
+}
+
+void ebtc_batch_destroy(ebtc_batch* b) {
+  if (!b) return;
+  for (auto& e : b->execs) {
+    (void)hipGraphExecDestroy(e.exec);
+    (void)hipGraphDestroy(e.graph);
+  }
+  if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+  delete b;
+}
+
+int ebtc_plan(ebtc_batch* b, const ebtc_opts* o, size_t* ws_bytes, size_t* ckpt_bytes) {
+  g_err.clear();
+  if (!b || !ws_bytes) return fail(EBTC_EINVAL, "NULL batch or output");
+  int rc = check_opts(o);
+  if (rc) return rc;
+  *ws_bytes = make_layout(b, o).total;
+  if (ckpt_bytes) *ckpt_bytes = sizeof(double) * kCkptDoubles * (size_t)b->R;
+  return EBTC_OK;
+}
+
+int ebtc_scores(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, void* scores_out, double* log_scale_out,
+                void* ckpt_out, ebtc_diag* diag_out, void* stream) {
+  g_err.clear();
+  if (!b) return fail(EBTC_EINVAL, "NULL batch");
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (!ws || !scores_out || !log_scale_out) return fail(EBTC_EINVAL, "NULL workspace, scores or log_scale output");
+  const Layout L = make_layout(b, o);
+  if (ws_bytes < L.total)
+    return fail(EBTC_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(L.total));
+  if (((uintptr_t)ws & 255) != 0) return fail(EBTC_EINVAL, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  const int lanes = o->lanes_per_row ? o->lanes_per_row : auto_lanes(b->mean_degree);
+  const int hub = o->hub_threshold ? o->hub_threshold : 16 * lanes;
+  char* w = (char*)ws;
+  rc = upload_tables(b, w, L, s);
+  if (rc) return rc;
+  if (o->schedule == EBTC_SCHED_PLAIN)
+    return enqueue_plain(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, lanes, hub, s);
+  if (!o->use_hipgraph)
+    return enqueue_batched(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, lanes, hub, s);
+  const ExecKey key{ws, scores_out, log_scale_out, ckpt_out, diag_out, o->m, o->m_max, o->reorth, o->shift, lanes, hub,
+                    o->tol};
+  for (auto& e : b->execs) {
+    if (e.key == key) {
+      EBTC_HIP(hipGraphLaunch(e.exec, s));
+      return EBTC_OK;
+    }
+  }
+  if (!b->capture_stream) EBTC_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
+  EBTC_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
+  rc = enqueue_batched(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, lanes, hub, b->capture_stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(b->capture_stream, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (ec != hipSuccess) return fail(EBTC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(EBTC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+  }
+  if (b->execs.size() >= 4) {
+    (void)hipGraphExecDestroy(b->execs.front().exec);
+    (void)hipGraphDestroy(b->execs.front().graph);
+    b->execs.erase(b->execs.begin());
+  }
+  b->execs.push_back({key, graph, exec});
+  EBTC_HIP(hipGraphLaunch(exec, s));
+  return EBTC_OK;
+}
+
+int ebtc_profile_phases(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, void* scores_out,
+                        double* log_scale_out, double* phase_ms, int64_t* phase_launches, void* stream) {
+  g_err.clear();
+  if (!b || !phase_ms || !phase_launches) return fail(EBTC_EINVAL, "NULL batch or phase output");
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (!ws || !scores_out || !log_scale_out) return fail(EBTC_EINVAL, "NULL workspace, scores or log_scale output");
+  const Layout L = make_layout(b, o);
+  if (ws_bytes < L.total) return fail(EBTC_EWORKSPACE, "workspace too small");
+  if (((uintptr_t)ws & 255) != 0) return fail(EBTC_EINVAL, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  const int lanes = o->lanes_per_row ? o->lanes_per_row : auto_lanes(b->mean_degree);
+  const int hub = o->hub_threshold ? o->hub_threshold : 16 * lanes;
+  char* w = (char*)ws;
+  rc = upload_tables(b, w, L, s);
+  if (rc) return rc;
+  Prof prof;
+  prof.s = s;
+  rc = enqueue_batched(b, o, w, L, scores_out, log_scale_out, nullptr, nullptr, lanes, hub, s, &prof);
+  if (rc) return rc;
+  EBTC_HIP(hipStreamSynchronize(s));
+  for (int p = 0; p < EBTC_PHASE_COUNT; ++p) {
+    phase_ms[p] = 0.0;
+    phase_launches[p] = 0;
+  }
+  for (auto& r : prof.recs) {
+    float ms = 0.f;
+    EBTC_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    phase_ms[r.phase] += ms;
+    phase_launches[r.phase] += 1;
+  }
+  return EBTC_OK;
+}
+
+int ebtc_topk_ws_bytes(ebtc_batch* b, size_t* ws_bytes) {
+  g_err.clear();
+  if (!b || !ws_bytes) return fail(EBTC_EINVAL, "NULL batch or output");
+  *ws_bytes = align_up(sizeof(GraphInfo) * b->G) + align_up(sizeof(int32_t) * b->G) + align_up(sizeof(int64_t) * b->G);
+  return EBTC_OK;
+}
+
+int ebtc_topk(ebtc_batch* b, const void* scores, const int32_t* k_per_graph, int32_t* idx_out, void* val_out,
+              void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!b || !scores || !k_per_graph || !idx_out || !ws) return fail(EBTC_EINVAL, "NULL argument");
+  size_t need = 0;
+  ebtc_topk_ws_bytes(b, &need);
+  if (ws_bytes < need) return fail(EBTC_EWORKSPACE, "top-k workspace too small");
+  if (((uintptr_t)ws & 255) != 0) return fail(EBTC_EINVAL, "workspace must be 256-byte aligned");
+  b->topk_k.assign(k_per_graph, k_per_graph + b->G);
+  b->topk_off.resize(b->G);
+  int64_t off = 0;
+  for (int32_t g = 0; g < b->G; ++g) {
+    const int32_t k = b->topk_k[g];
+    if (k < 0 || k > b->n[g] || k > EBTC_TOPK_LIMIT)
+      return fail(k > EBTC_TOPK_LIMIT ? EBTC_ENOTSUPPORTED : EBTC_EINVAL,
+                  "graph " + std::to_string(g) + ": K must be in [0, min(n, 4096)]");
+    b->topk_off[g] = off;
+    off += k;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  const size_t o1 = align_up(sizeof(GraphInfo) * b->G), o2 = o1 + align_up(sizeof(int32_t) * b->G);
+  EBTC_HIP(hipMemcpyAsync(w, b->graphs.data(), sizeof(GraphInfo) * b->G, hipMemcpyHostToDevice, s));
+  EBTC_HIP(hipMemcpyAsync(w + o1, b->topk_k.data(), sizeof(int32_t) * b->G, hipMemcpyHostToDevice, s));
+  EBTC_HIP(hipMemcpyAsync(w + o2, b->topk_off.data(), sizeof(int64_t) * b->G, hipMemcpyHostToDevice, s));
+  EBTC_LAUNCH(launch_topk(b->dtype, (const GraphInfo*)w, b->G, (const int32_t*)(w + o1), (const int64_t*)(w + o2),
+                          scores, idx_out, val_out, s));
+  return EBTC_OK;
+}
+
+int ebtc_spmv(int32_t dtype, int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const void* values,
+              const void* x, void* y, int32_t lanes_per_row, int32_t hub_threshold, void* stream) {
+  g_err.clear();
+  if (dtype != EBTC_F32 && dtype != EBTC_F64) return fail(EBTC_EINVAL, "dtype must be EBTC_F32 or EBTC_F64");
+  if (n < 1 || !row_ptr || !col_idx || !x || !y) return fail(EBTC_EINVAL, "n < 1 or NULL pointer");
+  if (x == y) return fail(EBTC_EINVAL, "x and y must be distinct");
+  const int lanes = lanes_per_row ? lanes_per_row : 8;
+  if (lanes != 4 && lanes != 8 && lanes != 16 && lanes != 32)
+    return fail(EBTC_EINVAL, "lanes_per_row must be 0, 4, 8, 16 or 32");
+  if (hub_threshold < 0) return fail(EBTC_EINVAL, "hub_threshold must be >= 0");
+  const int hub = hub_threshold ? hub_threshold : 16 * lanes;
+  EBTC_LAUNCH(launch_spmv(dtype, values != nullptr, lanes, hub, n, row_ptr, col_idx, values, x, y, (hipStream_t)stream));
+  return EBTC_OK;
+}
+
+int ebtc_tridiag_expv(int32_t count, int32_t k, const double* alpha, const double* beta, double* y_out,
+                      double* theta_out, int32_t shift, void* stream) {
+  g_err.clear();
+  if (count < 0) return fail(EBTC_EINVAL, "count must be >= 0");
+  if (k < 1 || k > EBTC_M_LIMIT) return fail(EBTC_EINVAL, "k must be in [1, 64]");
+  if (count == 0) return EBTC_OK;
+  if (!alpha || !beta || !y_out || !theta_out) return fail(EBTC_EINVAL, "NULL pointer");
+  EBTC_LAUNCH(launch_tridiag_arrays(count, k, alpha, beta, y_out, theta_out, shift, (hipStream_t)stream));
+  return EBTC_OK;
+}
+
+int ebtc_validate_ws_bytes(ebtc_batch* b, size_t* ws_bytes) {
+  g_err.clear();
+  if (!b || !ws_bytes) return fail(EBTC_EINVAL, "NULL batch or output");
+  *ws_bytes = align_up(sizeof(Task) * b->R) + align_up(sizeof(int64_t) * b->R) + align_up(sizeof(int32_t) * b->R);
+  return EBTC_OK;
+}
+
+int ebtc_validate(ebtc_batch* b, void* ws, size_t ws_bytes, int64_t* first_bad, void* stream) {
+  g_err.clear();
+  if (!b || !ws || !first_bad) return fail(EBTC_EINVAL, "NULL argument");
+  size_t need = 0;
+  ebtc_validate_ws_bytes(b, &need);
+  if (ws_bytes < need) return fail(EBTC_EWORKSPACE, "validate workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  Layout L;
+  L.m_slots = 1;
+  fill_tables(b, L);
+  char* w = (char*)ws;
+  const size_t o1 = align_up(sizeof(Task) * b->R), o2 = o1 + align_up(sizeof(int64_t) * b->R);
+  std::vector<int32_t> bad(b->R, 0);
+  EBTC_HIP(hipMemcpyAsync(w, b->tasks.data(), sizeof(Task) * b->R, hipMemcpyHostToDevice, s));
+  EBTC_HIP(hipMemcpyAsync(w + o1, b->nnz_r.data(), sizeof(int64_t) * b->R, hipMemcpyHostToDevice, s));
+  EBTC_HIP(hipMemcpyAsync(w + o2, bad.data(), sizeof(int32_t) * b->R, hipMemcpyHostToDevice, s));
+  EBTC_LAUNCH(launch_validate(b->row_ptr, b->col_idx, (const Task*)w, (const int64_t*)(w + o1), b->R, b->n_max,
+                              (int32_t*)(w + o2), s));
+  EBTC_HIP(hipMemcpyAsync(bad.data(), w + o2, sizeof(int32_t) * b->R, hipMemcpyDeviceToHost, s));
+  EBTC_HIP(hipStreamSynchronize(s));
+  *first_bad = -1;
+  for (int64_t r = 0; r < b->R; ++r)
+    if (bad[r]) {
+      *first_bad = r;
+      break;
+    }
+  return EBTC_OK;
+}
+
+}  // extern "C"

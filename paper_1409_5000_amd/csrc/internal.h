@@ -1,0 +1,118 @@
+// Internal types and launchers of the EBTC library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/ebtc.h"
+
+namespace ebtc {
+
+constexpr int kBlock = 256;          // threads of a streaming workgroup (4 waves of 64)
+constexpr int kRowsPerBlock = 1024;  // CSR rows owned by one workgroup in the Lanczos kernels
+constexpr int kRowsPerThread = kRowsPerBlock / kBlock;
+constexpr int kMLimit = EBTC_M_LIMIT;
+constexpr int kPartStride = 64;      // doubles per workgroup in the dot-partial arena
+constexpr int kMaxChunks = 32;       // chunks of the canonical partial-sum order
+
+// One realization of the batch as the kernels see it (device table, 64 bytes).
+struct Task {
+  int64_t rowptr_off;  // start of the realization's local row_ptr block
+  int64_t nnz_off;     // start of its entries in col_idx / values
+  int64_t vec_off;     // element offset of its basis block (m_slots x n, vector-major) in the V arena
+  int64_t w_off;       // element offset of its product vector w [n] in the W arena
+  int64_t u_off;       // element offset of its combined vector u [n] in the U arena
+  int64_t part_off;    // double offset of its per-workgroup dot partials (nblk x kPartStride); the
+                       // norm partials (nblk) sit at the same offset / kPartStride in the norm arena
+  int32_t n;
+  int32_t graph;
+  int32_t nblk;        // row blocks of kRowsPerBlock rows
+  int32_t blk_begin;   // first flattened workgroup id of this realization in a batched launch
+};
+static_assert(sizeof(Task) == 64, "Task layout");
+
+struct GraphInfo {
+  int64_t score_off;   // offset of the graph's block in the score output
+  int32_t n;
+  int32_t first;       // first realization index
+  int32_t count;       // realizations of this graph
+  int32_t pad;
+};
+static_assert(sizeof(GraphInfo) == 24, "GraphInfo layout");
+
+// Per-realization Lanczos state (FP64 scalars), one per realization in the workspace.
+// Basis vectors are stored unnormalised: v_i = s[i] * Vraw_i (the normalisation of step j is folded
+// into the scale instead of a separate pass over the vector).
+struct RState {
+  double alpha[kMLimit];
+  double beta[kMLimit];
+  double s[kMLimit + 1];
+  double c[kMLimit + 1];   // Gram-Schmidt coefficients on the raw basis for the current step
+  double y[kMLimit];       // exp(T - theta I) e1
+  double theta;
+  double est;
+  double scale;            // max(|alpha_0..j|, beta_0..j-1): the breakdown reference
+  double beta0;            // ||start vector|| = sqrt(n)
+  int32_t m_used;
+  int32_t flags;
+  int32_t done;            // 1 once the realization stopped (breakdown, estimate met, cap)
+  int32_t pad0;
+};
+
+// Arguments shared by the Lanczos streaming kernels.
+struct LzArgs {
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const void* values;      // nullptr = all ones
+  const Task* tasks;
+  const int32_t* blkmap;   // flattened workgroup -> task; nullptr = single-task launch
+  int32_t single_task;
+  int32_t hub_threshold;
+  RState* state;
+  void* V;
+  void* W;
+  void* U;
+  double* part;            // dot partials
+  double* npart;           // norm partials
+  int32_t m_fixed;         // fixed m, or 0 (adaptive)
+  int32_t m_max;
+  double eps;              // unit roundoff of the working precision
+  ebtc_diag* diag;         // optional diagnostics output (combine flags non-finite results there)
+};
+
+// ---- launchers (k_lanczos.hip)
+hipError_t launch_blkmap(const Task* tasks, int64_t R, int32_t* blkmap, hipStream_t s);
+hipError_t launch_start(int dtype, const LzArgs& a, int64_t nblocks, hipStream_t s);
+hipError_t launch_spmv_dots(int dtype, bool has_val, int lanes, int j, const LzArgs& a, int64_t nblocks,
+                            hipStream_t s);
+hipError_t launch_dots_again(int dtype, int j, const LzArgs& a, int64_t nblocks, hipStream_t s);
+hipError_t launch_update(int dtype, int j, bool from_w, bool final_pass, bool second_pass, const LzArgs& a,
+                         int64_t nblocks, hipStream_t s);
+hipError_t launch_combine(int dtype, const LzArgs& a, int64_t nblocks, hipStream_t s);
+hipError_t launch_sum(int dtype, const GraphInfo* graphs, int32_t G, int32_t max_blocks, const Task* tasks,
+                      const RState* state, const void* U, void* scores, double* log_scale, hipStream_t s);
+hipError_t launch_spmv(int dtype, bool has_val, int lanes, int hub, int32_t n, const int32_t* row_ptr,
+                       const int32_t* col_idx, const void* values, const void* x, void* y, hipStream_t s);
+
+// ---- launchers (k_tridiag.hip)
+// mode 0: final (closes step m_steps-1 when still open; writes y/theta/est, diag, checkpoint);
+// mode 1: adaptive check after step j (closes step j, stops on breakdown, estimate < tol or m_max).
+hipError_t launch_tridiag_state(const LzArgs& a, int64_t first, int64_t count, int mode, int j, int m_steps,
+                                int shift, double tol, ebtc_diag* diag, double* ckpt, hipStream_t s);
+hipError_t launch_tridiag_arrays(int32_t count, int32_t k, const double* alpha, const double* beta, double* y,
+                                 double* theta, int32_t shift, hipStream_t s);
+
+// ---- launchers (k_topk.hip)
+hipError_t launch_topk(int dtype, const GraphInfo* graphs, int32_t G, const int32_t* kvec, const int64_t* koff,
+                       const void* scores, int32_t* idx_out, void* val_out, hipStream_t s);
+
+// ---- launchers (k_topk.hip, structural check)
+hipError_t launch_validate(const int32_t* row_ptr, const int32_t* col_idx, const Task* tasks, const int64_t* nnz,
+                           int64_t R, int32_t max_n, int32_t* bad, hipStream_t s);
+
+// checkpoint layout per realization (doubles): alpha[kMLimit], beta[kMLimit], theta, beta0, m_used, flags
+constexpr int kCkptDoubles = 2 * kMLimit + 4;
+
+}  // namespace ebtc

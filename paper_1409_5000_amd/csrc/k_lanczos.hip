@@ -1,0 +1,530 @@
+// Lanczos streaming kernels for gfx950 (MI355X, wave64).
+//
+// One Lanczos step j of exp(A) 1 (Krylov approximation, "The total communicability", eq. (4)):
+//   phase A  closes step j-1 (beta_{j-1} from the norm partials, breakdown test, scale 1/beta_{j-1}
+//            of the unnormalised basis vector), then w = A v_j (CSR SpMV) and the per-workgroup
+//            partial dot products <v_i, w>, i <= j;
+//   phase B  reduces the dot partials, v~_{j+1} = w - sum_i h_i v_i (classical Gram-Schmidt against
+//            the whole basis) and the per-workgroup partial squared norm.
+// Workgroups never wait for each other inside a kernel and use no device-scope fences or atomics:
+// partial sums go to memory and the next kernel (after the launch boundary) reduces them. Every
+// reader uses the same canonical summation order, so all of them see bit-identical totals.
+// Every workgroup owns kRowsPerBlock consecutive rows of one realization. Launches either cover
+// one realization (plain loop) or every realization of the batch at once (batched), in which case
+// a table maps each workgroup to its realization.
+//
+// Memory layout: basis vectors are vector-major (V[i][0..n)), so every phase streams them with
+// fully coalesced loads; the SpMV gathers from the one contiguous vector v_j.
+#include "device_common.h"
+
+namespace ebtc {
+namespace {
+
+constexpr int kWaves = kBlock / 64;
+
+// Workgroups are dispatched round-robin over the eight XCDs (workgroup id mod 8). Map them so that
+// each XCD walks a contiguous range of logical workgroups: the workgroups of one realization then
+// share one XCD's L2, where the gathered vector v_j stays resident.
+__device__ inline int logical_block() {
+  const int G = gridDim.x, b = blockIdx.x;
+  const int x = b & 7, q = b >> 3;
+  const int base = G >> 3, rem = G & 7;
+  return x * base + (x < rem ? x : rem) + q;
+}
+
+struct Ref {
+  int task;
+  int blk;
+};
+
+__device__ inline Ref resolve(const LzArgs& a) {
+  const int lb = logical_block();
+  if (a.blkmap == nullptr) return {a.single_task, lb};
+  const int t = a.blkmap[lb];
+  return {t, lb - a.tasks[t].blk_begin};
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum of one double over the workgroup; every thread gets the result.
+__device__ inline double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) t += red[i];
+  return t;
+}
+
+// Butterfly reduce-scatter of P values per lane over the 64 lanes of a wave: after the call v[0]
+// of lane l holds the wave-wide sum of value index (P == 64 ? l : l >> 1). Costs P - 1 (+1)
+// shuffles instead of 6 P for P separate reductions.
+template <int P, int M>
+struct ReduceScatter {
+  __device__ static inline void run(double* v, int lane) {
+    if constexpr (P > 1) {
+      constexpr int h = P / 2;
+      const bool up = (lane & M) != 0;
+#pragma unroll
+      for (int k = 0; k < h; ++k) {
+        const double keep = up ? v[k + h] : v[k];
+        const double send = up ? v[k] : v[k + h];
+        v[k] = keep + __shfl_xor(send, M, 64);
+      }
+    } else {
+      v[0] += __shfl_xor(v[0], M, 64);
+    }
+    if constexpr (M > 1) ReduceScatter<(P > 1 ? P / 2 : 1), M / 2>::run(v, lane);
+  }
+};
+
+// w[r - r0] = scale * (A x)[r] for rows r0 <= r < r1 into LDS. Rows with more than `hub` entries are
+// reduced by the whole workgroup (tree over 256 partial sums) after the others; the rest by groups
+// of L lanes (each lane sums its strided share, then an L-lane shuffle tree).
+template <typename T, bool HAS_VAL, int L>
+__device__ inline void spmv_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                 const T* __restrict__ va, const T* __restrict__ x, int r0, int r1, int hub,
+                                 double scale, T* w_lds, int* hub_list, int* hub_count, double* red) {
+  const int tid = threadIdx.x;
+  if (tid == 0) *hub_count = 0;
+  __syncthreads();
+  const int grp = tid / L, lane = tid % L;
+  for (int r = r0 + grp; r < r1; r += kBlock / L) {
+    const int b = rp[r], e = rp[r + 1];
+    if (e - b > hub) {
+      if (lane == 0) hub_list[atomicAdd(hub_count, 1)] = r;
+      continue;
+    }
+    T acc = 0;
+    for (int k = b + lane; k < e; k += L) {
+      const T xv = x[ci[k]];
+      if constexpr (HAS_VAL) acc += va[k] * xv; else acc += xv;
+    }
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) w_lds[r - r0] = (T)((double)acc * scale);
+  }
+  __syncthreads();
+  const int nh = *hub_count;
+  for (int h = 0; h < nh; ++h) {
+    const int r = hub_list[h];
+    const int b = rp[r], e = rp[r + 1];
+    T acc = 0;
+    for (int k = b + tid; k < e; k += kBlock) {
+      const T xv = x[ci[k]];
+      if constexpr (HAS_VAL) acc += va[k] * xv; else acc += xv;
+    }
+    const double tot = block_sum((double)acc, red);
+    if (tid == 0) w_lds[r - r0] = (T)(tot * scale);
+  }
+  __syncthreads();
+}
+
+// Partial dots p_i = sum_rows Vraw_i[r] * w[r] (i <= j) of this workgroup's rows, reduced over the
+// workgroup and stored to part_blk[i]. Basis loads are issued eight vectors at a time (clamped to
+// slot j, whose contribution is masked) so that many loads are in flight per thread.
+template <typename T, int P>
+__device__ inline void block_dots(const T* __restrict__ Vr, int n, int j, int r0, int r1, const T* wsrc_lds,
+                                  const T* wsrc_glob, T* wstore, double* part_blk, double (*red)[P]) {
+  const int tid = threadIdx.x;
+  T p[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) p[i] = 0;
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int r = r0 + q * kBlock + tid;
+    if (r < r1) {
+      const T wv = wsrc_lds ? wsrc_lds[r - r0] : wsrc_glob[r];
+      if (wstore) wstore[r] = wv;
+#pragma unroll
+      for (int i0 = 0; i0 < P; i0 += 8) {
+        if (i0 <= j) {
+          T v[8];
+#pragma unroll
+          for (int c = 0; c < 8; ++c) v[c] = Vr[(size_t)min(i0 + c, j) * n + r];
+#pragma unroll
+          for (int c = 0; c < 8; ++c) p[i0 + c] += (i0 + c <= j) ? v[c] * wv : (T)0;
+        }
+      }
+    }
+  }
+  double pd[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) pd[i] = (double)p[i];
+  const int lane = tid & 63, wave = tid >> 6;
+  ReduceScatter<P, 32>::run(pd, lane);
+  if (P == 64 || (lane & 1) == 0) red[wave][P == 64 ? lane : (lane >> 1)] = pd[0];
+  __syncthreads();
+  if (tid < P && tid <= j) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s += red[w][tid];
+    part_blk[tid] = s;
+  }
+}
+
+// Phase A of step j. Opens by closing step j-1 from its norm partials (every workgroup computes the
+// same beta_{j-1} in the same order; workgroup 0 records it), then w = s_j A Vraw_j and the dots.
+template <typename T, bool HAS_VAL, int L, int P>
+__global__ __launch_bounds__(kBlock) void k_spmv_dots(LzArgs a, int j) {
+  __shared__ T w_lds[kRowsPerBlock];
+  __shared__ int hub_list[kRowsPerBlock];
+  __shared__ int hub_count;
+  __shared__ double red[kWaves][P];
+  __shared__ double red1[kMaxChunks];
+  const Ref ref = resolve(a);
+  const Task tk = a.tasks[ref.task];
+  RState* st = a.state + ref.task;
+  if (st->done) return;
+  double sj;
+  if (j == 0) {
+    sj = st->s[0];
+  } else {
+    const StepClose c = close_step(st, a.npart + tk.part_off / kPartStride, tk.nblk, j - 1, a.eps, red1);
+    if (ref.blk == 0 && threadIdx.x == 0) {
+      st->beta[j - 1] = c.beta;
+      if (c.flags) {
+        st->flags |= c.flags;
+        st->done = 1;
+        st->m_used = j;
+      } else {
+        st->s[j] = 1.0 / c.beta;
+      }
+    }
+    if (c.flags) return;
+    sj = 1.0 / c.beta;
+  }
+  const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
+  T* Vr = (T*)a.V + tk.vec_off;
+  const T* va = HAS_VAL ? (const T*)a.values + tk.nnz_off : nullptr;
+  spmv_rows<T, HAS_VAL, L>(a.row_ptr + tk.rowptr_off, a.col_idx + tk.nnz_off, va, Vr + (size_t)j * n, r0, r1,
+                           a.hub_threshold, sj, w_lds, hub_list, &hub_count, red1);
+  block_dots<T, P>(Vr, n, j, r0, r1, w_lds, nullptr, (T*)a.W + tk.w_off,
+                   a.part + tk.part_off + (size_t)ref.blk * kPartStride, red);
+}
+
+// Second Gram-Schmidt pass: dots of the once-orthogonalised vector (stored in slot j+1).
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_dots_again(LzArgs a, int j) {
+  __shared__ double red[kWaves][P];
+  const Ref ref = resolve(a);
+  const Task tk = a.tasks[ref.task];
+  const RState* st = a.state + ref.task;
+  if (st->done) return;
+  const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
+  const T* Vr = (const T*)a.V + tk.vec_off;
+  block_dots<T, P>(Vr, n, j, r0, r1, nullptr, Vr + (size_t)(j + 1) * n, nullptr,
+                   a.part + tk.part_off + (size_t)ref.blk * kPartStride, red);
+}
+
+// Phase B of step j: every workgroup reduces the dot partials of all workgroups of its realization
+// in the canonical order (identical coefficients everywhere, no inter-workgroup synchronisation),
+// then v~_{j+1} = src - sum_i c_i Vraw_i (FP64 accumulation, rounded once), plus the partial
+// squared norm on the final pass.
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, int final_pass, int second) {
+  __shared__ double cs[P];
+  __shared__ double csum[P][kMaxChunks];
+  __shared__ double red[kWaves];
+  const Ref ref = resolve(a);
+  const Task tk = a.tasks[ref.task];
+  RState* st = a.state + ref.task;
+  if (st->done) return;
+  const int tid = threadIdx.x;
+  const double* part = a.part + tk.part_off;
+  const int nblk = tk.nblk, chunk = part_chunk(nblk), nch = (nblk + chunk - 1) / chunk;
+  for (int item = tid; item < nch * (j + 1); item += kBlock) {
+    const int c = item / (j + 1), i = item - c * (j + 1);
+    double s = 0.0;
+    const int b1 = min(nblk, (c + 1) * chunk);
+    for (int b = c * chunk; b < b1; ++b) s += part[(size_t)b * kPartStride + i];
+    csum[i][c] = s;
+  }
+  __syncthreads();
+  if (tid < P) {
+    double coef = 0.0;
+    if (tid <= j) {
+      double t = 0.0;
+      for (int c = 0; c < nch; ++c) t += csum[tid][c];
+      const double si = st->s[tid];
+      const double h = si * t;
+      coef = h * si;
+      if (tid == j && ref.blk == 0) st->alpha[j] = second ? st->alpha[j] + h : h;
+    }
+    cs[tid] = coef;
+  }
+  __syncthreads();
+  const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
+  T* Vr = (T*)a.V + tk.vec_off;
+  const T* src = from_w ? (const T*)a.W + tk.w_off : Vr + (size_t)(j + 1) * n;
+  T* dst = Vr + (size_t)(j + 1) * n;
+  double nrm = 0.0;
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int r = r0 + q * kBlock + tid;
+    if (r < r1) {
+      double acc = (double)src[r];
+#pragma unroll
+      for (int i0 = 0; i0 < P; i0 += 8) {
+        if (i0 <= j) {
+          T v[8];
+#pragma unroll
+          for (int c = 0; c < 8; ++c) v[c] = Vr[(size_t)min(i0 + c, j) * n + r];
+#pragma unroll
+          for (int c = 0; c < 8; ++c) acc -= cs[i0 + c] * (double)v[c];
+        }
+      }
+      const T out = (T)acc;
+      dst[r] = out;
+      nrm += (double)out * (double)out;
+    }
+  }
+  if (!final_pass) return;
+  nrm = block_sum(nrm, red);
+  if (tid == 0) a.npart[tk.part_off / kPartStride + ref.blk] = nrm;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_start(LzArgs a) {
+  const Ref ref = resolve(a);
+  const Task tk = a.tasks[ref.task];
+  const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
+  T* v0 = (T*)a.V + tk.vec_off;
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) v0[r] = (T)1;  // v_0 = s_0 * 1, s_0 = 1/sqrt(n)
+  if (ref.blk == 0 && threadIdx.x == 0) {
+    RState* st = a.state + ref.task;
+    st->beta0 = sqrt((double)n);
+    st->s[0] = 1.0 / st->beta0;
+    st->theta = 0.0;
+    st->est = 0.0;
+    st->scale = 0.0;
+    st->m_used = 0;
+    st->flags = 0;
+    st->done = 0;
+  }
+}
+
+// u = beta0 * sum_i y_i v_i = sum_i (beta0 y_i s_i) Vraw_i, so exp(A) 1 ~ e^{theta*} u.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_combine(LzArgs a) {
+  __shared__ double d[kMLimit];
+  const Ref ref = resolve(a);
+  const Task tk = a.tasks[ref.task];
+  const RState* st = a.state + ref.task;
+  const int k = st->m_used;  // >= 1 once the steps ran
+  const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
+  if ((int)threadIdx.x < k) d[threadIdx.x] = st->beta0 * st->y[threadIdx.x] * st->s[threadIdx.x];
+  __syncthreads();
+  const T* Vr = (const T*)a.V + tk.vec_off;
+  T* u = (T*)a.U + tk.u_off;
+  bool finite = true;
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int r = r0 + q * kBlock + (int)threadIdx.x;
+    if (r < r1) {
+      double acc = 0.0;
+      for (int i = 0; i < k; ++i) acc += d[i] * (double)Vr[(size_t)i * n + r];
+      const T out = (T)acc;
+      u[r] = out;
+      finite = finite && isfinite((double)out);
+    }
+  }
+  // e.g. exp(A) 1 beyond the working range when the shift is switched off
+  if (__syncthreads_or(!finite) && threadIdx.x == 0) {
+    atomicOr(&a.state[ref.task].flags, EBTC_FLAG_NONFINITE);
+    if (a.diag) atomicOr(&a.diag[ref.task].flags, EBTC_FLAG_NONFINITE);
+  }
+}
+
+// eq. (5) in scaled form: S~_g = sum_k e^{theta_k - Sigma_g} u_k, k ascending, FP64 weights and
+// accumulation; Sigma_g = max_k theta_k.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sum(const GraphInfo* graphs, const Task* tasks, const RState* state,
+                                                 const T* U, T* scores, double* log_scale) {
+  __shared__ double wk[kBlock];
+  __shared__ int64_t uo[kBlock];
+  __shared__ double sig;
+  const GraphInfo gi = graphs[blockIdx.y];
+  const int r0 = blockIdx.x * kRowsPerBlock;
+  if (r0 >= gi.n) return;
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    double m = -INFINITY;
+    for (int k = tid; k < gi.count; k += 64) m = fmax(m, state[gi.first + k].theta);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (tid == 0) sig = m;
+  }
+  __syncthreads();
+  double acc[kRowsPerThread];
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) acc[q] = 0.0;
+  for (int kb = 0; kb < gi.count; kb += kBlock) {
+    const int cnt = min(kBlock, gi.count - kb);
+    if (tid < cnt) {
+      wk[tid] = exp(state[gi.first + kb + tid].theta - sig);
+      uo[tid] = tasks[gi.first + kb + tid].u_off;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < cnt; ++kk) {
+      const double wgt = wk[kk];
+      const T* u = U + uo[kk];
+#pragma unroll
+      for (int q = 0; q < kRowsPerThread; ++q) {
+        const int r = r0 + q * kBlock + tid;
+        if (r < gi.n) acc[q] += wgt * (double)u[r];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int r = r0 + q * kBlock + tid;
+    if (r < gi.n) scores[gi.score_off + r] = (T)acc[q];
+  }
+  if (blockIdx.x == 0 && tid == 0) log_scale[blockIdx.y] = sig;
+}
+
+__global__ void k_blkmap(const Task* tasks, int32_t* blkmap) {
+  const Task tk = tasks[blockIdx.x];
+  for (int b = threadIdx.x; b < tk.nblk; b += blockDim.x) blkmap[tk.blk_begin + b] = (int32_t)blockIdx.x;
+}
+
+template <typename T, bool HAS_VAL, int L>
+__global__ __launch_bounds__(kBlock) void k_spmv(int32_t n, const int32_t* rp, const int32_t* ci, const T* va,
+                                                  const T* x, T* y, int hub) {
+  __shared__ T w_lds[kRowsPerBlock];
+  __shared__ int hub_list[kRowsPerBlock];
+  __shared__ int hub_count;
+  __shared__ double red1[kWaves];
+  const int r0 = blockIdx.x * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
+  spmv_rows<T, HAS_VAL, L>(rp, ci, va, x, r0, r1, hub, 1.0, w_lds, hub_list, &hub_count, red1);
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) y[r] = w_lds[r - r0];
+}
+
+template <typename T, bool HAS_VAL, int L, int P>
+hipError_t spmv_dots_t(int j, const LzArgs& a, int64_t nb, hipStream_t s) {
+  hipLaunchKernelGGL((k_spmv_dots<T, HAS_VAL, L, P>), dim3((unsigned)nb), dim3(kBlock), 0, s, a, j);
+  return hipGetLastError();
+}
+
+template <typename T, bool HAS_VAL, int P>
+hipError_t spmv_dots_l(int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
+  switch (lanes) {
+    case 4: return spmv_dots_t<T, HAS_VAL, 4, P>(j, a, nb, s);
+    case 8: return spmv_dots_t<T, HAS_VAL, 8, P>(j, a, nb, s);
+    case 16: return spmv_dots_t<T, HAS_VAL, 16, P>(j, a, nb, s);
+    case 32: return spmv_dots_t<T, HAS_VAL, 32, P>(j, a, nb, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, bool HAS_VAL>
+hipError_t spmv_dots_p(int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
+  return (j + 1 <= 32) ? spmv_dots_l<T, HAS_VAL, 32>(lanes, j, a, nb, s)
+                       : spmv_dots_l<T, HAS_VAL, 64>(lanes, j, a, nb, s);
+}
+
+template <typename T, bool HAS_VAL, int L>
+hipError_t spmv_t(int32_t n, const int32_t* rp, const int32_t* ci, const void* va, const void* x, void* y,
+                  int hub, hipStream_t s) {
+  const int nb = (n + kRowsPerBlock - 1) / kRowsPerBlock;
+  hipLaunchKernelGGL((k_spmv<T, HAS_VAL, L>), dim3(nb), dim3(kBlock), 0, s, n, rp, ci, (const T*)va,
+                     (const T*)x, (T*)y, hub);
+  return hipGetLastError();
+}
+
+template <typename T, bool HAS_VAL>
+hipError_t spmv_l(int lanes, int32_t n, const int32_t* rp, const int32_t* ci, const void* va, const void* x,
+                  void* y, int hub, hipStream_t s) {
+  switch (lanes) {
+    case 4: return spmv_t<T, HAS_VAL, 4>(n, rp, ci, va, x, y, hub, s);
+    case 8: return spmv_t<T, HAS_VAL, 8>(n, rp, ci, va, x, y, hub, s);
+    case 16: return spmv_t<T, HAS_VAL, 16>(n, rp, ci, va, x, y, hub, s);
+    case 32: return spmv_t<T, HAS_VAL, 32>(n, rp, ci, va, x, y, hub, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_blkmap(const Task* tasks, int64_t R, int32_t* blkmap, hipStream_t s) {
+  hipLaunchKernelGGL(k_blkmap, dim3((unsigned)R), dim3(256), 0, s, tasks, blkmap);
+  return hipGetLastError();
+}
+
+hipError_t launch_start(int dtype, const LzArgs& a, int64_t nb, hipStream_t s) {
+  if (dtype == EBTC_F64)
+    hipLaunchKernelGGL(k_start<double>, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_start<float>, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_dots(int dtype, bool has_val, int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
+  if (dtype == EBTC_F64)
+    return has_val ? spmv_dots_p<double, true>(lanes, j, a, nb, s) : spmv_dots_p<double, false>(lanes, j, a, nb, s);
+  return has_val ? spmv_dots_p<float, true>(lanes, j, a, nb, s) : spmv_dots_p<float, false>(lanes, j, a, nb, s);
+}
+
+hipError_t launch_dots_again(int dtype, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
+  const dim3 g((unsigned)nb), b(kBlock);
+  if (dtype == EBTC_F64) {
+    if (j + 1 <= 32) hipLaunchKernelGGL((k_dots_again<double, 32>), g, b, 0, s, a, j);
+    else hipLaunchKernelGGL((k_dots_again<double, 64>), g, b, 0, s, a, j);
+  } else {
+    if (j + 1 <= 32) hipLaunchKernelGGL((k_dots_again<float, 32>), g, b, 0, s, a, j);
+    else hipLaunchKernelGGL((k_dots_again<float, 64>), g, b, 0, s, a, j);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_update(int dtype, int j, bool from_w, bool final_pass, bool second_pass, const LzArgs& a,
+                         int64_t nb, hipStream_t s) {
+  const dim3 g((unsigned)nb), b(kBlock);
+  const int fw = from_w ? 1 : 0, fp = final_pass ? 1 : 0, sp = second_pass ? 1 : 0;
+  if (dtype == EBTC_F64) {
+    if (j + 1 <= 32) hipLaunchKernelGGL((k_update<double, 32>), g, b, 0, s, a, j, fw, fp, sp);
+    else hipLaunchKernelGGL((k_update<double, 64>), g, b, 0, s, a, j, fw, fp, sp);
+  } else {
+    if (j + 1 <= 32) hipLaunchKernelGGL((k_update<float, 32>), g, b, 0, s, a, j, fw, fp, sp);
+    else hipLaunchKernelGGL((k_update<float, 64>), g, b, 0, s, a, j, fw, fp, sp);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(int dtype, const LzArgs& a, int64_t nb, hipStream_t s) {
+  if (dtype == EBTC_F64)
+    hipLaunchKernelGGL(k_combine<double>, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_combine<float>, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum(int dtype, const GraphInfo* graphs, int32_t G, int32_t max_blocks, const Task* tasks,
+                      const RState* state, const void* U, void* scores, double* log_scale, hipStream_t s) {
+  const dim3 g((unsigned)max_blocks, (unsigned)G), b(kBlock);
+  if (dtype == EBTC_F64)
+    hipLaunchKernelGGL(k_sum<double>, g, b, 0, s, graphs, tasks, state, (const double*)U, (double*)scores, log_scale);
+  else
+    hipLaunchKernelGGL(k_sum<float>, g, b, 0, s, graphs, tasks, state, (const float*)U, (float*)scores, log_scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv(int dtype, bool has_val, int lanes, int hub, int32_t n, const int32_t* rp,
+                       const int32_t* ci, const void* va, const void* x, void* y, hipStream_t s) {
+  if (dtype == EBTC_F64)
+    return has_val ? spmv_l<double, true>(lanes, n, rp, ci, va, x, y, hub, s)
+                   : spmv_l<double, false>(lanes, n, rp, ci, va, x, y, hub, s);
+  return has_val ? spmv_l<float, true>(lanes, n, rp, ci, va, x, y, hub, s)
+                 : spmv_l<float, false>(lanes, n, rp, ci, va, x, y, hub, s);
+}
+
+}  // namespace ebtc

@@ -1,0 +1,223 @@
+// Top-K selection per graph: the K largest summed scores are the candidate target nodes
+// ("The total communicability": the largest 20 EBTC values; the paper sorts with Introsort,
+// O(n log n); a radix select finds the same set in O(n)).
+//
+// One 1024-thread workgroup per graph:
+//   1. radix select on order-preserving integer keys of the scores, 8 bits per pass from the top,
+//      finds the key t of the K-th largest score and how many entries equal to t are needed;
+//   2. one pass collects every entry above t, plus the lowest-id entries equal to t (an ordered
+//      block scan in id order when there are more ties than needed);
+//   3. a bitonic sort in LDS orders the K candidates by descending score, then ascending id.
+#include "internal.h"
+
+namespace ebtc {
+namespace {
+
+constexpr int kTopkThreads = 1024;
+
+__device__ inline uint32_t key_of(float v) {
+  const uint32_t b = __float_as_uint(v);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ inline uint64_t key_of(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+
+template <typename T, typename K>
+__global__ __launch_bounds__(kTopkThreads) void k_topk(const GraphInfo* graphs, const int32_t* kvec,
+                                                       const int64_t* koff, const T* scores, int32_t* idx_out,
+                                                       T* val_out) {
+  __shared__ uint32_t hist[256];
+  __shared__ K s_prefix, s_mask;
+  __shared__ int s_remaining, s_eq_total, s_ngt, s_eq_seen;
+  __shared__ int wave_cnt[kTopkThreads / 64];
+  __shared__ K ckey[EBTC_TOPK_LIMIT];
+  __shared__ int cid[EBTC_TOPK_LIMIT];
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const GraphInfo gi = graphs[g];
+  const int K_ = kvec[g];
+  if (K_ <= 0) return;
+  const int n = gi.n;
+  const T* s = scores + gi.score_off;
+  constexpr int BITS = (int)sizeof(K) * 8;
+  if (tid == 0) {
+    s_prefix = 0;
+    s_mask = 0;
+    s_remaining = K_;
+  }
+  __syncthreads();
+  for (int shift = BITS - 8; shift >= 0; shift -= 8) {
+    if (tid < 256) hist[tid] = 0;
+    __syncthreads();
+    const K prefix = s_prefix, mask = s_mask;
+    for (int i = tid; i < n; i += kTopkThreads) {
+      const K k = key_of(s[i]);
+      if ((k & mask) == prefix) atomicAdd(&hist[(int)((k >> shift) & 255)], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int cum = 0, b = 255;
+      for (; b > 0; --b) {
+        if (cum + (int)hist[b] >= s_remaining) break;
+        cum += (int)hist[b];
+      }
+      s_remaining -= cum;
+      s_prefix = prefix | ((K)b << shift);
+      s_mask = mask | ((K)255 << shift);
+      if (shift == 0) s_eq_total = (int)hist[b];
+      s_ngt = 0;
+      s_eq_seen = 0;
+    }
+    __syncthreads();
+  }
+  const K t = s_prefix;
+  const int need = s_remaining;         // entries equal to t to take
+  const int gt_total = K_ - need;       // entries strictly above t
+  const bool all_ties = (s_eq_total == need);
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int base = 0; base < n; base += kTopkThreads) {
+    const int i = base + tid;
+    const K k = (i < n) ? key_of(s[i]) : (K)0;
+    const bool gt = (i < n) && k > t;
+    const bool eq = (i < n) && k == t;
+    if (gt) {
+      const int slot = atomicAdd(&s_ngt, 1);
+      ckey[slot] = k;
+      cid[slot] = i;
+    }
+    if (all_ties) {
+      if (eq) {
+        const int slot = gt_total + atomicAdd(&s_eq_seen, 1);
+        ckey[slot] = k;
+        cid[slot] = i;
+      }
+    } else {
+      const int seen = s_eq_seen;  // uniform: updated only between the barriers below
+      if (seen < need) {
+        const unsigned long long bal = __ballot(eq);
+        if (lane == 0) wave_cnt[wave] = __popcll(bal);
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int w = 0; w < kTopkThreads / 64; ++w) {
+          before += (w < wave) ? wave_cnt[w] : 0;
+          total += wave_cnt[w];
+        }
+        const int rank = seen + before + __popcll(bal & ((1ull << lane) - 1ull));
+        if (eq && rank < need) {
+          ckey[gt_total + rank] = k;
+          cid[gt_total + rank] = i;
+        }
+        __syncthreads();
+        if (tid == 0) s_eq_seen = seen + total;
+        __syncthreads();
+      }
+    }
+  }
+  __syncthreads();
+  int P2 = 1;
+  while (P2 < K_) P2 <<= 1;
+  for (int i = K_ + tid; i < P2; i += kTopkThreads) {
+    ckey[i] = (K)0;
+    cid[i] = 0x7fffffff;
+  }
+  __syncthreads();
+  // bitonic sort, "before" = larger key, then smaller id
+  for (int size = 2; size <= P2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < P2; i += kTopkThreads) {
+        const int p = i ^ stride;
+        if (p > i) {
+          const bool desc = (i & size) == 0;
+          const K ka = ckey[i], kb = ckey[p];
+          const int ia = cid[i], ib = cid[p];
+          const bool a_first = (ka > kb) || (ka == kb && ia < ib);
+          if (a_first != desc) {
+            ckey[i] = kb;
+            ckey[p] = ka;
+            cid[i] = ib;
+            cid[p] = ia;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int64_t o = koff[g];
+  for (int r = tid; r < K_; r += kTopkThreads) {
+    idx_out[o + r] = cid[r];
+    if (val_out) val_out[o + r] = s[cid[r]];
+  }
+}
+
+// Phase 1: row_ptr of each realization starts at 0, is non-decreasing and ends at its entry count.
+__global__ void k_validate_rowptr(const int32_t* row_ptr, const Task* tasks, const int64_t* nnz, int32_t* bad) {
+  const Task tk = tasks[blockIdx.x];
+  const int32_t* rp = row_ptr + tk.rowptr_off;
+  const int64_t z = nnz[blockIdx.x];
+  int b = 0;
+  for (int i = threadIdx.x; i < tk.n; i += blockDim.x)
+    if (rp[i] > rp[i + 1] || rp[i] < 0) b = 1;
+  if (threadIdx.x == 0 && (rp[0] != 0 || (int64_t)rp[tk.n] != z)) b = 1;
+  if (__syncthreads_or(b) && threadIdx.x == 0) bad[blockIdx.x] = 1;
+}
+
+// Phase 2 (only where phase 1 passed): columns in range, strictly increasing, no self-loop, and the
+// transposed entry exists (binary search in the column's row).
+__global__ void k_validate_entries(const int32_t* row_ptr, const int32_t* col_idx, const Task* tasks, int32_t* bad) {
+  const int r = blockIdx.y;
+  if (bad[r]) return;
+  const Task tk = tasks[r];
+  const int32_t* rp = row_ptr + tk.rowptr_off;
+  const int32_t* ci = col_idx + tk.nnz_off;
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  int b = 0;
+  if (row < tk.n) {
+    const int s = rp[row], e = rp[row + 1];
+    for (int k = s; k < e && !b; ++k) {
+      const int c = ci[k];
+      if (c < 0 || c >= tk.n || c == row || (k > s && ci[k - 1] >= c)) {
+        b = 1;
+        break;
+      }
+      int lo = rp[c], hi = rp[c + 1];
+      bool found = false;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const int v = ci[mid];
+        if (v == row) {
+          found = true;
+          break;
+        }
+        if (v < row) lo = mid + 1; else hi = mid;
+      }
+      if (!found) b = 1;
+    }
+  }
+  if (b) bad[r] = 1;
+}
+
+}  // namespace
+
+hipError_t launch_topk(int dtype, const GraphInfo* graphs, int32_t G, const int32_t* kvec, const int64_t* koff,
+                       const void* scores, int32_t* idx_out, void* val_out, hipStream_t s) {
+  if (dtype == EBTC_F64)
+    hipLaunchKernelGGL((k_topk<double, uint64_t>), dim3((unsigned)G), dim3(kTopkThreads), 0, s, graphs, kvec, koff,
+                       (const double*)scores, idx_out, (double*)val_out);
+  else
+    hipLaunchKernelGGL((k_topk<float, uint32_t>), dim3((unsigned)G), dim3(kTopkThreads), 0, s, graphs, kvec, koff,
+                       (const float*)scores, idx_out, (float*)val_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const int32_t* row_ptr, const int32_t* col_idx, const Task* tasks, const int64_t* nnz,
+                           int64_t R, int32_t max_n, int32_t* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate_rowptr, dim3((unsigned)R), dim3(256), 0, s, row_ptr, tasks, nnz, bad);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_validate_entries, dim3((unsigned)((max_n + 255) / 256), (unsigned)R), dim3(256), 0, s, row_ptr,
+                     col_idx, tasks, bad);
+  return hipGetLastError();
+}
+
+}  // namespace ebtc

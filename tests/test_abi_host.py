@@ -1,0 +1,212 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every function the header
+declares, validates descriptors and options with the documented status codes, reports workspace
+sizes that match the documented layout, and keeps ebtc_last_error in step. No compute call is made.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1409_5000_amd import _abi as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE_DEV = 0x7F0000000000  # never dereferenced by host-only calls
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "ebtc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ebtc_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = A.lib()
+    names = header_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), f"{name} declared in ebtc.h but not exported"
+    assert sorted(A.EXPORTED) == names
+
+
+def test_version_and_status_strings():
+    a, b = ctypes.c_int(), ctypes.c_int()
+    assert A.lib().ebtc_version(ctypes.byref(a), ctypes.byref(b)) == 0 and (a.value, b.value) == (0, 1)
+    assert A.lib().ebtc_version(None, None) == A.EBTC_EINVAL
+    for s in range(6):
+        assert A.lib().ebtc_status_str(s)
+    assert A.lib().ebtc_status_str(99) == b"unknown status"
+
+
+def make_desc(G=1, nreal=(3,), n=(10,), nnz=(20, 20, 20), dtype=A.EBTC_F32, keep=None):
+    keep = [] if keep is None else keep
+    gn = np.array(n, np.int32)
+    gr = np.array(nreal, np.int32)
+    R = int(gr.sum())
+    ro = np.zeros(R, np.int64)
+    acc = 0
+    r = 0
+    for g in range(G):
+        for _ in range(gr[g]):
+            ro[r] = acc
+            acc += gn[g] + 1
+            r += 1
+    no = np.concatenate([[0], np.cumsum(np.array(nnz, np.int64))]).astype(np.int64)
+    keep += [gn, gr, ro, no]
+    i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+    d = A.BatchDesc(dtype, G, R, gn.ctypes.data_as(i32p), gr.ctypes.data_as(i32p), ro.ctypes.data_as(i64p),
+                    no.ctypes.data_as(i64p), FAKE_DEV, FAKE_DEV + 4096, None)
+    return d, keep
+
+
+def create(d):
+    h = ctypes.c_void_p()
+    rc = A.lib().ebtc_batch_create(ctypes.byref(d), ctypes.byref(h))
+    return rc, h
+
+
+def test_batch_create_ok_and_destroy_null_safe():
+    d, keep = make_desc()
+    rc, h = create(d)
+    assert rc == 0 and h.value
+    A.lib().ebtc_batch_destroy(h)
+    A.lib().ebtc_batch_destroy(None)
+
+
+@pytest.mark.parametrize("mutate,code,text", [
+    (lambda d: setattr(d, "dtype", 7), A.EBTC_EINVAL, "dtype"),
+    (lambda d: setattr(d, "num_graphs", 0), A.EBTC_EINVAL, "num_graphs"),
+    (lambda d: setattr(d, "num_realizations", 0), A.EBTC_EINVAL, "num_realizations"),
+    (lambda d: setattr(d, "num_realizations", 4), A.EBTC_EBADGRAPH, "sum of graph_nreal"),
+    (lambda d: setattr(d, "row_ptr", None), A.EBTC_EINVAL, "row_ptr"),
+    (lambda d: setattr(d, "graph_n", None), A.EBTC_EINVAL, "host array"),
+])
+def test_batch_create_rejects(mutate, code, text):
+    d, keep = make_desc()
+    mutate(d)
+    rc, h = create(d)
+    assert rc == code and not h.value
+    assert text in A.lib().ebtc_last_error().decode()
+
+
+def test_batch_create_rejects_bad_counts():
+    d, keep = make_desc(n=(0,))
+    assert create(d)[0] == A.EBTC_EINVAL
+    d, keep = make_desc(nnz=(20, -5, 20))
+    assert create(d)[0] == A.EBTC_EBADGRAPH
+    d, keep = make_desc(nnz=(20, 2 ** 31, 20))
+    assert create(d)[0] == A.EBTC_EBADGRAPH
+
+
+def test_int64_offsets_beyond_2_31_accepted():
+    # three realizations of 2^30 entries each: batch offsets pass 2^31 while each realization stays < 2^31
+    d, keep = make_desc(n=(1000,), nnz=(2 ** 30, 2 ** 30, 2 ** 30))
+    rc, h = create(d)
+    assert rc == 0
+    A.lib().ebtc_batch_destroy(h)
+
+
+def plan(h, **kw):
+    o = A.default_opts(**kw)
+    ws, ck = ctypes.c_size_t(), ctypes.c_size_t()
+    rc = A.lib().ebtc_plan(h, ctypes.byref(o), ctypes.byref(ws), ctypes.byref(ck))
+    return rc, ws.value, ck.value
+
+
+def align(x):
+    return (x + 255) // 256 * 256
+
+
+def expected_ws(G, nreal, n, m_slots, es, rstate_bytes):
+    R = sum(nreal)
+    blocks = sum(((ng + 1023) // 1024) * nr for ng, nr in zip(n, nreal))
+    rows = sum(ng * nr for ng, nr in zip(n, nreal))
+    off = align(64 * R)
+    off = align(off + 24 * G)
+    off = align(off + 4 * blocks)
+    off = align(off + rstate_bytes * R)
+    off = align(off + 8 * 64 * blocks)
+    off = align(off + es * m_slots * rows)
+    off = align(off + es * rows)
+    off = align(off + es * rows)
+    return off
+
+
+RSTATE_BYTES = 8 * (64 + 64 + 65 + 65 + 64 + 4) + 4 * 8
+
+
+@pytest.mark.parametrize("dtype,es", [(A.EBTC_F32, 4), (A.EBTC_F64, 8)])
+def test_plan_workspace_arithmetic(dtype, es):
+    d, keep = make_desc(G=2, nreal=(2, 3), n=(3000, 70), nnz=(10, 10, 10, 10, 10), dtype=dtype)
+    rc, h = create(d)
+    assert rc == 0
+    rc, ws, ck = plan(h, m=30)
+    assert rc == 0
+    assert ws == expected_ws(2, (2, 3), (3000, 70), 31, es, RSTATE_BYTES)
+    assert ck == 5 * A.CKPT_DOUBLES * 8
+    rc, ws2, _ = plan(h, m=0, m_max=60, tol=1e-6)
+    assert rc == 0 and ws2 == expected_ws(2, (2, 3), (3000, 70), 61, es, RSTATE_BYTES)
+    A.lib().ebtc_batch_destroy(h)
+
+
+@pytest.mark.parametrize("kw,text", [
+    (dict(m=65), "m must be"), (dict(m=-1), "m must be"), (dict(m=0, m_max=0), "m_max"),
+    (dict(m=0, tol=0.0), "tol"), (dict(reorth=3), "reorth"), (dict(schedule=9), "schedule"),
+    (dict(lanes_per_row=5), "lanes_per_row"), (dict(hub_threshold=-1), "hub_threshold"),
+])
+def test_plan_rejects_bad_opts(kw, text):
+    d, keep = make_desc()
+    rc, h = create(d)
+    rc, _, _ = plan(h, **kw)
+    assert rc == A.EBTC_EINVAL and text in A.lib().ebtc_last_error().decode()
+    A.lib().ebtc_batch_destroy(h)
+
+
+def test_scores_rejects_before_enqueue():
+    d, keep = make_desc()
+    rc, h = create(d)
+    o = A.default_opts(m=10)
+    # NULL outputs and a too-small workspace fail on the host before any HIP call
+    rc = A.lib().ebtc_scores(h, ctypes.byref(o), FAKE_DEV, 1 << 40, None, None, None, None, None)
+    assert rc == A.EBTC_EINVAL
+    rc = A.lib().ebtc_scores(h, ctypes.byref(o), FAKE_DEV, 16, FAKE_DEV, FAKE_DEV, None, None, None)
+    assert rc == A.EBTC_EWORKSPACE and "need" in A.lib().ebtc_last_error().decode()
+    rc = A.lib().ebtc_scores(h, ctypes.byref(o), FAKE_DEV + 8, 1 << 40, FAKE_DEV, FAKE_DEV, None, None, None)
+    assert rc == A.EBTC_EINVAL and "aligned" in A.lib().ebtc_last_error().decode()
+    A.lib().ebtc_batch_destroy(h)
+
+
+def test_topk_rejects_bad_k():
+    d, keep = make_desc(n=(10,))
+    rc, h = create(d)
+    ws = ctypes.c_size_t()
+    assert A.lib().ebtc_topk_ws_bytes(h, ctypes.byref(ws)) == 0 and ws.value > 0
+    for k, code in ((11, A.EBTC_EINVAL), (-1, A.EBTC_EINVAL)):
+        kv = (ctypes.c_int32 * 1)(k)
+        rc = A.lib().ebtc_topk(h, FAKE_DEV, kv, FAKE_DEV, None, FAKE_DEV, ws.value, None)
+        assert rc == code
+    rc = A.lib().ebtc_topk(h, FAKE_DEV, (ctypes.c_int32 * 1)(3), FAKE_DEV, None, FAKE_DEV, 1, None)
+    assert rc == A.EBTC_EWORKSPACE
+    A.lib().ebtc_batch_destroy(h)
+
+
+def test_component_entry_points_validate():
+    L = A.lib()
+    assert L.ebtc_spmv(5, 10, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV + 64, 0, 0, None) == A.EBTC_EINVAL
+    assert L.ebtc_spmv(0, 0, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV + 64, 0, 0, None) == A.EBTC_EINVAL
+    assert L.ebtc_spmv(0, 10, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV, 0, 0, None) == A.EBTC_EINVAL
+    assert L.ebtc_spmv(0, 10, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV + 64, 6, 0, None) == A.EBTC_EINVAL
+    assert L.ebtc_tridiag_expv(1, 65, FAKE_DEV, FAKE_DEV, FAKE_DEV, FAKE_DEV, 1, None) == A.EBTC_EINVAL
+    assert L.ebtc_tridiag_expv(-1, 5, FAKE_DEV, FAKE_DEV, FAKE_DEV, FAKE_DEV, 1, None) == A.EBTC_EINVAL
+    assert L.ebtc_tridiag_expv(0, 5, None, None, None, None, 1, None) == A.EBTC_OK
+
+
+def test_last_error_cleared_on_success():
+    d, keep = make_desc()
+    d.dtype = 9
+    assert create(d)[0] != 0 and A.lib().ebtc_last_error()
+    d2, keep2 = make_desc()
+    rc, h = create(d2)
+    assert rc == 0 and A.lib().ebtc_last_error() == b""
+    A.lib().ebtc_batch_destroy(h)

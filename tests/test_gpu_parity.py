@@ -1,0 +1,366 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, element by element.
+
+Bars: FP64 mode 1e-12 (normwise and on the oracle's top-2K), FP32 mode 1e-5, identical top-K sets
+(tie band rule in tests/parity.py), identical m_used for fixed m. Integer work (SpMV on 0/1
+patterns in FP64, top-K indices) is compared exactly.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from fixtures import configs as C, graphs as G
+from oracle import dense as odense, lanczos as olanczos, scores as oscores, tridiag as otridiag
+from tests import graphs_small as gs
+from tests.parity import TOL, errors, scaled, topk_consistent
+
+pytestmark = pytest.mark.gpu
+
+
+def api():
+    from paper_1409_5000_amd import api as _api
+    return _api
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+class DenseBatch:
+    """Host batch from dense adjacency matrices: graphs = list (per graph) of lists of matrices."""
+
+    def __init__(self, graphs, dtype="f64", weighted=False):
+        parts = []
+        for reals in graphs:
+            csrs = []
+            for M in reals:
+                S = sp.csr_matrix(M)
+                S.sort_indices()
+                csrs.append((S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data))
+            parts.append(csrs)
+        self.dtype = np.dtype(np.float64 if dtype == "f64" else np.float32)
+        self.n = np.array([reals[0].shape[0] for reals in graphs], np.int32)
+        self.nreal = np.array([len(r) for r in graphs], np.int32)
+        rps, cis, vals, ro, no, gof = [], [], [], [], [0], []
+        rtot = ztot = 0
+        for g, csrs in enumerate(parts):
+            for rp, ci, v in csrs:
+                ro.append(rtot)
+                rps.append(rp)
+                cis.append(ci)
+                vals.append(v)
+                rtot += rp.size
+                ztot += ci.size
+                no.append(ztot)
+                gof.append(g)
+        self.row_ptr = np.concatenate(rps)
+        self.col_idx = np.concatenate(cis)
+        self.values = np.concatenate(vals).astype(self.dtype) if weighted else None
+        self.rowptr_off = np.array(ro, np.int64)
+        self.nnz_off = np.array(no, np.int64)
+        self.graph_of = np.array(gof, np.int32)
+        self.R = len(ro)
+
+    def csr(self, r):
+        g = int(self.graph_of[r])
+        n = int(self.n[g])
+        rp = self.row_ptr[self.rowptr_off[r]: self.rowptr_off[r] + n + 1]
+        a, b = int(self.nnz_off[r]), int(self.nnz_off[r + 1])
+        return n, rp, self.col_idx[a:b], None if self.values is None else self.values[a:b]
+
+
+def run_gpu(hb, **kw):
+    torch = torch_mod()
+    b = api().Batch.from_host(hb)
+    out = b.scores(**kw)
+    torch.cuda.synchronize()
+    return b, out
+
+
+def check_against_oracle(hb, out, b, m, tol_key, K=None, tol=0.0, m_max=60, reorth_ref=2, check_m=True):
+    ref = oscores.batch_scores(hb, m=m, tol=tol, m_max=m_max, reorth=reorth_ref)
+    s_all = out.scores.double().cpu().numpy()
+    ls = out.log_scale.cpu().numpy()
+    diag = out.diag_numpy()
+    report = []
+    r0 = 0
+    for g, gsc in enumerate(ref):
+        s_hat = scaled(s_all[b.graph_slice(g)], ls[g], gsc.log_scale)
+        k = K if K is not None else min(10, s_hat.size)
+        en, et = errors(s_hat, gsc.s, k)
+        report.append((en, et))
+        assert en <= TOL[tol_key], f"graph {g}: err_norm {en:.3e}"
+        assert et <= TOL[tol_key], f"graph {g}: err_top {et:.3e}"
+        R_g = int(b.graph_nreal[g])
+        m_gpu = diag["m_used"][r0:r0 + R_g]
+        if check_m:
+            assert np.array_equal(m_gpu, gsc.m_used), (m_gpu, gsc.m_used)
+        else:
+            assert np.max(np.abs(m_gpu - gsc.m_used)) <= 1
+        r0 += R_g
+    return ref, report
+
+
+# ------------------------------------------------------------------ component: SpMV
+
+@pytest.mark.parametrize("lanes", [4, 8, 16, 32])
+@pytest.mark.parametrize("hub", [0, 3])
+def test_spmv_fp64_exact_on_patterns(gpu_lib, lanes, hub):
+    torch = torch_mod()
+    n = 5000
+    keys = G.ba_keys(n, 4, G.rng_for(11, 0, 1))          # heavy-tailed degrees: exercises the hub path
+    rp, ci = G.csr_from_keys(keys, n)
+    x = np.random.default_rng(1).integers(-8, 9, size=n).astype(np.float64)  # integer sums: exact in FP64
+    ref = odense.csr_to_scipy(n, rp, ci) @ x
+    dev = torch.device("cuda")
+    y = api().spmv(torch.as_tensor(rp).to(dev), torch.as_tensor(ci).to(dev), None,
+                   torch.as_tensor(x).to(dev), lanes=lanes, hub=hub)
+    assert np.array_equal(y.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_spmv_fp32_ragged(gpu_lib, weighted):
+    torch = torch_mod()
+    n = 3077  # not a multiple of the 1024-row tile
+    keys = G.er_keys(n, 12.0 / (n - 1), G.rng_for(11, 1, 1))
+    rp, ci = G.csr_from_keys(keys, n)
+    rng = np.random.default_rng(2)
+    vals = rng.uniform(0.5, 1.5, ci.size).astype(np.float32) if weighted else None
+    x = rng.normal(size=n).astype(np.float32)
+    ref = odense.csr_to_scipy(n, rp, ci, vals) @ x.astype(np.float64)
+    dev = torch.device("cuda")
+    y = api().spmv(torch.as_tensor(rp).to(dev), torch.as_tensor(ci).to(dev),
+                   None if vals is None else torch.as_tensor(vals).to(dev), torch.as_tensor(x).to(dev))
+    assert np.max(np.abs(y.cpu().numpy() - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+# ------------------------------------------------------------------ component: tridiagonal exponential
+
+@pytest.mark.parametrize("k", [1, 2, 7, 30, 64])
+def test_tridiag_expv_vs_oracle(gpu_lib, k):
+    torch = torch_mod()
+    rng = np.random.default_rng(k)
+    cases = []
+    for kind in ("random", "clustered", "split", "wide"):
+        a = rng.normal(0, 4, k)
+        b = np.abs(rng.normal(0, 2, k))
+        if kind == "clustered":
+            a = 3.0 + 1e-9 * rng.normal(size=k)
+            b = np.full(k, 1e-7)
+        if kind == "split" and k > 3:
+            b[k // 2] = 0.0
+        if kind == "wide":
+            a = rng.normal(0, 40, k)
+            b = np.abs(rng.normal(0, 30, k))
+        cases.append((a, b))
+    alpha = np.stack([c[0] for c in cases])
+    beta = np.stack([c[1] for c in cases])
+    dev = torch.device("cuda")
+    y, th = api().tridiag_expv(torch.as_tensor(alpha).to(dev), torch.as_tensor(beta).to(dev))
+    y, th = y.cpu().numpy(), th.cpu().numpy()
+    for c, (a, b) in enumerate(cases):
+        yr, tr = otridiag.expv_e1(a, b[: k - 1])
+        assert abs(th[c] - tr) <= 1e-13 * max(1.0, abs(tr)), (c, th[c], tr)
+        # ||exp(T - theta I)||_2 = 1 and ||e1|| = 1: both routes are accurate to a few ulps of 1 in absolute
+        # terms, and relatively whenever y is not itself tiny (as it never is for a Lanczos T started at v1)
+        assert np.max(np.abs(y[c] - yr)) <= 1e-13 * max(np.max(np.abs(yr)), 1e-2), c
+
+
+# ------------------------------------------------------------------ closed forms through the whole path
+
+@pytest.mark.parametrize("name,A,closed_val", [
+    ("K100", gs.complete(100), lambda n: np.full(n, np.exp(99.0))),
+    ("C2500", gs.cycle(2500), lambda n: np.full(n, np.exp(2.0))),
+])
+def test_regular_graphs_break_down_at_one_step(gpu_lib, name, A, closed_val):
+    hb = DenseBatch([[A]], "f64")
+    b, out = run_gpu(hb, m=20)
+    d = out.diag_numpy()
+    assert d["m_used"][0] == 1 and d["flags"][0] & 1
+    s = out.scores.cpu().numpy() * np.exp(out.log_scale.cpu().numpy()[0])
+    ref = closed_val(A.shape[0])
+    assert np.max(np.abs(s - ref)) <= 1e-12 * ref.max()
+
+
+def test_star_and_empty_graph(gpu_lib):
+    star = gs.bipartite(1, 1499)
+    a = np.sqrt(1499.0)
+    ref_star = np.array([np.cosh(a) + a * np.sinh(a)] + [np.cosh(a) + np.sinh(a) / a] * 1499)
+    hb = DenseBatch([[star], [np.zeros((700, 700))]], "f64")
+    b, out = run_gpu(hb, m=20)
+    d = out.diag_numpy()
+    assert d["m_used"].tolist() == [2, 1]
+    s = out.scores.cpu().numpy()
+    ls = out.log_scale.cpu().numpy()
+    got_star = s[b.graph_slice(0)] * np.exp(ls[0])
+    assert np.max(np.abs(got_star - ref_star)) <= 1e-12 * ref_star.max()
+    assert np.max(np.abs(s[b.graph_slice(1)] - 1.0)) <= 1e-15 and ls[1] == 0.0
+
+
+def test_path_krylov_space_closes_exact(gpu_lib):
+    n = 41
+    hb = DenseBatch([[gs.path(n)]], "f64")
+    b, out = run_gpu(hb, m=40)
+    assert out.diag_numpy()["m_used"][0] == (n + 1) // 2
+    ref = odense.ebtc_eigh(gs.path(n))
+    s = out.scores.cpu().numpy() * np.exp(out.log_scale.cpu().numpy()[0])
+    assert np.max(np.abs(s - ref)) <= 1e-12 * ref.max()
+
+
+def test_fp32_overflow_without_shift_is_flagged(gpu_lib):
+    hb = DenseBatch([[gs.complete(120)]], "f32")
+    b, out = run_gpu(hb, m=10, shift=False)
+    assert out.diag_numpy()["flags"][0] & 4  # NONFINITE: e^119 is beyond FP32
+
+
+# ------------------------------------------------------------------ end to end, tiny workload (FP64)
+
+@pytest.mark.parametrize("schedule,hipgraph", [("plain", False), ("batched", False), ("batched", True)])
+def test_tiny_workload_fp64(gpu_lib, schedule, hipgraph):
+    import json
+    import os
+    w = C.workload(0)
+    hb = C.build(w)
+    b, out = run_gpu(hb, m=w.m, schedule=schedule, hipgraph=hipgraph)
+    ref, rep = check_against_oracle(hb, out, b, w.m, "f64", K=10)
+    idx, val = b.topk(out.scores, 10)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "tiny_er_n200_oracle.json")))
+    assert idx.cpu().numpy().tolist() == gold["topk"]
+    assert idx.cpu().numpy().tolist() == oscores.topk(ref[0].s, 10).tolist()
+
+
+def test_schedules_agree_bitwise(gpu_lib):
+    torch = torch_mod()
+    w = C.scaled(C.workload(1), n=9000, N=5)
+    hb = C.build(w)
+    b = api().Batch.from_host(hb)
+    outs = []
+    for sched, hg in (("plain", False), ("batched", False), ("batched", True), ("batched", True)):
+        o = b.scores(m=w.m, schedule=sched, hipgraph=hg)
+        torch.cuda.synchronize()
+        outs.append(o.scores.cpu().numpy().copy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])  # fixed-order reductions: deterministic across schedules
+
+
+def test_hipgraph_replays_match_eager(gpu_lib):
+    torch = torch_mod()
+    w = C.scaled(C.workload(1), n=6000, N=4)
+    hb = C.build(w)
+    b = api().Batch.from_host(hb)
+    eager = b.scores(m=w.m, hipgraph=False)
+    torch.cuda.synchronize()
+    e = eager.scores.cpu().numpy().copy()
+    run = b.run(m=w.m, hipgraph=True)
+    for _ in range(4):
+        out = run.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.scores.cpu().numpy(), e)
+        _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+
+
+# ------------------------------------------------------------------ FP32 workloads, reduced and full size
+
+def test_batched_er_fp32_reduced(gpu_lib):
+    w = C.scaled(C.workload(1), n=20000, N=6)
+    hb = C.build(w)
+    b, out = run_gpu(hb, m=w.m)
+    ref, rep = check_against_oracle(hb, out, b, w.m, "f32", K=50)
+    idx, _ = b.topk(out.scores, 50)
+    ok, band = topk_consistent(idx.cpu().numpy(), ref[0].s, 50, TOL["f32"])
+    assert ok
+
+
+def test_uneven_graphs_one_batch(gpu_lib):
+    # three graphs of different sizes and families, ragged tails, 1..3 realizations each
+    w = C.scaled(C.workload(4), graphs=slice(0, 3))
+    specs = [dict(n=2500, N=2), dict(n=1100, N=3), dict(n=4097, N=1)]
+    import dataclasses
+    w = dataclasses.replace(w, graphs=tuple(dataclasses.replace(s, **kw) if s.family != "er" else
+                                            dataclasses.replace(s, bg=s.bg * (s.n - 1) / (kw["n"] - 1), **kw)
+                                            for s, kw in zip(w.graphs, specs)))
+    hb = C.build(w)
+    b, out = run_gpu(hb, m=30)
+    check_against_oracle(hb, out, b, 30, "f32", K=20)
+    for g in range(3):
+        assert out.log_scale.cpu().numpy()[g] > 0
+
+
+def test_adaptive_mode_fp32(gpu_lib):
+    w = C.scaled(C.workload(4), graphs=slice(0, 4))
+    import dataclasses
+    w = dataclasses.replace(w, graphs=tuple(dataclasses.replace(s, n=3000, N=2, bg=(s.bg * (s.n - 1) / 2999)
+                                                                if s.family == "er" else s.bg) for s in w.graphs))
+    hb = C.build(w)
+    b, out = run_gpu(hb, m=0, tol=1e-6, m_max=60)
+    check_against_oracle(hb, out, b, 0, "f32", K=20, tol=1e-6, m_max=60, check_m=False)
+    d = out.diag_numpy()
+    assert np.all(d["est"] < 1e-6) or np.any(d["flags"] & 2)
+
+
+def test_reorth_two_passes(gpu_lib):
+    w = C.scaled(C.workload(3), n=12000, N=3)
+    hb = C.build(w)
+    b, out = run_gpu(hb, m=w.m, reorth=2)
+    check_against_oracle(hb, out, b, w.m, "f32", K=40)
+
+
+def test_weighted_values(gpu_lib):
+    w = C.scaled(C.workload(3), n=8000, N=2)
+    hb = C.build(w)
+    rng = np.random.default_rng(5)
+    # symmetric weights: one weight per undirected edge
+    vals = np.empty(hb.col_idx.size, np.float32)
+    for r in range(hb.R):
+        n, rp, ci, _ = hb.csr(r)
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        lo, hi = np.minimum(rows, ci), np.maximum(rows, ci)
+        h = (lo.astype(np.int64) * 2654435761 + hi * 40503) % 1000
+        vals[hb.nnz_off[r]:hb.nnz_off[r + 1]] = 0.5 + h / 1000.0
+    hb.values = vals
+    b, out = run_gpu(hb, m=w.m)
+    check_against_oracle(hb, out, b, w.m, "f32", K=40)
+
+
+# ------------------------------------------------------------------ top-K
+
+def test_topk_ties_and_sizes(gpu_lib):
+    torch = torch_mod()
+    rng = np.random.default_rng(7)
+    sizes = [1, 5, 1000, 4097]
+
+    class B:  # empty graphs of the block sizes under test: only the graph table matters for top-K
+        pass
+    hb = B()
+    hb.dtype = np.float32
+    hb.n = np.array(sizes, np.int32)
+    hb.nreal = np.ones(len(sizes), np.int32)
+    hb.rowptr_off = np.concatenate([[0], np.cumsum(np.array(sizes) + 1)[:-1]]).astype(np.int64)
+    hb.nnz_off = np.zeros(len(sizes) + 1, np.int64)
+    hb.row_ptr = np.zeros(int(np.sum(np.array(sizes) + 1)), np.int32)
+    hb.col_idx = np.zeros(1, np.int32)
+    hb.values = None
+    b = api().Batch.from_host(hb)
+    blocks = [rng.integers(0, 7, size=n).astype(np.float32) for n in sizes]  # heavy ties
+    blocks[3][::3] = 1e30
+    s = torch.as_tensor(np.concatenate(blocks)).to("cuda")
+    ks = [1, 5, 37, 1500]
+    idx, val = b.topk(s, ks)
+    idx = idx.cpu().numpy()
+    o = 0
+    for blk, k in zip(blocks, ks):
+        brute = [i for _, i in sorted((-float(v), i) for i, v in enumerate(blk))][:k]
+        assert idx[o:o + k].tolist() == brute
+        o += k
+
+
+def test_validate_detects_bad_realization(gpu_lib):
+    good = gs.random_graph(300, 0.05, 1)
+    bad = gs.random_graph(300, 0.05, 2)
+    bad[3, 7] = 1.0
+    bad[7, 3] = 0.0  # asymmetric
+    hb = DenseBatch([[good, good, bad]], "f64")
+    b = api().Batch.from_host(hb)
+    assert b.validate() == 2
+    hb2 = DenseBatch([[good, good]], "f64")
+    assert api().Batch.from_host(hb2).validate() == -1
