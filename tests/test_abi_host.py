@@ -127,13 +127,14 @@ def expected_ws(G, nreal, n, m_slots, es, rstate_bytes):
     off = align(off + 4 * blocks)
     off = align(off + rstate_bytes * R)
     off = align(off + 8 * 64 * blocks)
+    off = align(off + 8 * blocks)
     off = align(off + es * m_slots * rows)
     off = align(off + es * rows)
     off = align(off + es * rows)
     return off
 
 
-RSTATE_BYTES = 8 * (64 + 64 + 65 + 65 + 64 + 4) + 4 * 8
+RSTATE_BYTES = 8 * (64 + 64 + 65 + 65 + 64 + 4) + 4 * 4
 
 
 @pytest.mark.parametrize("dtype,es", [(A.EBTC_F32, 4), (A.EBTC_F64, 8)])
