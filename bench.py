@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 
 METRIC = "graph-realizations/s for Krylov exp(A)·1 + achieved HBM GB/s; batched vs plain"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_spmv_dots.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c1.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1409_5000_amd", "csrc", f) for f in ("k_lanczos.hip", "internal.h")]
 
 
@@ -43,8 +43,14 @@ def log(msg: str) -> None:
 # n rows, z stored entries, j = step, es = vector/value element bytes; every array element touched
 # once per launch (the gathered vector counted once: n elements).
 
-def spmv_dots_bytes(n, z, j, es, has_val):
-    return 4 * (n + 1) + z * (4 + (es if has_val else 0)) + n * es + (j + 1) * n * es + n * es
+def spmv_bytes(n, z, es, has_val):
+    # row_ptr, col_idx, values, the gathered vector (each element once), w written
+    return 4 * (n + 1) + z * (4 + (es if has_val else 0)) + n * es + n * es
+
+
+def dots_bytes(n, j, es):
+    # w and basis vectors 0..j read
+    return n * es + (j + 1) * n * es
 
 
 def update_bytes(n, j, es):
@@ -63,16 +69,16 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(achieved_bytes_per_launch: float):
-    """HBM bytes per spmv_dots launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source; else None."""
+def load_traffic(kernel_phase: str, alg_bytes_per_launch: float):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
         t = json.load(f)
     if t.get("kernel_hash") != kernel_hash():
         return None
-    return t.get("hbm_bytes_per_launch")
+    return t.get("hbm_bytes_per_launch", {}).get(kernel_phase)
 
 
 def main() -> int:
@@ -84,6 +90,10 @@ def main() -> int:
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workers", type=int, default=0)
+    ap.add_argument("--seg-len", type=int, default=0, help="SpMV gather source: 0 auto, -1 direct, >0 LDS segment")
+    ap.add_argument("--realizations", type=int, default=0, help="limit realizations per graph (0 = all)")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="for rocprofv3: one eager batched pass per gather form plus a 1 GiB copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (realizations and graphs "
@@ -108,7 +118,7 @@ def main() -> int:
 
     w = C.workload(args.config)
     t0 = time.time()
-    hb = C.build_parallel(w, workers=workers)
+    hb = C.build_parallel(w, workers=workers, realizations=args.realizations or None)
     log(f"generated {w.name}: R={hb.R} nnz={hb.nnz_off[-1]} in {time.time() - t0:.1f}s")
     m, tol, m_max = w.m, (w.tol or 1e-6), (w.m_max or 60)
     b = api.Batch.from_host(hb)
@@ -116,7 +126,19 @@ def main() -> int:
     has_val = hb.values is not None
     K = hb.K
 
-    run = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=True, diag=True)
+    if args.profile_run:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)  # calibration: reads and writes exactly 1 GiB
+        out = {}
+        for label, sl, ln in (("stream", -1, 0), ("lane_groups", -1, 8), ("lds_staged", 35000, 0)):
+            rr = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=False, diag=False, seg_len=sl, lanes=ln)
+            out[label] = rr.profile()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": w.name, "realizations": hb.R, "phases": out}), flush=True)
+        return 0
+
+    run = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=True, diag=True, seg_len=args.seg_len)
 
     def step(r):
         out = r.launch()
@@ -143,7 +165,7 @@ def main() -> int:
     gpu_ls = run.log_scale.cpu().numpy()
 
     # plain per-realization loop on the same batch
-    runp = b.run(m=m, tol=tol, m_max=m_max, schedule="plain", hipgraph=False, diag=False)
+    runp = b.run(m=m, tol=tol, m_max=m_max, schedule="plain", hipgraph=False, diag=False, seg_len=args.seg_len)
     step(runp)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -155,30 +177,42 @@ def main() -> int:
     log(f"plain: {1000 * plain_wall / args.plain_steps:.3f} ms/step, {plain_value:.1f} realizations/s")
 
     # per-kernel durations with HIP events around each launch (eager batched sequence)
-    rune = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=False, diag=True)
+    rune = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=False, diag=True, seg_len=args.seg_len)
     rune.profile()
     phases = rune.profile()
+    # the two SpMV gather forms side by side (LDS-staged column segments vs direct gathers)
+    spmv_modes = {}
+    for label, sl, ln in (("stream", -1, 0), ("lane_groups", -1, 8), ("lds_staged", 35000, 0)):
+        rr = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=False, diag=False, seg_len=sl, lanes=ln)
+        rr.profile()
+        ph = rr.profile()
+        spmv_modes[label] = round(ph["spmv"][0] / max(1, ph["spmv"][1]), 5)
+        del rr
+    log(f"spmv ms/launch by gather form: {spmv_modes}")
     d = rune.launch().diag_numpy()
     torch.cuda.synchronize()
     m_used = d["m_used"]
-    sd_bytes = 0.0
-    up_bytes = 0.0
+    sp_bytes = dt_bytes = up_bytes = 0.0
     for r in range(hb.R):
         n, rp, ci, _ = hb.csr(r)
         z = ci.size
         for j in range(int(m_used[r])):
-            sd_bytes += spmv_dots_bytes(n, z, j, es, has_val)
+            sp_bytes += spmv_bytes(n, z, es, has_val)
+            dt_bytes += dots_bytes(n, j, es)
             up_bytes += update_bytes(n, j, es)
-    sd_ms, sd_launches = phases["spmv_dots"]
-    up_ms, up_launches = phases["update"]
-    dominant = max(phases, key=lambda p: phases[p][0])
-    achieved = sd_bytes / (sd_ms * 1e-3) / 1e9
-    per_launch = sd_bytes / max(1, sd_launches)
-    traffic = load_traffic(per_launch)
-    total_alg = sd_bytes + up_bytes + sum(combine_bytes(int(hb.n[hb.graph_of[r]]), int(m_used[r]), es)
-                                          for r in range(hb.R))
+    alg = {"spmv": sp_bytes, "dots": dt_bytes, "update": up_bytes}
+    if phases["dots"][1] == 0:  # vector staged in LDS: SpMV and dots are one kernel (w read counted once extra)
+        alg = {"spmv": sp_bytes + dt_bytes, "update": up_bytes}
+    dominant = max(alg, key=lambda p: phases[p][0])
+    dom_ms, dom_launches = phases[dominant]
+    achieved = alg[dominant] / (dom_ms * 1e-3) / 1e9
+    per_launch = alg[dominant] / max(1, dom_launches)
+    traffic = load_traffic(dominant, per_launch)
+    total_alg = sp_bytes + dt_bytes + up_bytes + sum(
+        combine_bytes(int(hb.n[hb.graph_of[r]]), int(m_used[r]), es) for r in range(hb.R))
     log("phases (ms, launches): " + ", ".join(f"{p}={v[0]:.3f}/{v[1]}" for p, v in phases.items()))
-    log(f"spmv_dots: {achieved:.0f} GB/s algorithmic; update: {up_bytes / (up_ms * 1e-3) / 1e9:.0f} GB/s")
+    log("algorithmic GB/s: " + ", ".join(f"{p}={alg[p] / (phases[p][0] * 1e-3) / 1e9:.0f}" for p in alg
+                                         if phases[p][0] > 0))
 
     result = {
         "metric": METRIC,
@@ -200,11 +234,12 @@ def main() -> int:
         "plain": {"value": round(plain_value, 2), "ms_per_step": round(1000 * plain_wall / args.plain_steps, 3),
                   "batched_over_plain": round(value / plain_value, 2)},
         "effective_GBps_whole_path": round(total_alg * args.steps / wall / 1e9, 1),
-        "roofline": {"bound": "hbm", "kernel": "k_spmv_dots (SpMV + dot partials)", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "alg_bytes_per_launch": round(per_launch),
-                     "avg_launch_ms": round(sd_ms / max(1, sd_launches), 5), "dominant_phase": dominant,
-                     "phase_ms": {p: round(v[0], 4) for p, v in phases.items()}},
+                     "avg_launch_ms": round(dom_ms / max(1, dom_launches), 5), "dominant_phase": dominant,
+                     "phase_ms": {p: round(v[0], 4) for p, v in phases.items()},
+                     "spmv_ms_per_launch_by_gather_form": spmv_modes},
         "cpu_baseline": None,
         "parity": None,
     }

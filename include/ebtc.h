@@ -95,6 +95,9 @@ typedef struct {
   int32_t shift;         /* 1 (default): factor out theta*; 0: theta* = 0 (overflow-prone, tests)  */
   int32_t lanes_per_row; /* SpMV lanes per CSR row: 0 = auto, else 4, 8, 16 or 32                 */
   int32_t hub_threshold; /* rows with more entries are reduced by a whole workgroup; 0 = auto     */
+  int32_t seg_len;       /* SpMV gather source: 0 = auto, -1 = gather from HBM/L2, > 0 = stage the
+                            vector through LDS in column segments of this many elements (clamped to
+                            what fits next to the per-row state: 35328 FP32 / 16640 FP64)        */
 } ebtc_opts;
 
 /* Per-realization diagnostics (device array [R], written by ebtc_scores). */
@@ -155,10 +158,10 @@ int ebtc_topk(ebtc_batch* batch, const void* scores, const int32_t* k_per_graph,
 
 /* ---------------------------------------------------------------- component entry points         */
 /* y = A x for one CSR matrix (the Krylov step's product), asynchronous. Same CSR rules as a batch;
- * values NULL = all ones; x, y device [n] of dtype, distinct. lanes_per_row / hub_threshold as in
- * ebtc_opts. */
+ * values NULL = all ones; x, y device [n] of dtype, distinct. lanes_per_row / hub_threshold /
+ * seg_len as in ebtc_opts (seg_len 0 here means gather without staging). */
 int ebtc_spmv(int32_t dtype, int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const void* values,
-              const void* x, void* y, int32_t lanes_per_row, int32_t hub_threshold, void* stream);
+              const void* x, void* y, int32_t lanes_per_row, int32_t hub_threshold, int32_t seg_len, void* stream);
 
 /* For `count` symmetric tridiagonal matrices of size k (1 <= k <= EBTC_M_LIMIT), FP64, asynchronous:
  * theta_out[c] = largest eigenvalue (0 when shift == 0) and y_out[c*k ..] = exp(T_c - theta I) e1.
@@ -170,8 +173,8 @@ int ebtc_tridiag_expv(int32_t count, int32_t k, const double* alpha, const doubl
 /* ---------------------------------------------------------------- measurement                    */
 enum ebtc_phase {
   EBTC_PHASE_START = 0,      /* start vector and state initialisation                           */
-  EBTC_PHASE_SPMV_DOTS = 1,  /* w = A v_j and the partial dots <v_i, w>                         */
-  EBTC_PHASE_DOTS_AGAIN = 2, /* second Gram-Schmidt pass: dots (reorth = 2 only)                */
+  EBTC_PHASE_SPMV = 1,       /* w = A v_j (with the dots too when the vector is staged in LDS)  */
+  EBTC_PHASE_DOTS = 2,       /* partial dots <v_i, w> (both Gram-Schmidt passes)               */
   EBTC_PHASE_UPDATE = 3,     /* Gram-Schmidt update, norm, breakdown test                       */
   EBTC_PHASE_TRIDIAG = 4,    /* FP64 tridiagonal exponential (final and adaptive checks)        */
   EBTC_PHASE_COMBINE = 5,    /* u = beta0 V y                                                    */

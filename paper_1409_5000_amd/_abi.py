@@ -25,7 +25,7 @@ EXPORTED = [
     "ebtc_batch_destroy", "ebtc_plan", "ebtc_scores", "ebtc_topk_ws_bytes", "ebtc_topk", "ebtc_spmv",
     "ebtc_tridiag_expv", "ebtc_validate_ws_bytes", "ebtc_validate", "ebtc_profile_phases",
 ]
-PHASES = ["start", "spmv_dots", "dots_again", "update", "tridiag", "combine", "sum"]
+PHASES = ["start", "spmv", "dots", "update", "tridiag", "combine", "sum"]
 
 
 class BatchDesc(ctypes.Structure):
@@ -41,6 +41,7 @@ class Opts(ctypes.Structure):
     _fields_ = [
         ("m", c_int32), ("m_max", c_int32), ("tol", c_double), ("reorth", c_int32), ("schedule", c_int32),
         ("use_hipgraph", c_int32), ("shift", c_int32), ("lanes_per_row", c_int32), ("hub_threshold", c_int32),
+        ("seg_len", c_int32),
     ]
 
 
@@ -76,7 +77,7 @@ def lib() -> ctypes.CDLL:
         "ebtc_scores": (c_int, [vp, POINTER(Opts), vp, sz, vp, vp, vp, vp, vp]),
         "ebtc_topk_ws_bytes": (c_int, [vp, POINTER(sz)]),
         "ebtc_topk": (c_int, [vp, vp, POINTER(c_int32), vp, vp, vp, sz, vp]),
-        "ebtc_spmv": (c_int, [c_int32, c_int32, vp, vp, vp, vp, vp, c_int32, c_int32, vp]),
+        "ebtc_spmv": (c_int, [c_int32, c_int32, vp, vp, vp, vp, vp, c_int32, c_int32, c_int32, vp]),
         "ebtc_tridiag_expv": (c_int, [c_int32, c_int32, vp, vp, vp, vp, c_int32, vp]),
         "ebtc_validate_ws_bytes": (c_int, [vp, POINTER(sz)]),
         "ebtc_validate": (c_int, [vp, vp, sz, POINTER(c_int64), vp]),

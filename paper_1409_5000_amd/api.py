@@ -33,9 +33,10 @@ def current_stream() -> ctypes.c_void_p:
 
 
 def make_opts(m: int = 30, tol: float = 1e-6, m_max: int = 60, reorth: int = 1, schedule: str = "batched",
-              hipgraph: bool = True, shift: bool = True, lanes: int = 0, hub: int = 0) -> A.Opts:
+              hipgraph: bool = True, shift: bool = True, lanes: int = 0, hub: int = 0, seg_len: int = 0) -> A.Opts:
     return A.default_opts(m=m, tol=tol, m_max=m_max, reorth=reorth, schedule=_SCHED[schedule],
-                          use_hipgraph=int(hipgraph), shift=int(shift), lanes_per_row=lanes, hub_threshold=hub)
+                          use_hipgraph=int(hipgraph), shift=int(shift), lanes_per_row=lanes, hub_threshold=hub,
+                          seg_len=seg_len)
 
 
 @dataclass
@@ -173,12 +174,12 @@ class Batch:
 
 
 def spmv(row_ptr: torch.Tensor, col_idx: torch.Tensor, values: torch.Tensor | None, x: torch.Tensor,
-         lanes: int = 0, hub: int = 0) -> torch.Tensor:
-    """y = A x for one CSR matrix on the device (the Krylov step's product)."""
+         lanes: int = 0, hub: int = 0, seg_len: int = 0) -> torch.Tensor:
+    """y = A x for one CSR matrix on the device (the Krylov step's product); seg_len > 0 stages x in LDS."""
     code = A.EBTC_F64 if x.dtype == torch.float64 else A.EBTC_F32
     y = torch.empty_like(x)
     A.check(A.lib().ebtc_spmv(code, x.numel(), _vp(row_ptr), _vp(col_idx), _vp(values), _vp(x), _vp(y), lanes, hub,
-                              current_stream()))
+                              seg_len, current_stream()))
     return y
 
 

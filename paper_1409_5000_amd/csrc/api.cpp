@@ -40,12 +40,12 @@ struct ExecKey {
   double* log_scale;
   void* ckpt;
   ebtc_diag* diag;
-  int m, m_max, reorth, shift, lanes, hub;
+  int m, m_max, reorth, shift, lanes, hub, seglen;
   double tol;
   bool operator==(const ExecKey& o) const {
     return ws == o.ws && scores == o.scores && log_scale == o.log_scale && ckpt == o.ckpt && diag == o.diag &&
            m == o.m && m_max == o.m_max && reorth == o.reorth && shift == o.shift && lanes == o.lanes &&
-           hub == o.hub && tol == o.tol;
+           hub == o.hub && seglen == o.seglen && tol == o.tol;
   }
 };
 
@@ -94,14 +94,23 @@ int check_opts(const ebtc_opts* o) {
       o->lanes_per_row != 32)
     return fail(EBTC_EINVAL, "lanes_per_row must be 0, 4, 8, 16 or 32");
   if (o->hub_threshold < 0) return fail(EBTC_EINVAL, "hub_threshold must be >= 0");
+  if (o->seg_len < -1) return fail(EBTC_EINVAL, "seg_len must be -1, 0 or > 0");
   return EBTC_OK;
 }
 
+// Schedule of the SpMV for a batch: lanes per row, hub threshold and LDS segment length.
+struct SpmvPlan {
+  int lanes, hub, seglen;
+};
+
+SpmvPlan spmv_plan(const ebtc_batch* b, const ebtc_opts* o);
+
+// Lanes per CSR row: the SpMV loads four entries per lane before using them, so L lanes cover 4L
+// entries per trip; pick the smallest power of two with 4L >= mean degree (4..32).
 int auto_lanes(double mean_degree) {
-  if (mean_degree < 6.0) return 4;
-  if (mean_degree < 20.0) return 8;
-  if (mean_degree < 48.0) return 16;
-  return 32;
+  int L = 4;
+  while (L < 32 && 4.0 * L < mean_degree) L *= 2;
+  return L;
 }
 
 Layout make_layout(const ebtc_batch* b, const ebtc_opts* o) {
@@ -174,6 +183,25 @@ int upload_tables(ebtc_batch* b, char* ws, const Layout& L, hipStream_t s) {
   return EBTC_OK;
 }
 
+SpmvPlan spmv_plan(const ebtc_batch* b, const ebtc_opts* o) {
+  SpmvPlan p;
+  const int maxseg = staged_max_seglen(b->dtype);
+  int seg = o->seg_len;
+  if (seg == 0) {
+    // Stage when the vector passes through LDS in at most four segments (the per-workgroup staging
+    // traffic, n elements, then stays near the CSR bytes the workgroup streams) and rows are short
+    // enough for their entries to sit in registers (mean degree <= 24 for 32 register slots).
+    const int nseg = (b->n_max + maxseg - 1) / maxseg;
+    seg = -1;  // measured: the CSR-stream SpMV is the faster default; staging stays selectable
+    (void)nseg;
+  }
+  p.seglen = seg > 0 ? std::min(seg, maxseg) : 0;
+  // lanes 0 = the CSR-stream SpMV (default); explicit lanes select the lane-group SpMV
+  p.lanes = o->lanes_per_row;
+  p.hub = o->hub_threshold ? o->hub_threshold : 16 * (p.lanes ? p.lanes : 8);
+  return p;
+}
+
 LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, int hub) {
   LzArgs a{};
   a.row_ptr = b->row_ptr;
@@ -190,6 +218,7 @@ LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout
   a.part = (double*)(ws + L.off_part);
   a.npart = (double*)(ws + L.off_npart);
   a.m_fixed = o->m;
+  a.seglen = spmv_plan(b, o).seglen;
   a.m_max = o->m > 0 ? o->m : o->m_max;
   a.eps = b->dtype == EBTC_F64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
   return a;
@@ -238,10 +267,11 @@ int run_steps(const ebtc_batch* b, const ebtc_opts* o, const LzArgs& a, int64_t 
   const int steps = o->m > 0 ? o->m : o->m_max;
   EBTC_PHASE(prof, EBTC_PHASE_START, launch_start(b->dtype, a, nblocks, s));
   for (int j = 0; j < steps; ++j) {
-    EBTC_PHASE(prof, EBTC_PHASE_SPMV_DOTS, launch_spmv_dots(b->dtype, has_val, lanes, j, a, nblocks, s));
+    EBTC_PHASE(prof, EBTC_PHASE_SPMV, launch_spmv_step(b->dtype, has_val, lanes, j, a, nblocks, s));
+    EBTC_PHASE(prof, EBTC_PHASE_DOTS, launch_dots_step(b->dtype, j, a, nblocks, s));
     if (o->reorth == 2) {
       EBTC_PHASE(prof, EBTC_PHASE_UPDATE, launch_update(b->dtype, j, true, false, false, a, nblocks, s));
-      EBTC_PHASE(prof, EBTC_PHASE_DOTS_AGAIN, launch_dots_again(b->dtype, j, a, nblocks, s));
+      EBTC_PHASE(prof, EBTC_PHASE_DOTS, launch_dots_again(b->dtype, j, a, nblocks, s));
       EBTC_PHASE(prof, EBTC_PHASE_UPDATE, launch_update(b->dtype, j, false, true, true, a, nblocks, s));
     } else {
       EBTC_PHASE(prof, EBTC_PHASE_UPDATE, launch_update(b->dtype, j, true, true, false, a, nblocks, s));
@@ -327,6 +357,7 @@ void ebtc_default_opts(ebtc_opts* o) {
   o->shift = 1;
   o->lanes_per_row = 0;
   o->hub_threshold = 0;
+  o->seg_len = 0;
 }
 
 int ebtc_batch_create(const ebtc_batch_desc* d, ebtc_batch** out) {
@@ -444,8 +475,9 @@ int ebtc_scores(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, vo
     return fail(EBTC_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(L.total));
   if (((uintptr_t)ws & 255) != 0) return fail(EBTC_EINVAL, "workspace must be 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  const int lanes = o->lanes_per_row ? o->lanes_per_row : auto_lanes(b->mean_degree);
-  const int hub = o->hub_threshold ? o->hub_threshold : 16 * lanes;
+  const SpmvPlan sp = spmv_plan(b, o);
+  const int lanes = sp.lanes, hub = sp.hub;
+  if (sp.seglen > 0) EBTC_HIP(prepare_staged_kernels());
   char* w = (char*)ws;
   rc = upload_tables(b, w, L, s);
   if (rc) return rc;
@@ -453,8 +485,8 @@ int ebtc_scores(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, vo
     return enqueue_plain(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, lanes, hub, s);
   if (!o->use_hipgraph)
     return enqueue_batched(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, lanes, hub, s);
-  const ExecKey key{ws, scores_out, log_scale_out, ckpt_out, diag_out, o->m, o->m_max, o->reorth, o->shift, lanes, hub,
-                    o->tol};
+  const ExecKey key{ws,       scores_out, log_scale_out, ckpt_out, diag_out,  o->m, o->m_max,
+                    o->reorth, o->shift, lanes,         hub,      sp.seglen, o->tol};
   for (auto& e : b->execs) {
     if (e.key == key) {
       EBTC_HIP(hipGraphLaunch(e.exec, s));
@@ -498,8 +530,9 @@ int ebtc_profile_phases(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_b
   if (ws_bytes < L.total) return fail(EBTC_EWORKSPACE, "workspace too small");
   if (((uintptr_t)ws & 255) != 0) return fail(EBTC_EINVAL, "workspace must be 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  const int lanes = o->lanes_per_row ? o->lanes_per_row : auto_lanes(b->mean_degree);
-  const int hub = o->hub_threshold ? o->hub_threshold : 16 * lanes;
+  const SpmvPlan sp = spmv_plan(b, o);
+  const int lanes = sp.lanes, hub = sp.hub;
+  if (sp.seglen > 0) EBTC_HIP(prepare_staged_kernels());
   char* w = (char*)ws;
   rc = upload_tables(b, w, L, s);
   if (rc) return rc;
@@ -559,17 +592,21 @@ int ebtc_topk(ebtc_batch* b, const void* scores, const int32_t* k_per_graph, int
 }
 
 int ebtc_spmv(int32_t dtype, int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const void* values,
-              const void* x, void* y, int32_t lanes_per_row, int32_t hub_threshold, void* stream) {
+              const void* x, void* y, int32_t lanes_per_row, int32_t hub_threshold, int32_t seg_len, void* stream) {
   g_err.clear();
   if (dtype != EBTC_F32 && dtype != EBTC_F64) return fail(EBTC_EINVAL, "dtype must be EBTC_F32 or EBTC_F64");
   if (n < 1 || !row_ptr || !col_idx || !x || !y) return fail(EBTC_EINVAL, "n < 1 or NULL pointer");
   if (x == y) return fail(EBTC_EINVAL, "x and y must be distinct");
-  const int lanes = lanes_per_row ? lanes_per_row : 8;
-  if (lanes != 4 && lanes != 8 && lanes != 16 && lanes != 32)
+  const int lanes = lanes_per_row;
+  if (lanes != 0 && lanes != 4 && lanes != 8 && lanes != 16 && lanes != 32)
     return fail(EBTC_EINVAL, "lanes_per_row must be 0, 4, 8, 16 or 32");
   if (hub_threshold < 0) return fail(EBTC_EINVAL, "hub_threshold must be >= 0");
-  const int hub = hub_threshold ? hub_threshold : 16 * lanes;
-  EBTC_LAUNCH(launch_spmv(dtype, values != nullptr, lanes, hub, n, row_ptr, col_idx, values, x, y, (hipStream_t)stream));
+  if (seg_len < -1) return fail(EBTC_EINVAL, "seg_len must be -1, 0 or > 0");
+  const int hub = hub_threshold ? hub_threshold : 16 * (lanes ? lanes : 8);
+  const int seg = seg_len > 0 ? std::min(seg_len, staged_max_seglen(dtype)) : 0;
+  if (seg > 0) EBTC_HIP(prepare_staged_kernels());
+  EBTC_LAUNCH(launch_spmv(dtype, values != nullptr, lanes, hub, seg, n, row_ptr, col_idx, values, x, y,
+                          (hipStream_t)stream));
   return EBTC_OK;
 }
 

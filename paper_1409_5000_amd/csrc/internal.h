@@ -11,8 +11,10 @@
 namespace ebtc {
 
 constexpr int kBlock = 256;          // threads of a streaming workgroup (4 waves of 64)
-constexpr int kRowsPerBlock = 1024;  // CSR rows owned by one workgroup in the Lanczos kernels
+constexpr int kRowsPerBlock = 2048;  // CSR rows owned by one workgroup in the Lanczos kernels
 constexpr int kRowsPerThread = kRowsPerBlock / kBlock;
+constexpr int kStagedThreads = 1024; // threads of the LDS-staged SpMV workgroup (16 waves)
+constexpr int kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
 constexpr int kMLimit = EBTC_M_LIMIT;
 constexpr int kPartStride = 64;      // doubles per workgroup in the dot-partial arena
 constexpr int kMaxChunks = 32;       // chunks of the canonical partial-sum order
@@ -51,9 +53,10 @@ struct RState {
   double s[kMLimit + 1];
   double c[kMLimit + 1];   // Gram-Schmidt coefficients on the raw basis for the current step
   double y[kMLimit];       // exp(T - theta I) e1
+  double scal[kMLimit];    // scal[j] = max(|alpha_0..j|, beta_0..j-1): the breakdown reference of step j
   double theta;
   double est;
-  double scale;            // max(|alpha_0..j|, beta_0..j-1): the breakdown reference
+  double spare;
   double beta0;            // ||start vector|| = sqrt(n)
   int32_t m_used;
   int32_t flags;
@@ -76,25 +79,32 @@ struct LzArgs {
   void* U;
   double* part;            // dot partials
   double* npart;           // norm partials
+  int32_t seglen;          // > 0: LDS-staged SpMV with column segments of this many elements
   int32_t m_fixed;         // fixed m, or 0 (adaptive)
   int32_t m_max;
   double eps;              // unit roundoff of the working precision
   ebtc_diag* diag;         // optional diagnostics output (combine flags non-finite results there)
 };
 
-// ---- launchers (k_lanczos.hip)
+// ---- launchers (k_lanczos.hip, k_spmv.hip)
 hipError_t launch_blkmap(const Task* tasks, int64_t R, int32_t* blkmap, hipStream_t s);
 hipError_t launch_start(int dtype, const LzArgs& a, int64_t nblocks, hipStream_t s);
-hipError_t launch_spmv_dots(int dtype, bool has_val, int lanes, int j, const LzArgs& a, int64_t nblocks,
+// Phase A: the SpMV kernel (direct gathers, or LDS-staged when a.seglen > 0), then the dots kernel.
+hipError_t launch_spmv_step(int dtype, bool has_val, int lanes, int j, const LzArgs& a, int64_t nblocks,
                             hipStream_t s);
+hipError_t launch_dots_step(int dtype, int j, const LzArgs& a, int64_t nblocks, hipStream_t s);
 hipError_t launch_dots_again(int dtype, int j, const LzArgs& a, int64_t nblocks, hipStream_t s);
 hipError_t launch_update(int dtype, int j, bool from_w, bool final_pass, bool second_pass, const LzArgs& a,
                          int64_t nblocks, hipStream_t s);
 hipError_t launch_combine(int dtype, const LzArgs& a, int64_t nblocks, hipStream_t s);
 hipError_t launch_sum(int dtype, const GraphInfo* graphs, int32_t G, int32_t max_blocks, const Task* tasks,
                       const RState* state, const void* U, void* scores, double* log_scale, hipStream_t s);
-hipError_t launch_spmv(int dtype, bool has_val, int lanes, int hub, int32_t n, const int32_t* row_ptr,
+hipError_t launch_spmv(int dtype, bool has_val, int lanes, int hub, int seglen, int32_t n, const int32_t* row_ptr,
                        const int32_t* col_idx, const void* values, const void* x, void* y, hipStream_t s);
+// Largest column segment (elements) the staged SpMV can hold in LDS next to its per-row state.
+int staged_max_seglen(int dtype);
+// Opts the staged kernels in to the full LDS once per process (call before any stream capture).
+hipError_t prepare_staged_kernels();
 
 // ---- launchers (k_tridiag.hip)
 // mode 0: final (closes step m_steps-1 when still open; writes y/theta/est, diag, checkpoint);

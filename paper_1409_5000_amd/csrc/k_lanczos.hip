@@ -20,126 +20,21 @@
 namespace ebtc {
 namespace {
 
-constexpr int kWaves = kBlock / 64;
-
-// Workgroups are dispatched round-robin over the eight XCDs (workgroup id mod 8). Map them so that
-// each XCD walks a contiguous range of logical workgroups: the workgroups of one realization then
-// share one XCD's L2, where the gathered vector v_j stays resident.
-__device__ inline int logical_block() {
-  const int G = gridDim.x, b = blockIdx.x;
-  const int x = b & 7, q = b >> 3;
-  const int base = G >> 3, rem = G & 7;
-  return x * base + (x < rem ? x : rem) + q;
-}
-
-struct Ref {
-  int task;
-  int blk;
-};
-
-__device__ inline Ref resolve(const LzArgs& a) {
-  const int lb = logical_block();
-  if (a.blkmap == nullptr) return {a.single_task, lb};
-  const int t = a.blkmap[lb];
-  return {t, lb - a.tasks[t].blk_begin};
-}
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Sum of one double over the workgroup; every thread gets the result.
-__device__ inline double block_sum(double v, double* red) {
-  v = wave_sum(v);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int i = 0; i < kWaves; ++i) t += red[i];
-  return t;
-}
-
-// Butterfly reduce-scatter of P values per lane over the 64 lanes of a wave: after the call v[0]
-// of lane l holds the wave-wide sum of value index (P == 64 ? l : l >> 1). Costs P - 1 (+1)
-// shuffles instead of 6 P for P separate reductions.
-template <int P, int M>
-struct ReduceScatter {
-  __device__ static inline void run(double* v, int lane) {
-    if constexpr (P > 1) {
-      constexpr int h = P / 2;
-      const bool up = (lane & M) != 0;
-#pragma unroll
-      for (int k = 0; k < h; ++k) {
-        const double keep = up ? v[k + h] : v[k];
-        const double send = up ? v[k] : v[k + h];
-        v[k] = keep + __shfl_xor(send, M, 64);
-      }
-    } else {
-      v[0] += __shfl_xor(v[0], M, 64);
-    }
-    if constexpr (M > 1) ReduceScatter<(P > 1 ? P / 2 : 1), M / 2>::run(v, lane);
-  }
-};
-
-// w[r - r0] = scale * (A x)[r] for rows r0 <= r < r1 into LDS. Rows with more than `hub` entries are
-// reduced by the whole workgroup (tree over 256 partial sums) after the others; the rest by groups
-// of L lanes (each lane sums its strided share, then an L-lane shuffle tree).
-template <typename T, bool HAS_VAL, int L>
-__device__ inline void spmv_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                 const T* __restrict__ va, const T* __restrict__ x, int r0, int r1, int hub,
-                                 double scale, T* w_lds, int* hub_list, int* hub_count, double* red) {
-  const int tid = threadIdx.x;
-  if (tid == 0) *hub_count = 0;
-  __syncthreads();
-  const int grp = tid / L, lane = tid % L;
-  for (int r = r0 + grp; r < r1; r += kBlock / L) {
-    const int b = rp[r], e = rp[r + 1];
-    if (e - b > hub) {
-      if (lane == 0) hub_list[atomicAdd(hub_count, 1)] = r;
-      continue;
-    }
-    T acc = 0;
-    for (int k = b + lane; k < e; k += L) {
-      const T xv = x[ci[k]];
-      if constexpr (HAS_VAL) acc += va[k] * xv; else acc += xv;
-    }
-#pragma unroll
-    for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) w_lds[r - r0] = (T)((double)acc * scale);
-  }
-  __syncthreads();
-  const int nh = *hub_count;
-  for (int h = 0; h < nh; ++h) {
-    const int r = hub_list[h];
-    const int b = rp[r], e = rp[r + 1];
-    T acc = 0;
-    for (int k = b + tid; k < e; k += kBlock) {
-      const T xv = x[ci[k]];
-      if constexpr (HAS_VAL) acc += va[k] * xv; else acc += xv;
-    }
-    const double tot = block_sum((double)acc, red);
-    if (tid == 0) w_lds[r - r0] = (T)(tot * scale);
-  }
-  __syncthreads();
-}
-
 // Partial dots p_i = sum_rows Vraw_i[r] * w[r] (i <= j) of this workgroup's rows, reduced over the
-// workgroup and stored to part_blk[i]. Basis loads are issued eight vectors at a time (clamped to
-// slot j, whose contribution is masked) so that many loads are in flight per thread.
-template <typename T, int P>
+// workgroup (NT threads) and stored to part_blk[i]. Basis loads are issued eight vectors at a time
+// (clamped to slot j, whose contribution is masked) so that many loads are in flight per thread.
+// red: (NT / 64) * P doubles of LDS.
+template <typename T, int P, int NT>
 __device__ inline void block_dots(const T* __restrict__ Vr, int n, int j, int r0, int r1, const T* wsrc_lds,
-                                  const T* wsrc_glob, T* wstore, double* part_blk, double (*red)[P]) {
+                                  const T* wsrc_glob, T* wstore, double* part_blk, double* red) {
+  constexpr int RPT = kRowsPerBlock / NT;
   const int tid = threadIdx.x;
   T p[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) p[i] = 0;
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
-    const int r = r0 + q * kBlock + tid;
+  for (int q = 0; q < RPT; ++q) {
+    const int r = r0 + q * NT + tid;
     if (r < r1) {
       const T wv = wsrc_lds ? wsrc_lds[r - r0] : wsrc_glob[r];
       if (wstore) wstore[r] = wv;
@@ -160,68 +55,42 @@ __device__ inline void block_dots(const T* __restrict__ Vr, int n, int j, int r0
   for (int i = 0; i < P; ++i) pd[i] = (double)p[i];
   const int lane = tid & 63, wave = tid >> 6;
   ReduceScatter<P, 32>::run(pd, lane);
-  if (P == 64 || (lane & 1) == 0) red[wave][P == 64 ? lane : (lane >> 1)] = pd[0];
+  if (P == 64 || (lane & 1) == 0) red[wave * P + (P == 64 ? lane : (lane >> 1))] = pd[0];
   __syncthreads();
   if (tid < P && tid <= j) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) s += red[w][tid];
+    for (int w = 0; w < NT / 64; ++w) s += red[w * P + tid];
     part_blk[tid] = s;
   }
 }
 
-// Phase A of step j. Opens by closing step j-1 from its norm partials (every workgroup computes the
-// same beta_{j-1} in the same order; workgroup 0 records it), then w = s_j A Vraw_j and the dots.
-template <typename T, bool HAS_VAL, int L, int P>
-__global__ __launch_bounds__(kBlock) void k_spmv_dots(LzArgs a, int j) {
-  __shared__ T w_lds[kRowsPerBlock];
-  __shared__ int hub_list[kRowsPerBlock];
-  __shared__ int hub_count;
-  __shared__ double red[kWaves][P];
-  __shared__ double red1[kMaxChunks];
-  const Ref ref = resolve(a);
-  const Task tk = a.tasks[ref.task];
-  RState* st = a.state + ref.task;
-  if (st->done) return;
-  double sj;
-  if (j == 0) {
-    sj = st->s[0];
-  } else {
-    const StepClose c = close_step(st, a.npart + tk.part_off / kPartStride, tk.nblk, j - 1, a.eps, red1);
-    if (ref.blk == 0 && threadIdx.x == 0) {
-      st->beta[j - 1] = c.beta;
-      if (c.flags) {
-        st->flags |= c.flags;
-        st->done = 1;
-        st->m_used = j;
-      } else {
-        st->s[j] = 1.0 / c.beta;
-      }
-    }
-    if (c.flags) return;
-    sj = 1.0 / c.beta;
-  }
-  const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
-  T* Vr = (T*)a.V + tk.vec_off;
-  const T* va = HAS_VAL ? (const T*)a.values + tk.nnz_off : nullptr;
-  spmv_rows<T, HAS_VAL, L>(a.row_ptr + tk.rowptr_off, a.col_idx + tk.nnz_off, va, Vr + (size_t)j * n, r0, r1,
-                           a.hub_threshold, sj, w_lds, hub_list, &hub_count, red1);
-  block_dots<T, P>(Vr, n, j, r0, r1, w_lds, nullptr, (T*)a.W + tk.w_off,
-                   a.part + tk.part_off + (size_t)ref.blk * kPartStride, red);
-}
-
-// Second Gram-Schmidt pass: dots of the once-orthogonalised vector (stored in slot j+1).
+// k_dots_step: dot partials of w (written by k_spmv_step) against Vraw_0..j.
 template <typename T, int P>
-__global__ __launch_bounds__(kBlock) void k_dots_again(LzArgs a, int j) {
-  __shared__ double red[kWaves][P];
+__global__ __launch_bounds__(kBlock) void k_dots_step(LzArgs a, int j) {
+  __shared__ double red[kWaves * P];
   const Ref ref = resolve(a);
   const Task tk = a.tasks[ref.task];
   const RState* st = a.state + ref.task;
   if (st->done) return;
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
   const T* Vr = (const T*)a.V + tk.vec_off;
-  block_dots<T, P>(Vr, n, j, r0, r1, nullptr, Vr + (size_t)(j + 1) * n, nullptr,
-                   a.part + tk.part_off + (size_t)ref.blk * kPartStride, red);
+  block_dots<T, P, kBlock>(Vr, n, j, r0, r1, nullptr, (const T*)a.W + tk.w_off, nullptr,
+                           a.part + tk.part_off + (size_t)ref.blk * kPartStride, red);
+}
+
+// Second Gram-Schmidt pass: dots of the once-orthogonalised vector (stored in slot j+1).
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_dots_again(LzArgs a, int j) {
+  __shared__ double red[kWaves * P];
+  const Ref ref = resolve(a);
+  const Task tk = a.tasks[ref.task];
+  const RState* st = a.state + ref.task;
+  if (st->done) return;
+  const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
+  const T* Vr = (const T*)a.V + tk.vec_off;
+  block_dots<T, P, kBlock>(Vr, n, j, r0, r1, nullptr, Vr + (size_t)(j + 1) * n, nullptr,
+                           a.part + tk.part_off + (size_t)ref.blk * kPartStride, red);
 }
 
 // Phase B of step j: every workgroup reduces the dot partials of all workgroups of its realization
@@ -256,7 +125,15 @@ __global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, 
       const double si = st->s[tid];
       const double h = si * t;
       coef = h * si;
-      if (tid == j && ref.blk == 0) st->alpha[j] = second ? st->alpha[j] + h : h;
+      if (tid == j && ref.blk == 0) {
+        const double alpha = second ? st->alpha[j] + h : h;
+        st->alpha[j] = alpha;
+        if (final_pass) {  // breakdown reference of step j: max(|alpha_0..j|, beta_0..j-1)
+          double sc = fabs(alpha);
+          if (j > 0) sc = fmax(sc, fmax(st->scal[j - 1], st->beta[j - 1]));
+          st->scal[j] = isfinite(alpha) ? sc : alpha;
+        }
+      }
     }
     cs[tid] = coef;
   }
@@ -287,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, 
     }
   }
   if (!final_pass) return;
-  nrm = block_sum(nrm, red);
+  nrm = block_sum<kBlock>(nrm, red);
   if (tid == 0) a.npart[tk.part_off / kPartStride + ref.blk] = nrm;
 }
 
@@ -304,7 +181,6 @@ __global__ __launch_bounds__(kBlock) void k_start(LzArgs a) {
     st->s[0] = 1.0 / st->beta0;
     st->theta = 0.0;
     st->est = 0.0;
-    st->scale = 0.0;
     st->m_used = 0;
     st->flags = 0;
     st->done = 0;
@@ -397,60 +273,10 @@ __global__ void k_blkmap(const Task* tasks, int32_t* blkmap) {
   for (int b = threadIdx.x; b < tk.nblk; b += blockDim.x) blkmap[tk.blk_begin + b] = (int32_t)blockIdx.x;
 }
 
-template <typename T, bool HAS_VAL, int L>
-__global__ __launch_bounds__(kBlock) void k_spmv(int32_t n, const int32_t* rp, const int32_t* ci, const T* va,
-                                                  const T* x, T* y, int hub) {
-  __shared__ T w_lds[kRowsPerBlock];
-  __shared__ int hub_list[kRowsPerBlock];
-  __shared__ int hub_count;
-  __shared__ double red1[kWaves];
-  const int r0 = blockIdx.x * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
-  spmv_rows<T, HAS_VAL, L>(rp, ci, va, x, r0, r1, hub, 1.0, w_lds, hub_list, &hub_count, red1);
-  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) y[r] = w_lds[r - r0];
-}
-
-template <typename T, bool HAS_VAL, int L, int P>
-hipError_t spmv_dots_t(int j, const LzArgs& a, int64_t nb, hipStream_t s) {
-  hipLaunchKernelGGL((k_spmv_dots<T, HAS_VAL, L, P>), dim3((unsigned)nb), dim3(kBlock), 0, s, a, j);
+template <typename T, int P>
+hipError_t dots_step_t(int j, const LzArgs& a, int64_t nb, hipStream_t s) {
+  hipLaunchKernelGGL((k_dots_step<T, P>), dim3((unsigned)nb), dim3(kBlock), 0, s, a, j);
   return hipGetLastError();
-}
-
-template <typename T, bool HAS_VAL, int P>
-hipError_t spmv_dots_l(int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
-  switch (lanes) {
-    case 4: return spmv_dots_t<T, HAS_VAL, 4, P>(j, a, nb, s);
-    case 8: return spmv_dots_t<T, HAS_VAL, 8, P>(j, a, nb, s);
-    case 16: return spmv_dots_t<T, HAS_VAL, 16, P>(j, a, nb, s);
-    case 32: return spmv_dots_t<T, HAS_VAL, 32, P>(j, a, nb, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <typename T, bool HAS_VAL>
-hipError_t spmv_dots_p(int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
-  return (j + 1 <= 32) ? spmv_dots_l<T, HAS_VAL, 32>(lanes, j, a, nb, s)
-                       : spmv_dots_l<T, HAS_VAL, 64>(lanes, j, a, nb, s);
-}
-
-template <typename T, bool HAS_VAL, int L>
-hipError_t spmv_t(int32_t n, const int32_t* rp, const int32_t* ci, const void* va, const void* x, void* y,
-                  int hub, hipStream_t s) {
-  const int nb = (n + kRowsPerBlock - 1) / kRowsPerBlock;
-  hipLaunchKernelGGL((k_spmv<T, HAS_VAL, L>), dim3(nb), dim3(kBlock), 0, s, n, rp, ci, (const T*)va,
-                     (const T*)x, (T*)y, hub);
-  return hipGetLastError();
-}
-
-template <typename T, bool HAS_VAL>
-hipError_t spmv_l(int lanes, int32_t n, const int32_t* rp, const int32_t* ci, const void* va, const void* x,
-                  void* y, int hub, hipStream_t s) {
-  switch (lanes) {
-    case 4: return spmv_t<T, HAS_VAL, 4>(n, rp, ci, va, x, y, hub, s);
-    case 8: return spmv_t<T, HAS_VAL, 8>(n, rp, ci, va, x, y, hub, s);
-    case 16: return spmv_t<T, HAS_VAL, 16>(n, rp, ci, va, x, y, hub, s);
-    case 32: return spmv_t<T, HAS_VAL, 32>(n, rp, ci, va, x, y, hub, s);
-    default: return hipErrorInvalidValue;
-  }
 }
 
 }  // namespace
@@ -468,10 +294,16 @@ hipError_t launch_start(int dtype, const LzArgs& a, int64_t nb, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_spmv_dots(int dtype, bool has_val, int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
-  if (dtype == EBTC_F64)
-    return has_val ? spmv_dots_p<double, true>(lanes, j, a, nb, s) : spmv_dots_p<double, false>(lanes, j, a, nb, s);
-  return has_val ? spmv_dots_p<float, true>(lanes, j, a, nb, s) : spmv_dots_p<float, false>(lanes, j, a, nb, s);
+hipError_t launch_dots_step(int dtype, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
+  const dim3 g((unsigned)nb), b(kBlock);
+  if (dtype == EBTC_F64) {
+    if (j + 1 <= 32) hipLaunchKernelGGL((k_dots_step<double, 32>), g, b, 0, s, a, j);
+    else hipLaunchKernelGGL((k_dots_step<double, 64>), g, b, 0, s, a, j);
+  } else {
+    if (j + 1 <= 32) hipLaunchKernelGGL((k_dots_step<float, 32>), g, b, 0, s, a, j);
+    else hipLaunchKernelGGL((k_dots_step<float, 64>), g, b, 0, s, a, j);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_dots_again(int dtype, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
@@ -516,15 +348,6 @@ hipError_t launch_sum(int dtype, const GraphInfo* graphs, int32_t G, int32_t max
   else
     hipLaunchKernelGGL(k_sum<float>, g, b, 0, s, graphs, tasks, state, (const float*)U, (float*)scores, log_scale);
   return hipGetLastError();
-}
-
-hipError_t launch_spmv(int dtype, bool has_val, int lanes, int hub, int32_t n, const int32_t* rp,
-                       const int32_t* ci, const void* va, const void* x, void* y, hipStream_t s) {
-  if (dtype == EBTC_F64)
-    return has_val ? spmv_l<double, true>(lanes, n, rp, ci, va, x, y, hub, s)
-                   : spmv_l<double, false>(lanes, n, rp, ci, va, x, y, hub, s);
-  return has_val ? spmv_l<float, true>(lanes, n, rp, ci, va, x, y, hub, s)
-                 : spmv_l<float, false>(lanes, n, rp, ci, va, x, y, hub, s);
 }
 
 }  // namespace ebtc

@@ -28,11 +28,6 @@ __device__ inline double wave_min(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
   return v;
 }
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 // Number of eigenvalues of the tridiagonal (a, b) below x.
 __device__ inline int sturm_count(const double* a, const double* b, int k, double x, double pivmin) {

@@ -120,7 +120,7 @@ def align(x):
 
 def expected_ws(G, nreal, n, m_slots, es, rstate_bytes):
     R = sum(nreal)
-    blocks = sum(((ng + 1023) // 1024) * nr for ng, nr in zip(n, nreal))
+    blocks = sum(((ng + 2047) // 2048) * nr for ng, nr in zip(n, nreal))
     rows = sum(ng * nr for ng, nr in zip(n, nreal))
     off = align(64 * R)
     off = align(off + 24 * G)
@@ -134,7 +134,7 @@ def expected_ws(G, nreal, n, m_slots, es, rstate_bytes):
     return off
 
 
-RSTATE_BYTES = 8 * (64 + 64 + 65 + 65 + 64 + 4) + 4 * 4
+RSTATE_BYTES = 8 * (64 + 64 + 65 + 65 + 64 + 64 + 3) + 4 * 4
 
 
 @pytest.mark.parametrize("dtype,es", [(A.EBTC_F32, 4), (A.EBTC_F64, 8)])
@@ -155,6 +155,7 @@ def test_plan_workspace_arithmetic(dtype, es):
     (dict(m=65), "m must be"), (dict(m=-1), "m must be"), (dict(m=0, m_max=0), "m_max"),
     (dict(m=0, tol=0.0), "tol"), (dict(reorth=3), "reorth"), (dict(schedule=9), "schedule"),
     (dict(lanes_per_row=5), "lanes_per_row"), (dict(hub_threshold=-1), "hub_threshold"),
+    (dict(seg_len=-3), "seg_len"),
 ])
 def test_plan_rejects_bad_opts(kw, text):
     d, keep = make_desc()
@@ -194,10 +195,11 @@ def test_topk_rejects_bad_k():
 
 def test_component_entry_points_validate():
     L = A.lib()
-    assert L.ebtc_spmv(5, 10, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV + 64, 0, 0, None) == A.EBTC_EINVAL
-    assert L.ebtc_spmv(0, 0, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV + 64, 0, 0, None) == A.EBTC_EINVAL
-    assert L.ebtc_spmv(0, 10, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV, 0, 0, None) == A.EBTC_EINVAL
-    assert L.ebtc_spmv(0, 10, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV + 64, 6, 0, None) == A.EBTC_EINVAL
+    assert L.ebtc_spmv(5, 10, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV + 64, 0, 0, 0, None) == A.EBTC_EINVAL
+    assert L.ebtc_spmv(0, 0, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV + 64, 0, 0, 0, None) == A.EBTC_EINVAL
+    assert L.ebtc_spmv(0, 10, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV, 0, 0, 0, None) == A.EBTC_EINVAL
+    assert L.ebtc_spmv(0, 10, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV + 64, 6, 0, 0, None)
+    assert L.ebtc_spmv(0, 10, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV + 64, 0, 0, -2, None) == A.EBTC_EINVAL == A.EBTC_EINVAL
     assert L.ebtc_tridiag_expv(1, 65, FAKE_DEV, FAKE_DEV, FAKE_DEV, FAKE_DEV, 1, None) == A.EBTC_EINVAL
     assert L.ebtc_tridiag_expv(-1, 5, FAKE_DEV, FAKE_DEV, FAKE_DEV, FAKE_DEV, 1, None) == A.EBTC_EINVAL
     assert L.ebtc_tridiag_expv(0, 5, None, None, None, None, 1, None) == A.EBTC_OK

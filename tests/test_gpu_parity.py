@@ -103,7 +103,7 @@ def check_against_oracle(hb, out, b, m, tol_key, K=None, tol=0.0, m_max=60, reor
 
 # ------------------------------------------------------------------ component: SpMV
 
-@pytest.mark.parametrize("lanes", [4, 8, 16, 32])
+@pytest.mark.parametrize("lanes", [0, 4, 8, 16, 32])
 @pytest.mark.parametrize("hub", [0, 3])
 def test_spmv_fp64_exact_on_patterns(gpu_lib, lanes, hub):
     torch = torch_mod()
@@ -116,6 +116,45 @@ def test_spmv_fp64_exact_on_patterns(gpu_lib, lanes, hub):
     y = api().spmv(torch.as_tensor(rp).to(dev), torch.as_tensor(ci).to(dev), None,
                    torch.as_tensor(x).to(dev), lanes=lanes, hub=hub)
     assert np.array_equal(y.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("seg_len", [777, 2500, 5000])
+@pytest.mark.parametrize("lanes,hub", [(4, 0), (8, 40), (16, 0)])
+def test_spmv_staged_fp64_exact(gpu_lib, seg_len, lanes, hub):
+    # LDS-staged gathers: several column segments, ragged last segment, hub rows (BA degrees)
+    torch = torch_mod()
+    n = 5000
+    keys = G.ba_keys(n, 4, G.rng_for(11, 2, 1))
+    rp, ci = G.csr_from_keys(keys, n)
+    x = np.random.default_rng(3).integers(-8, 9, size=n).astype(np.float64)
+    ref = odense.csr_to_scipy(n, rp, ci) @ x
+    dev = torch.device("cuda")
+    y = api().spmv(torch.as_tensor(rp).to(dev), torch.as_tensor(ci).to(dev), None,
+                   torch.as_tensor(x).to(dev), lanes=lanes, hub=hub, seg_len=seg_len)
+    assert np.array_equal(y.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_spmv_stream_hub_rows(gpu_lib, dtype):
+    # rows longer than the stream kernel's LDS capacity (3072 / 6144 products) and chunked ranges
+    torch = torch_mod()
+    n = 20000
+    rng = np.random.default_rng(9)
+    keys = G.er_keys(n, 6.0 / (n - 1), G.rng_for(11, 3, 1))
+    hubs = np.array([5, 700, 701, 19999])
+    extra = [G.canon(np.full(7000, h), rng.choice(n, 7000, replace=False), n) for h in hubs]
+    keys = np.unique(np.concatenate([keys] + extra))
+    keys = keys[(keys // n) != (keys % n)]
+    rp, ci = G.csr_from_keys(keys, n)
+    dt = np.float64 if dtype == "f64" else np.float32
+    x = rng.integers(-8, 9, size=n).astype(dt)
+    ref = odense.csr_to_scipy(n, rp, ci) @ x.astype(np.float64)
+    dev = torch.device("cuda")
+    y = api().spmv(torch.as_tensor(rp).to(dev), torch.as_tensor(ci).to(dev), None, torch.as_tensor(x).to(dev))
+    if dtype == "f64":
+        assert np.array_equal(y.cpu().numpy(), ref)
+    else:  # integer sums below 2^24 are exact in FP32 as well
+        assert np.array_equal(y.cpu().numpy().astype(np.float64), ref)
 
 
 @pytest.mark.parametrize("weighted", [False, True])
@@ -241,6 +280,22 @@ def test_schedules_agree_bitwise(gpu_lib):
         outs.append(o.scores.cpu().numpy().copy())
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])  # fixed-order reductions: deterministic across schedules
+
+
+@pytest.mark.parametrize("seg_len,lanes", [(-1, 0), (-1, 8), (3001, 0), (9000, 0)])
+def test_gather_modes_agree(gpu_lib, seg_len, lanes):
+    # staged (auto: one segment) vs direct gathers (-1) vs several staged segments: same step arithmetic
+    # up to the order of the per-row sums
+    torch = torch_mod()
+    w = C.scaled(C.workload(1), n=9000, N=3)
+    hb = C.build(w)
+    b = api().Batch.from_host(hb)
+    ref = b.scores(m=w.m)
+    alt = b.scores(m=w.m, seg_len=seg_len, lanes=lanes)
+    torch.cuda.synchronize()
+    r, a = ref.scores.cpu().numpy(), alt.scores.cpu().numpy()
+    assert np.max(np.abs(r - a)) <= 1e-6 * np.max(np.abs(r))
+    check_against_oracle(hb, alt, b, w.m, "f32", K=50)
 
 
 def test_hipgraph_replays_match_eager(gpu_lib):
