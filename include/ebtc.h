@@ -142,6 +142,28 @@ int ebtc_plan(ebtc_batch* batch, const ebtc_opts* opts, size_t* ws_bytes, size_t
 int ebtc_scores(ebtc_batch* batch, const ebtc_opts* opts, void* ws, size_t ws_bytes, void* scores_out,
                 double* log_scale_out, void* ckpt_out, ebtc_diag* diag_out, void* stream);
 
+/* ---------------------------------------------------------------- adjoint                        */
+/* Workspace bytes for ebtc_scores_backward (host-only). EBTC_ENOTSUPPORTED when the Krylov
+ * dimension (m, or m_max in adaptive mode) exceeds 40. */
+int ebtc_plan_backward(ebtc_batch* batch, const ebtc_opts* opts, size_t* ws_bytes);
+/* Gradient of L = sum_g <grad_scores_g, S~_g> with respect to every stored CSR entry, with the
+ * log-scales held fixed, asynchronous on `stream`:
+ *   grad_values[e] = dL/dA_k(i, j) for entry e = (i, j) of realization k,
+ *                  ~ e^{-Sigma_g} [int_0^1 e^{sA} g 1^T e^{(1-s)A} ds]_{ij}
+ * (Frechet derivative of exp(A) 1, eq. (4), through the sum of eq. (5)). An undirected edge weight
+ * that feeds both (i, j) and (j, i) has gradient grad(i, j) + grad(j, i); tying is the caller's.
+ * Both exponential actions use their Lanczos approximations: the forward basis is recomputed from
+ * scratch with the forward's kernels (bitwise the same: every reduction runs in a fixed order), an
+ * adjoint Lanczos starts at the cotangent, the m x m coupling comes from the upper-right block of an
+ * FP64 block exponential, and an SDDMM over the CSR pattern forms the entries.
+ *   opts         the options of the forward call
+ *   log_scale    device [G] double, the forward's Sigma_g
+ *   grad_scores  device [sum_g n_g] of dtype, the cotangent of the scores
+ *   grad_values  device [nnz_off[R]] of dtype, written
+ *   ws, ws_bytes device workspace of at least ebtc_plan_backward's size */
+int ebtc_scores_backward(ebtc_batch* batch, const ebtc_opts* opts, const double* log_scale, const void* grad_scores,
+                         void* grad_values, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- selection                      */
 /* Device workspace bytes for ebtc_topk (host-only). */
 int ebtc_topk_ws_bytes(ebtc_batch* batch, size_t* ws_bytes);

@@ -23,7 +23,8 @@ CKPT_DOUBLES = 2 * M_LIMIT + 4
 EXPORTED = [
     "ebtc_version", "ebtc_status_str", "ebtc_last_error", "ebtc_default_opts", "ebtc_batch_create",
     "ebtc_batch_destroy", "ebtc_plan", "ebtc_scores", "ebtc_topk_ws_bytes", "ebtc_topk", "ebtc_spmv",
-    "ebtc_tridiag_expv", "ebtc_validate_ws_bytes", "ebtc_validate", "ebtc_profile_phases",
+    "ebtc_tridiag_expv", "ebtc_validate_ws_bytes", "ebtc_validate", "ebtc_profile_phases", "ebtc_plan_backward",
+    "ebtc_scores_backward",
 ]
 PHASES = ["start", "spmv", "dots", "update", "tridiag", "combine", "sum"]
 
@@ -82,6 +83,8 @@ def lib() -> ctypes.CDLL:
         "ebtc_validate_ws_bytes": (c_int, [vp, POINTER(sz)]),
         "ebtc_validate": (c_int, [vp, vp, sz, POINTER(c_int64), vp]),
         "ebtc_profile_phases": (c_int, [vp, POINTER(Opts), vp, sz, vp, vp, POINTER(c_double), POINTER(c_int64), vp]),
+        "ebtc_plan_backward": (c_int, [vp, POINTER(Opts), POINTER(sz)]),
+        "ebtc_scores_backward": (c_int, [vp, POINTER(Opts), vp, vp, vp, vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -164,6 +164,19 @@ class Batch:
                                   _vp(idx), _vp(val), _vp(wst), ws.value, current_stream()))
         return idx[:tot], val[:tot]
 
+    def scores_backward(self, log_scale: torch.Tensor, grad_scores: torch.Tensor, **kw) -> torch.Tensor:
+        """Gradient of sum_g <grad_scores_g, S~_g> with respect to every stored CSR entry (log-scales
+        fixed); `kw` are the options of the forward call."""
+        opts = make_opts(**kw)
+        ws = ctypes.c_size_t()
+        A.check(A.lib().ebtc_plan_backward(self.handle, ctypes.byref(opts), ctypes.byref(ws)))
+        wst = torch.empty(max(1, ws.value), dtype=torch.uint8, device=self.device)
+        g = grad_scores.to(self.tdtype).contiguous()
+        out = torch.empty(int(self.nnz_off[-1]), dtype=self.tdtype, device=self.device)
+        A.check(A.lib().ebtc_scores_backward(self.handle, ctypes.byref(opts), _vp(log_scale), _vp(g), _vp(out),
+                                             _vp(wst), ws.value, current_stream()))
+        return out
+
     def validate(self) -> int:
         ws = ctypes.c_size_t()
         A.check(A.lib().ebtc_validate_ws_bytes(self.handle, ctypes.byref(ws)))
@@ -190,3 +203,26 @@ def tridiag_expv(alpha: torch.Tensor, beta: torch.Tensor, shift: bool = True) ->
     th = torch.empty(count, dtype=torch.float64, device=alpha.device)
     A.check(A.lib().ebtc_tridiag_expv(count, k, _vp(alpha), _vp(beta), _vp(y), _vp(th), int(shift), current_stream()))
     return y, th
+
+
+class Communicability(torch.autograd.Function):
+    """(S~, log_scale) = Communicability.apply(values, batch, opts) with values the batch's edge-weight
+    tensor (the very tensor the batch was built on). Backward gives d<grad, S~>/d values through the
+    hand-written adjoint (log_scale is treated as a constant)."""
+
+    @staticmethod
+    def forward(ctx, values, batch, opts):
+        if batch.values is None or values.data_ptr() != batch.values.data_ptr():
+            raise ValueError("values must be the tensor the batch was created on")
+        out = batch.scores(diag=False, **opts)
+        ctx.batch = batch
+        ctx.opts = dict(opts)
+        ctx.save_for_backward(out.log_scale)
+        ctx.mark_non_differentiable(out.log_scale)
+        return out.scores, out.log_scale
+
+    @staticmethod
+    def backward(ctx, grad_scores, _grad_log_scale):
+        (log_scale,) = ctx.saved_tensors
+        g = ctx.batch.scores_backward(log_scale, grad_scores, **ctx.opts)
+        return g, None, None

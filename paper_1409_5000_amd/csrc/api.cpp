@@ -262,10 +262,10 @@ struct Prof {
 
 // Lanczos steps for the launches described by (a, nblocks); a.blkmap / a.single_task select the scope.
 int run_steps(const ebtc_batch* b, const ebtc_opts* o, const LzArgs& a, int64_t nblocks, int64_t first,
-              int64_t count, int lanes, hipStream_t s, Prof* prof) {
+              int64_t count, int lanes, hipStream_t s, Prof* prof, bool with_start = true) {
   const bool has_val = b->values != nullptr;
   const int steps = o->m > 0 ? o->m : o->m_max;
-  EBTC_PHASE(prof, EBTC_PHASE_START, launch_start(b->dtype, a, nblocks, s));
+  if (with_start) EBTC_PHASE(prof, EBTC_PHASE_START, launch_start(b->dtype, a, nblocks, s));
   for (int j = 0; j < steps; ++j) {
     EBTC_PHASE(prof, EBTC_PHASE_SPMV, launch_spmv_step(b->dtype, has_val, lanes, j, a, nblocks, s));
     EBTC_PHASE(prof, EBTC_PHASE_DOTS, launch_dots_step(b->dtype, j, a, nblocks, s));
@@ -317,6 +317,48 @@ int enqueue_plain(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, 
   const int32_t maxblk = (b->n_max + kRowsPerBlock - 1) / kRowsPerBlock;
   EBTC_LAUNCH(launch_sum(b->dtype, (const GraphInfo*)(ws + L.off_graphs), b->G, maxblk, a.tasks, a.state, a.U, scores,
                          log_scale, s));
+  return EBTC_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Backward workspace: the forward layout (recomputed forward), then the adjoint Lanczos state and
+// basis, the per-realization block exponentials and the node-major Z and normalised V.
+struct BwdLayout {
+  Layout fwd;
+  size_t off_astate = 0, off_aV = 0, off_X = 0, off_Z = 0, off_Vn = 0, total = 0;
+  int ld = 0;
+};
+
+BwdLayout make_bwd_layout(const ebtc_batch* b, const ebtc_opts* o) {
+  BwdLayout B;
+  B.fwd = make_layout(b, o);
+  const size_t es = elem_size(b->dtype);
+  const int steps = o->m > 0 ? o->m : o->m_max;
+  B.ld = (steps + 7) / 8 * 8;
+  size_t off = B.fwd.total;
+  B.off_astate = off;
+  off = align_up(off + sizeof(RState) * b->R);
+  B.off_aV = off;
+  off = align_up(off + es * (size_t)B.fwd.m_slots * b->total_rows);
+  B.off_X = off;
+  off = align_up(off + sizeof(double) * kMLimit * kMLimit * b->R);
+  B.off_Z = off;
+  off = align_up(off + es * (size_t)B.ld * b->total_rows);
+  B.off_Vn = off;
+  off = align_up(off + es * (size_t)B.ld * b->total_rows);
+  B.total = off;
+  return B;
+}
+
+int check_bwd_opts(const ebtc_opts* o) {
+  int rc = check_opts(o);
+  if (rc) return rc;
+  const int steps = o->m > 0 ? o->m : o->m_max;
+  if (steps > adjoint_max_m())
+    return fail(EBTC_ENOTSUPPORTED, "the adjoint supports Krylov dimensions up to " + std::to_string(adjoint_max_m()));
   return EBTC_OK;
 }
 
@@ -551,6 +593,58 @@ int ebtc_profile_phases(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_b
     phase_ms[r.phase] += ms;
     phase_launches[r.phase] += 1;
   }
+  return EBTC_OK;
+}
+
+int ebtc_plan_backward(ebtc_batch* b, const ebtc_opts* o, size_t* ws_bytes) {
+  g_err.clear();
+  if (!b || !ws_bytes) return fail(EBTC_EINVAL, "NULL batch or output");
+  int rc = check_bwd_opts(o);
+  if (rc) return rc;
+  *ws_bytes = make_bwd_layout(b, o).total;
+  return EBTC_OK;
+}
+
+int ebtc_scores_backward(ebtc_batch* b, const ebtc_opts* o, const double* log_scale, const void* grad_scores,
+                         void* grad_values, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!b) return fail(EBTC_EINVAL, "NULL batch");
+  int rc = check_bwd_opts(o);
+  if (rc) return rc;
+  if (!log_scale || !grad_scores || !grad_values || !ws)
+    return fail(EBTC_EINVAL, "NULL log_scale, grad_scores, grad_values or workspace");
+  const BwdLayout B = make_bwd_layout(b, o);
+  if (ws_bytes < B.total)
+    return fail(EBTC_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(B.total));
+  if (((uintptr_t)ws & 255) != 0) return fail(EBTC_EINVAL, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  const SpmvPlan sp = spmv_plan(b, o);
+  if (sp.seglen > 0) EBTC_HIP(prepare_staged_kernels());
+  char* w = (char*)ws;
+  rc = upload_tables(b, w, B.fwd, s);
+  if (rc) return rc;
+  // 1. forward recomputation (same kernels and order as ebtc_scores: bitwise the same basis)
+  LzArgs fa = make_args(b, o, w, B.fwd, sp.hub);
+  EBTC_LAUNCH(launch_blkmap(fa.tasks, b->R, (int32_t*)(w + B.fwd.off_blkmap), s));
+  rc = run_steps(b, o, fa, B.fwd.total_blocks, 0, b->R, sp.lanes, s, nullptr);
+  if (rc) return rc;
+  const int steps = o->m > 0 ? o->m : o->m_max;
+  EBTC_LAUNCH(launch_tridiag_state(fa, 0, b->R, 0, 0, steps, o->shift, o->tol, nullptr, nullptr, s));
+  // 2. adjoint Lanczos started at the cotangent (shares W and the partial-sum arenas)
+  LzArgs aa = fa;
+  aa.state = (RState*)(w + B.off_astate);
+  aa.V = w + B.off_aV;
+  EBTC_LAUNCH(launch_start_vec(b->dtype, aa, (const GraphInfo*)(w + B.fwd.off_graphs), grad_scores,
+                               B.fwd.total_blocks, s));
+  EBTC_LAUNCH(launch_start_norm(aa, b->R, s));
+  rc = run_steps(b, o, aa, B.fwd.total_blocks, 0, b->R, sp.lanes, s, nullptr, false);
+  if (rc) return rc;
+  EBTC_LAUNCH(launch_tridiag_state(aa, 0, b->R, 0, 0, steps, 1, o->tol, nullptr, nullptr, s));
+  // 3. block exponential, 4. node-major Z and V, 5. SDDMM on the pattern
+  double* X = (double*)(w + B.off_X);
+  EBTC_LAUNCH(launch_block_exp(fa.state, aa.state, fa.tasks, log_scale, X, b->R, s));
+  EBTC_LAUNCH(launch_build_zv(b->dtype, fa, aa, X, w + B.off_Z, w + B.off_Vn, B.ld, B.fwd.total_blocks, s));
+  EBTC_LAUNCH(launch_sddmm(b->dtype, B.ld, fa, w + B.off_Z, w + B.off_Vn, grad_values, B.fwd.total_blocks, s));
   return EBTC_OK;
 }
 

@@ -122,6 +122,18 @@ hipError_t launch_topk(int dtype, const GraphInfo* graphs, int32_t G, const int3
 hipError_t launch_validate(const int32_t* row_ptr, const int32_t* col_idx, const Task* tasks, const int64_t* nnz,
                            int64_t R, int32_t max_n, int32_t* bad, hipStream_t s);
 
+// ---- launchers (k_adjoint.hip)
+int adjoint_max_m();
+hipError_t launch_start_vec(int dtype, const LzArgs& a, const GraphInfo* graphs, const void* g, int64_t nblocks,
+                            hipStream_t s);
+hipError_t launch_start_norm(const LzArgs& a, int64_t R, hipStream_t s);
+hipError_t launch_block_exp(const RState* fwd, const RState* adj, const Task* tasks, const double* log_scale,
+                            double* xout, int64_t R, hipStream_t s);
+hipError_t launch_build_zv(int dtype, const LzArgs& fwd, const LzArgs& adj, const double* x, void* Z, void* Vn,
+                           int ld, int64_t nblocks, hipStream_t s);
+hipError_t launch_sddmm(int dtype, int ld, const LzArgs& fwd, const void* Z, const void* Vn, void* grad,
+                        int64_t nblocks, hipStream_t s);
+
 // checkpoint layout per realization (doubles): alpha[kMLimit], beta[kMLimit], theta, beta0, m_used, flags
 constexpr int kCkptDoubles = 2 * kMLimit + 4;
 

@@ -141,6 +141,19 @@ __global__ __launch_bounds__(64) void k_tridiag_state(LzArgs args, int64_t first
       }
       return;
     }
+  } else if (st->done && st->m_used < 1) {
+    // nothing to expand (an adjoint started at a zero cotangent): empty result
+    if (lane == 0) {
+      st->theta = 0.0;
+      st->est = 0.0;
+      if (diag) {
+        diag[r].m_used = 0;
+        diag[r].flags = st->flags;
+        diag[r].theta = 0.0;
+        diag[r].est = 0.0;
+      }
+    }
+    return;
   } else if (st->done) {
     k = st->m_used;
     beta_last = st->beta[k - 1];

@@ -1,0 +1,192 @@
+"""GPU parity of the adjoint (edge-weight gradient of the summed scores) against the FP64 oracle.
+
+Gradient of L = <g, S~> (log-scale fixed) per stored entry: e^{-Sigma} G_ij with
+G = int_0^1 e^{sA} g 1^T e^{(1-s)A} ds. Checked against the dense Van Loan block exponential
+(FP64 mode: 1e-9 normwise), dense Van Loan at n=500 in FP32 (1e-4 normwise), central differences of
+the FP64 oracle Lanczos on sampled undirected edges (FP32), the Euler identity, and autograd.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from fixtures import configs as C
+from oracle import dense as odense, gradient as ograd, lanczos as olanczos
+from tests import graphs_small as gs
+from tests.test_gpu_parity import DenseBatch
+
+pytestmark = pytest.mark.gpu
+
+
+def api():
+    from paper_1409_5000_amd import api as _api
+    return _api
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+def dense_reference(hb, b, g_blocks, log_scale):
+    """Per-entry reference gradient e^{-Sigma} G_ij from the dense Van Loan route (shifted by lambda_max)."""
+    ref = np.empty(int(hb.nnz_off[-1]))
+    for r in range(hb.R):
+        n, rp, ci, v = hb.csr(r)
+        A = odense.csr_to_scipy(n, rp, ci, v).toarray()
+        gi = int(hb.graph_of[r])
+        th = float(np.linalg.eigvalsh(A)[-1])
+        G = ograd.grad_vanloan(A - th * np.eye(n), g_blocks[gi]) * np.exp(th - log_scale[gi])
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        ref[hb.nnz_off[r]:hb.nnz_off[r + 1]] = G[rows, ci]
+    return ref
+
+
+def weighted_dense_batch(graphs, dtype, seed=0):
+    hb = DenseBatch(graphs, dtype, weighted=True)
+    rng = np.random.default_rng(seed)
+    vals = np.empty(hb.col_idx.size)
+    for r in range(hb.R):   # symmetric weights in (0.5, 1.5)
+        n, rp, ci, _ = hb.csr(r)
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        W = np.triu(rng.uniform(0.5, 1.5, (n, n)), 1)
+        W = W + W.T
+        vals[hb.nnz_off[r]:hb.nnz_off[r + 1]] = W[rows, ci]
+    hb.values = vals.astype(hb.dtype)
+    return hb
+
+
+def test_adjoint_fp64_vs_dense_vanloan(gpu_lib):
+    torch = torch_mod()
+    graphs = [[gs.random_graph(120, 0.08, 1), gs.random_graph(120, 0.1, 2)], [gs.random_graph(90, 0.12, 3)]]
+    hb = weighted_dense_batch(graphs, "f64", seed=4)
+    b = api().Batch.from_host(hb)
+    out = b.scores(m=40)
+    rng = np.random.default_rng(7)
+    g_blocks = [rng.normal(size=int(n)) for n in hb.n]
+    gt = torch.as_tensor(np.concatenate(g_blocks)).to("cuda")
+    grad = b.scores_backward(out.log_scale, gt, m=40)
+    torch.cuda.synchronize()
+    ref = dense_reference(hb, b, g_blocks, out.log_scale.cpu().numpy())
+    got = grad.cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-9 * np.max(np.abs(ref))
+
+
+def test_adjoint_fp32_n500_vs_dense(gpu_lib):
+    # a fresh instance of the differentiation recipe at n=500 (degree 16, 40-node target, m=30)
+    torch = torch_mod()
+    w = C.scaled(C.workload(3), n=500, N=2)
+    hb = C.build(w)
+    b = api().Batch.from_host(hb)
+    out = b.scores(m=w.m)
+    g = np.zeros(500)
+    g[b_targets(hb)] = 1.0   # loss = sum of the summed scores over the target nodes
+    grad = b.scores_backward(out.log_scale, torch.as_tensor(g).to("cuda"), m=w.m)
+    torch.cuda.synchronize()
+    ref = dense_reference(hb, b, [g], out.log_scale.cpu().numpy())
+    got = grad.double().cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref))
+
+
+def b_targets(hb, gi=0):
+    return np.asarray(hb.targets[gi], dtype=np.int64)
+
+
+def _fd_job(args):
+    hb, r, i, j, h, gvec, sigma, m = args
+    n, rp, ci, v = hb.csr(r)
+    A = odense.csr_to_scipy(n, rp, ci, v).tolil()
+    vals = []
+    for sgn in (1.0, -1.0):
+        B = A.copy()
+        B[i, j] = B[i, j] + sgn * h
+        B[j, i] = B[j, i] + sgn * h
+        res = olanczos.lanczos_expv(B.tocsr(), m=m)
+        vals.append(np.exp(res.theta - sigma) * float(gvec @ res.u))
+    return (vals[0] - vals[1]) / (2 * h)
+
+
+def fd_check(hb, b, out, grad, m, nedges, seed, tol_rel, tol_abs_frac, workers=8):
+    import multiprocessing as mp
+    rng = np.random.default_rng(seed)
+    sigma = float(out.log_scale.cpu().numpy()[0])
+    g = np.zeros(int(hb.n[0]))
+    g[b_targets(hb)] = 1.0
+    jobs, gpu_vals = [], []
+    gpu = grad.double().cpu().numpy()
+    for _ in range(nedges):
+        r = int(rng.integers(0, hb.R))
+        n, rp, ci, _ = hb.csr(r)
+        e = int(rng.integers(0, ci.size))
+        i = int(np.searchsorted(rp, e, side="right") - 1)
+        j = int(ci[e])
+        # entry (j, i) of the same realization
+        e2 = int(rp[j] + np.searchsorted(ci[rp[j]:rp[j + 1]], i))
+        gpu_vals.append(gpu[hb.nnz_off[r] + e] + gpu[hb.nnz_off[r] + e2])
+        jobs.append((hb, r, i, j, 1e-3, g, sigma, m))
+    with mp.get_context("fork").Pool(workers) as pool:
+        fd = np.array(pool.map(_fd_job, jobs))
+    gpu_vals = np.array(gpu_vals)
+    scale = np.max(np.abs(gpu))
+    err = np.abs(gpu_vals - fd)
+    assert np.all(err <= tol_rel * np.abs(fd) + tol_abs_frac * scale), (err.max(), np.abs(fd).max(), scale)
+
+
+def test_adjoint_fp32_central_differences_reduced(gpu_lib):
+    torch = torch_mod()
+    w = C.scaled(C.workload(3), n=20000, N=4)
+    hb = C.build(w)
+    b = api().Batch.from_host(hb)
+    out = b.scores(m=w.m)
+    g = np.zeros(int(hb.n[0]))
+    g[b_targets(hb)] = 1.0
+    grad = b.scores_backward(out.log_scale, torch.as_tensor(g).to("cuda"), m=w.m)
+    torch.cuda.synchronize()
+    fd_check(hb, b, out, grad, w.m, nedges=24, seed=3, tol_rel=1e-3, tol_abs_frac=1e-5)
+
+
+def test_adjoint_euler_identity_fp32(gpu_lib):
+    # sum_e A_e grad_e = sum_k e^{theta_k - Sigma} g^T A_k u_k (d/dt <g, S~(tA)> at t = 1)
+    torch = torch_mod()
+    w = C.scaled(C.workload(3), n=30000, N=3)
+    hb = C.build(w)
+    b = api().Batch.from_host(hb)
+    out = b.scores(m=w.m)
+    g = np.random.default_rng(1).normal(size=int(hb.n[0]))
+    grad = b.scores_backward(out.log_scale, torch.as_tensor(g).to("cuda"), m=w.m)
+    torch.cuda.synchronize()
+    sigma = float(out.log_scale.cpu().numpy()[0])
+    lhs = float(np.dot(hb.values.astype(np.float64), grad.double().cpu().numpy()))
+    rhs = 0.0
+    for r in range(hb.R):
+        n, rp, ci, v = hb.csr(r)
+        A = odense.csr_to_scipy(n, rp, ci, v)
+        res = olanczos.lanczos_expv(A, m=w.m)
+        rhs += np.exp(res.theta - sigma) * float(g @ (A @ res.u))
+    assert abs(lhs - rhs) <= 1e-5 * abs(rhs)
+
+
+def test_autograd_function_matches_backward(gpu_lib):
+    torch = torch_mod()
+    w = C.scaled(C.workload(3), n=5000, N=2)
+    hb = C.build(w)
+    b = api().Batch.from_host(hb)
+    values = b.values
+    values.requires_grad_(True)
+    scores, log_scale = api().Communicability.apply(values, b, {"m": w.m})
+    loss = scores[torch.as_tensor(b_targets(hb)).to("cuda")].sum()
+    loss.backward()
+    g = torch.zeros(int(hb.n[0]), dtype=torch.float32, device="cuda")
+    g[torch.as_tensor(b_targets(hb)).to("cuda")] = 1.0
+    direct = b.scores_backward(log_scale, g, m=w.m)
+    torch.cuda.synchronize()
+    assert torch.equal(values.grad, direct)
+
+
+def test_zero_cotangent_gives_zero_gradient(gpu_lib):
+    torch = torch_mod()
+    hb = weighted_dense_batch([[gs.random_graph(100, 0.1, 5)]], "f64")
+    b = api().Batch.from_host(hb)
+    out = b.scores(m=20)
+    grad = b.scores_backward(out.log_scale, torch.zeros(100, dtype=torch.float64, device="cuda"), m=20)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(grad).item() == 0
