@@ -92,6 +92,7 @@ def main() -> int:
     ap.add_argument("--workers", type=int, default=0)
     ap.add_argument("--seg-len", type=int, default=0, help="SpMV gather source: 0 auto, -1 direct, >0 LDS segment")
     ap.add_argument("--realizations", type=int, default=0, help="limit realizations per graph (0 = all)")
+    ap.add_argument("--adjoint", action="store_true", help="also time the adjoint (always on for workload 3)")
     ap.add_argument("--profile-run", action="store_true",
                     help="for rocprofv3: one eager batched pass per gather form plus a 1 GiB copy (counter calibration)")
     args = ap.parse_args()
@@ -163,6 +164,32 @@ def main() -> int:
     log(f"batched: {ms_per_step:.3f} ms/step, {value:.1f} realizations/s (events {gpu_ms / args.steps:.3f} ms/step)")
     gpu_scores = run.scores.double().cpu().numpy()
     gpu_ls = run.log_scale.cpu().numpy()
+
+    adjoint = None
+    if args.config == 3 or args.adjoint:
+        # forward alone (scores, no top-K) vs the adjoint (recompute + adjoint Lanczos + SDDMM);
+        # cotangent: the loss sums the summed scores over each graph's target nodes
+        g = torch.zeros(hb.n.sum(), dtype=b.tdtype, device="cuda")
+        for gi in range(int(hb.n.size)):
+            g[int(b.score_off[gi]) + torch.as_tensor(hb.targets[gi]).to("cuda")] = 1.0
+        bwd = b.backward_run(m=m, tol=tol, m_max=m_max, seg_len=args.seg_len)
+        for _ in range(args.warmup):
+            run.launch()
+            bwd.launch(run.log_scale, g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            run.launch()
+        torch.cuda.synchronize()
+        fwd_ms = 1000 * (time.perf_counter() - t0) / args.steps
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            bwd.launch(run.log_scale, g)
+        torch.cuda.synchronize()
+        bwd_ms = 1000 * (time.perf_counter() - t0) / args.steps
+        adjoint = {"forward_ms": round(fwd_ms, 3), "backward_ms": round(bwd_ms, 3),
+                   "backward_over_forward": round(bwd_ms / fwd_ms, 3), "budget": 3.0}
+        log(f"adjoint: forward {fwd_ms:.3f} ms, backward {bwd_ms:.3f} ms, ratio {bwd_ms / fwd_ms:.2f}")
 
     # plain per-realization loop on the same batch
     runp = b.run(m=m, tol=tol, m_max=m_max, schedule="plain", hipgraph=False, diag=False, seg_len=args.seg_len)
@@ -243,6 +270,8 @@ def main() -> int:
         "cpu_baseline": None,
         "parity": None,
     }
+    if adjoint is not None:
+        result["adjoint"] = adjoint
 
     if not args.no_cpu_baseline:
         from oracle import scores as oscores

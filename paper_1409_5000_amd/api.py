@@ -92,6 +92,25 @@ class Run:
         return {p: (ms[i], cnt[i]) for i, p in enumerate(A.PHASES)}
 
 
+class BackwardRun:
+    """Workspace and output for repeated ebtc_scores_backward calls with fixed options."""
+
+    def __init__(self, batch: "Batch", opts: A.Opts):
+        self.batch = batch
+        self.opts = opts
+        ws = ctypes.c_size_t()
+        A.check(A.lib().ebtc_plan_backward(batch.handle, ctypes.byref(opts), ctypes.byref(ws)))
+        self.ws_bytes = ws.value
+        self.ws = torch.empty(max(1, ws.value), dtype=torch.uint8, device=batch.device)
+        self.grad = torch.empty(max(1, int(batch.nnz_off[-1])), dtype=batch.tdtype, device=batch.device)
+
+    def launch(self, log_scale: torch.Tensor, grad_scores: torch.Tensor) -> torch.Tensor:
+        g = grad_scores.to(self.batch.tdtype).contiguous()
+        A.check(A.lib().ebtc_scores_backward(self.batch.handle, ctypes.byref(self.opts), _vp(log_scale), _vp(g),
+                                             _vp(self.grad), _vp(self.ws), self.ws_bytes, current_stream()))
+        return self.grad[: int(self.batch.nnz_off[-1])]
+
+
 class Batch:
     """G graphs x N_g realizations as device CSR arrays (borrowed by the native batch handle)."""
 
@@ -164,18 +183,13 @@ class Batch:
                                   _vp(idx), _vp(val), _vp(wst), ws.value, current_stream()))
         return idx[:tot], val[:tot]
 
+    def backward_run(self, **kw) -> "BackwardRun":
+        return BackwardRun(self, make_opts(**kw))
+
     def scores_backward(self, log_scale: torch.Tensor, grad_scores: torch.Tensor, **kw) -> torch.Tensor:
         """Gradient of sum_g <grad_scores_g, S~_g> with respect to every stored CSR entry (log-scales
         fixed); `kw` are the options of the forward call."""
-        opts = make_opts(**kw)
-        ws = ctypes.c_size_t()
-        A.check(A.lib().ebtc_plan_backward(self.handle, ctypes.byref(opts), ctypes.byref(ws)))
-        wst = torch.empty(max(1, ws.value), dtype=torch.uint8, device=self.device)
-        g = grad_scores.to(self.tdtype).contiguous()
-        out = torch.empty(int(self.nnz_off[-1]), dtype=self.tdtype, device=self.device)
-        A.check(A.lib().ebtc_scores_backward(self.handle, ctypes.byref(opts), _vp(log_scale), _vp(g), _vp(out),
-                                             _vp(wst), ws.value, current_stream()))
-        return out
+        return self.backward_run(**kw).launch(log_scale, grad_scores)
 
     def validate(self) -> int:
         ws = ctypes.c_size_t()

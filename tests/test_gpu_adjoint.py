@@ -190,3 +190,18 @@ def test_zero_cotangent_gives_zero_gradient(gpu_lib):
     grad = b.scores_backward(out.log_scale, torch.zeros(100, dtype=torch.float64, device="cuda"), m=20)
     torch.cuda.synchronize()
     assert torch.count_nonzero(grad).item() == 0
+
+
+def test_adjoint_full_size_central_differences(gpu_lib):
+    # the differentiation workload at full size: ER n=2e5 degree 16, 16 realizations, m=30, FP32
+    # weights at 1.0; loss = sum of the summed scores over the 40 target nodes; 100 random edges
+    torch = torch_mod()
+    w = C.workload(3)
+    hb = C.build_parallel(w, workers=16)
+    b = api().Batch.from_host(hb)
+    out = b.scores(m=w.m)
+    g = np.zeros(int(hb.n[0]))
+    g[b_targets(hb)] = 1.0
+    grad = b.scores_backward(out.log_scale, torch.as_tensor(g).to("cuda"), m=w.m)
+    torch.cuda.synchronize()
+    fd_check(hb, b, out, grad, w.m, nedges=100, seed=11, tol_rel=1e-3, tol_abs_frac=1e-5, workers=16)
