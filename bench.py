@@ -90,7 +90,10 @@ def main() -> int:
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workers", type=int, default=0)
-    ap.add_argument("--seg-len", type=int, default=0, help="SpMV gather source: 0 auto, -1 direct, >0 LDS segment")
+    ap.add_argument("--spmv", default="tuned", choices=["tuned", "stream", "lanes", "staged", "segmented"],
+                    help="SpMV form: tuned = time the forms on this batch first (ebtc_tune) and use the fastest")
+    ap.add_argument("--lanes", type=int, default=0, help="lane-group form: lanes per row (0 = 8)")
+    ap.add_argument("--seg-len", type=int, default=0, help="LDS-staged form: segment length (0 = largest)")
     ap.add_argument("--realizations", type=int, default=0, help="limit realizations per graph (0 = all)")
     ap.add_argument("--adjoint", action="store_true", help="also time the adjoint (always on for workload 3)")
     ap.add_argument("--profile-run", action="store_true",
@@ -132,14 +135,20 @@ def main() -> int:
         dst = torch.empty_like(src)
         dst.copy_(src)  # calibration: reads and writes exactly 1 GiB
         out = {}
-        for label, sl, ln in (("stream", -1, 0), ("lane_groups", -1, 8), ("lds_staged", 35000, 0)):
-            rr = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=False, diag=False, seg_len=sl, lanes=ln)
+        for label, form in (("stream", "stream"), ("lane_groups", "lanes"), ("lds_staged", "staged"),
+                            ("column_segmented", "segmented")):
+            rr = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=False, diag=False, spmv=form)
             out[label] = rr.profile()
         torch.cuda.synchronize()
         print(json.dumps({"profile_run": w.name, "realizations": hb.R, "phases": out}), flush=True)
         return 0
 
-    run = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=True, diag=True, seg_len=args.seg_len)
+    form = {"spmv": "auto" if args.spmv == "tuned" else args.spmv, "lanes": args.lanes, "seg_len": args.seg_len}
+    tuned = None
+    if args.spmv == "tuned":
+        tuned = b.tune(m=m, tol=tol, m_max=m_max)
+        log(f"tuned SpMV form: {tuned}")
+    run = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=True, diag=True, **form)
 
     def step(r):
         out = r.launch()
@@ -172,7 +181,7 @@ def main() -> int:
         g = torch.zeros(hb.n.sum(), dtype=b.tdtype, device="cuda")
         for gi in range(int(hb.n.size)):
             g[int(b.score_off[gi]) + torch.as_tensor(hb.targets[gi]).to("cuda")] = 1.0
-        bwd = b.backward_run(m=m, tol=tol, m_max=m_max, seg_len=args.seg_len)
+        bwd = b.backward_run(m=m, tol=tol, m_max=m_max, **form)
         for _ in range(args.warmup):
             run.launch()
             bwd.launch(run.log_scale, g)
@@ -192,7 +201,7 @@ def main() -> int:
         log(f"adjoint: forward {fwd_ms:.3f} ms, backward {bwd_ms:.3f} ms, ratio {bwd_ms / fwd_ms:.2f}")
 
     # plain per-realization loop on the same batch
-    runp = b.run(m=m, tol=tol, m_max=m_max, schedule="plain", hipgraph=False, diag=False, seg_len=args.seg_len)
+    runp = b.run(m=m, tol=tol, m_max=m_max, schedule="plain", hipgraph=False, diag=False, **form)
     step(runp)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -204,13 +213,14 @@ def main() -> int:
     log(f"plain: {1000 * plain_wall / args.plain_steps:.3f} ms/step, {plain_value:.1f} realizations/s")
 
     # per-kernel durations with HIP events around each launch (eager batched sequence)
-    rune = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=False, diag=True, seg_len=args.seg_len)
+    rune = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=False, diag=True, **form)
     rune.profile()
     phases = rune.profile()
     # the two SpMV gather forms side by side (LDS-staged column segments vs direct gathers)
     spmv_modes = {}
-    for label, sl, ln in (("stream", -1, 0), ("lane_groups", -1, 8), ("lds_staged", 35000, 0)):
-        rr = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=False, diag=False, seg_len=sl, lanes=ln)
+    for label, form_name in (("stream", "stream"), ("lane_groups", "lanes"), ("lds_staged", "staged"),
+                             ("column_segmented", "segmented")):
+        rr = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=False, diag=False, spmv=form_name)
         rr.profile()
         ph = rr.profile()
         spmv_modes[label] = round(ph["spmv"][0] / max(1, ph["spmv"][1]), 5)
@@ -257,7 +267,8 @@ def main() -> int:
         "config": {"workload": w.name, "graphs": int(hb.n.size), "realizations": hb.R,
                    "n": [int(x) for x in hb.n], "nnz_total": int(hb.nnz_off[-1]), "m": m,
                    "adaptive_tol": w.tol if m == 0 else None, "reorth": 1, "K": [int(x) for x in K[:4]],
-                   "schedule": "batched, hipGraph replay", "parallelism": "1 GPU"},
+                   "schedule": "batched, hipGraph replay", "parallelism": "1 GPU",
+                   "spmv_form": tuned if tuned is not None else form},
         "plain": {"value": round(plain_value, 2), "ms_per_step": round(1000 * plain_wall / args.plain_steps, 3),
                   "batched_over_plain": round(value / plain_value, 2)},
         "effective_GBps_whole_path": round(total_alg * args.steps / wall / 1e9, 1),

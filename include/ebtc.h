@@ -93,12 +93,28 @@ typedef struct {
   int32_t schedule;      /* enum ebtc_schedule                                                    */
   int32_t use_hipgraph;  /* batched schedule: capture the launch sequence once, replay it after    */
   int32_t shift;         /* 1 (default): factor out theta*; 0: theta* = 0 (overflow-prone, tests)  */
-  int32_t lanes_per_row; /* SpMV lanes per CSR row: 0 = auto, else 4, 8, 16 or 32                 */
+  int32_t spmv;          /* SpMV form (enum ebtc_spmv_form): 0 = auto (the form ebtc_tune picked for
+                            this batch, else the CSR-stream form)                                 */
+  int32_t lanes_per_row; /* lane-group form: lanes per CSR row, 4, 8, 16 or 32 (0 = 8)            */
   int32_t hub_threshold; /* rows with more entries are reduced by a whole workgroup; 0 = auto     */
-  int32_t seg_len;       /* SpMV gather source: 0 = auto, -1 = gather from HBM/L2, > 0 = stage the
-                            vector through LDS in column segments of this many elements (clamped to
-                            what fits next to the per-row state: 35328 FP32 / 16640 FP64)        */
+  int32_t seg_len;       /* LDS-staged and column-segmented forms: vector segment length in
+                            elements (0 = the form's default: the largest that fits for LDS-staged,
+                            16384 FP32 / 8192 FP64 for column-segmented)                          */
 } ebtc_opts;
+
+enum ebtc_spmv_form {
+  EBTC_SPMV_AUTO = 0,
+  EBTC_SPMV_STREAM = 1,      /* each workgroup streams its rows' contiguous entries, gathers, sums
+                                every row in FP64 from LDS                                         */
+  EBTC_SPMV_LANE_GROUPS = 2, /* L lanes per row, two rows and four entries per lane in flight      */
+  EBTC_SPMV_LDS_STAGED = 3,  /* the gathered vector streams through LDS in column segments         */
+  EBTC_SPMV_SEGMENTED = 4    /* each call first sorts every row block's entries by column segment
+                                (stable; 16-bit in-segment columns, 8-bit per-row counts); each step
+                                then stages one vector segment at a time in LDS and serves every
+                                gather of that segment from it. Needs ceil(n / seg_len) <= 32;
+                                row blocks with more than 65535 entries, or a row with more than 255
+                                entries in one segment, use the CSR-stream form                     */
+};
 
 /* Per-realization diagnostics (device array [R], written by ebtc_scores). */
 typedef struct {
@@ -192,6 +208,26 @@ int ebtc_spmv(int32_t dtype, int32_t n, const int32_t* row_ptr, const int32_t* c
 int ebtc_tridiag_expv(int32_t count, int32_t k, const double* alpha, const double* beta, double* y_out,
                       double* theta_out, int32_t shift, void* stream);
 
+/* ---------------------------------------------------------------- autotuning                     */
+/* Times the SpMV forms on this batch with HIP events -- the CSR stream, lane groups of 4, 8, 16 and
+ * 32 lanes per row, and the LDS-staged form when the largest vector passes through LDS in at most
+ * eight segments -- each as one warm-up and three timed launches of the first Lanczos product over
+ * every realization, and records the fastest in the batch (the column-segmented form is tried when
+ * ws_bytes covers ebtc_plan's size for opts with spmv = EBTC_SPMV_SEGMENTED; plan the later calls
+ * after tuning, since the chosen form sets their workspace size): later calls with opts->spmv ==
+ * EBTC_SPMV_AUTO use it (a form named in opts overrides it). Synchronous on the stream. Overwrites
+ * the workspace (size from ebtc_plan for opts, 256-byte aligned); not thread-safe with other calls
+ * on the same batch.
+ *   form_out, lanes_out, seglen_out  host (nullable): the chosen form and its parameters
+ *   ms_out  host [8] (nullable): ms per launch of stream, lanes 4, 8, 16, 32, LDS-staged,
+ *           column-segmented with 8192 and 16384 FP32 (4096 and 8192 FP64) columns per segment, the
+ *           latter two including their one sort per call spread over the call's m steps (-1 where
+ *           the form was not tried)
+ * Errors: EINVAL (NULL batch or workspace, bad opts), EWORKSPACE, EHIP. On error the batch keeps its
+ * previous choice. */
+int ebtc_tune(ebtc_batch* batch, const ebtc_opts* opts, void* ws, size_t ws_bytes, int32_t* form_out,
+              int32_t* lanes_out, int32_t* seglen_out, double* ms_out, void* stream);
+
 /* ---------------------------------------------------------------- measurement                    */
 enum ebtc_phase {
   EBTC_PHASE_START = 0,      /* start vector and state initialisation                           */
@@ -201,7 +237,8 @@ enum ebtc_phase {
   EBTC_PHASE_TRIDIAG = 4,    /* FP64 tridiagonal exponential (final and adaptive checks)        */
   EBTC_PHASE_COMBINE = 5,    /* u = beta0 V y                                                    */
   EBTC_PHASE_SUM = 6,        /* realization sum with per-graph log-scale                        */
-  EBTC_PHASE_COUNT = 7
+  EBTC_PHASE_PREPARE = 7,    /* column-segment sort of the entries (column-segmented SpMV only) */
+  EBTC_PHASE_COUNT = 8
 };
 /* Measurement only: runs ebtc_scores' batched launch sequence once, eagerly (no hipGraph), with a
  * HIP event recorded on `stream` before and after every kernel launch, then synchronises the

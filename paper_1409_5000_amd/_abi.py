@@ -24,9 +24,10 @@ EXPORTED = [
     "ebtc_version", "ebtc_status_str", "ebtc_last_error", "ebtc_default_opts", "ebtc_batch_create",
     "ebtc_batch_destroy", "ebtc_plan", "ebtc_scores", "ebtc_topk_ws_bytes", "ebtc_topk", "ebtc_spmv",
     "ebtc_tridiag_expv", "ebtc_validate_ws_bytes", "ebtc_validate", "ebtc_profile_phases", "ebtc_plan_backward",
-    "ebtc_scores_backward",
+    "ebtc_scores_backward", "ebtc_tune",
 ]
-PHASES = ["start", "spmv", "dots", "update", "tridiag", "combine", "sum"]
+SPMV_FORMS = {"auto": 0, "stream": 1, "lanes": 2, "staged": 3, "segmented": 4}
+PHASES = ["start", "spmv", "dots", "update", "tridiag", "combine", "sum", "prepare"]
 
 
 class BatchDesc(ctypes.Structure):
@@ -41,8 +42,8 @@ class BatchDesc(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [
         ("m", c_int32), ("m_max", c_int32), ("tol", c_double), ("reorth", c_int32), ("schedule", c_int32),
-        ("use_hipgraph", c_int32), ("shift", c_int32), ("lanes_per_row", c_int32), ("hub_threshold", c_int32),
-        ("seg_len", c_int32),
+        ("use_hipgraph", c_int32), ("shift", c_int32), ("spmv", c_int32), ("lanes_per_row", c_int32),
+        ("hub_threshold", c_int32), ("seg_len", c_int32),
     ]
 
 
@@ -85,6 +86,8 @@ def lib() -> ctypes.CDLL:
         "ebtc_profile_phases": (c_int, [vp, POINTER(Opts), vp, sz, vp, vp, POINTER(c_double), POINTER(c_int64), vp]),
         "ebtc_plan_backward": (c_int, [vp, POINTER(Opts), POINTER(sz)]),
         "ebtc_scores_backward": (c_int, [vp, POINTER(Opts), vp, vp, vp, vp, sz, vp]),
+        "ebtc_tune": (c_int, [vp, POINTER(Opts), vp, sz, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
+                              POINTER(c_double), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -33,10 +33,14 @@ def current_stream() -> ctypes.c_void_p:
 
 
 def make_opts(m: int = 30, tol: float = 1e-6, m_max: int = 60, reorth: int = 1, schedule: str = "batched",
-              hipgraph: bool = True, shift: bool = True, lanes: int = 0, hub: int = 0, seg_len: int = 0) -> A.Opts:
+              hipgraph: bool = True, shift: bool = True, spmv: str = "auto", lanes: int = 0, hub: int = 0,
+              seg_len: int = 0) -> A.Opts:
+    """Options of one call. spmv: "auto" (the tuned form, else "stream"), "stream", "lanes" (lanes per
+    row, default 8), "staged" (segment length seg_len, default the largest that fits in LDS) or
+    "segmented" (seg_len columns per segment, default 16384 FP32 / 8192 FP64)."""
     return A.default_opts(m=m, tol=tol, m_max=m_max, reorth=reorth, schedule=_SCHED[schedule],
-                          use_hipgraph=int(hipgraph), shift=int(shift), lanes_per_row=lanes, hub_threshold=hub,
-                          seg_len=seg_len)
+                          use_hipgraph=int(hipgraph), shift=int(shift), spmv=A.SPMV_FORMS[spmv], lanes_per_row=lanes,
+                          hub_threshold=hub, seg_len=seg_len)
 
 
 @dataclass
@@ -182,6 +186,26 @@ class Batch:
         A.check(A.lib().ebtc_topk(self.handle, _vp(scores), kv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                   _vp(idx), _vp(val), _vp(wst), ws.value, current_stream()))
         return idx[:tot], val[:tot]
+
+    def tune(self, **kw) -> dict:
+        """Times the SpMV forms on this batch (ebtc_tune) and keeps the fastest for spmv="auto" calls.
+        Plan Runs after tuning: the chosen form sets their workspace size."""
+        opts = make_opts(**kw)
+        ws = ctypes.c_size_t()
+        seg = make_opts(**{**kw, "spmv": "segmented", "seg_len": 4096 if self.dtype == "f64" else 8192})
+        if A.lib().ebtc_plan(self.handle, ctypes.byref(seg), ctypes.byref(ws), None) != A.EBTC_OK:
+            A.check(A.lib().ebtc_plan(self.handle, ctypes.byref(opts), ctypes.byref(ws), None))
+        wst = torch.empty(max(1, ws.value), dtype=torch.uint8, device=self.device)
+        form, lanes, segl = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        ms = (ctypes.c_double * 8)()
+        A.check(A.lib().ebtc_tune(self.handle, ctypes.byref(opts), _vp(wst), ws.value, ctypes.byref(form),
+                                  ctypes.byref(lanes), ctypes.byref(segl), ms, current_stream()))
+        names = {v: k for k, v in A.SPMV_FORMS.items()}
+        small = 4096 if self.dtype == "f64" else 8192
+        labels = ["stream", "lanes4", "lanes8", "lanes16", "lanes32", "staged", f"segmented{small}",
+                  f"segmented{2 * small}"]
+        return {"form": names[form.value], "lanes": lanes.value, "seg_len": segl.value,
+                "ms_per_launch": {l: ms[i] for i, l in enumerate(labels) if ms[i] >= 0}}
 
     def backward_run(self, **kw) -> "BackwardRun":
         return BackwardRun(self, make_opts(**kw))

@@ -30,6 +30,8 @@ struct Layout {
   int m_slots = 0;
   size_t off_tasks = 0, off_graphs = 0, off_blkmap = 0, off_state = 0, off_part = 0, off_npart = 0, off_V = 0,
          off_W = 0, off_U = 0;
+  // column-segmented SpMV arenas (present when the plan uses that form)
+  size_t off_segflag = 0, off_segcnt = 0, off_segcol = 0, off_segval = 0;
   size_t total = 0;
   int64_t total_blocks = 0;
 };
@@ -40,12 +42,12 @@ struct ExecKey {
   double* log_scale;
   void* ckpt;
   ebtc_diag* diag;
-  int m, m_max, reorth, shift, lanes, hub, seglen;
+  int m, m_max, reorth, shift, form, lanes, hub, seglen;
   double tol;
   bool operator==(const ExecKey& o) const {
     return ws == o.ws && scores == o.scores && log_scale == o.log_scale && ckpt == o.ckpt && diag == o.diag &&
-           m == o.m && m_max == o.m_max && reorth == o.reorth && shift == o.shift && lanes == o.lanes &&
-           hub == o.hub && seglen == o.seglen && tol == o.tol;
+           m == o.m && m_max == o.m_max && reorth == o.reorth && shift == o.shift && form == o.form &&
+           lanes == o.lanes && hub == o.hub && seglen == o.seglen && tol == o.tol;
   }
 };
 
@@ -79,6 +81,8 @@ struct ebtc_batch {
   std::vector<int64_t> topk_off;
   std::vector<ExecEntry> execs;
   hipStream_t capture_stream = nullptr;
+  // SpMV form chosen by ebtc_tune (0 = not tuned): used when opts->spmv is EBTC_SPMV_AUTO
+  int32_t tuned_form = 0, tuned_lanes = 0, tuned_seglen = 0;
 };
 
 namespace {
@@ -90,30 +94,35 @@ int check_opts(const ebtc_opts* o) {
   if (o->m == 0 && !(o->tol > 0.0)) return fail(EBTC_EINVAL, "adaptive mode needs tol > 0");
   if (o->reorth != 1 && o->reorth != 2) return fail(EBTC_EINVAL, "reorth must be 1 or 2");
   if (o->schedule < EBTC_SCHED_AUTO || o->schedule > EBTC_SCHED_BATCHED) return fail(EBTC_EINVAL, "unknown schedule");
+  if (o->spmv < EBTC_SPMV_AUTO || o->spmv > EBTC_SPMV_SEGMENTED) return fail(EBTC_EINVAL, "unknown spmv form");
   if (o->lanes_per_row != 0 && o->lanes_per_row != 4 && o->lanes_per_row != 8 && o->lanes_per_row != 16 &&
       o->lanes_per_row != 32)
     return fail(EBTC_EINVAL, "lanes_per_row must be 0, 4, 8, 16 or 32");
   if (o->hub_threshold < 0) return fail(EBTC_EINVAL, "hub_threshold must be >= 0");
-  if (o->seg_len < -1) return fail(EBTC_EINVAL, "seg_len must be -1, 0 or > 0");
+  if (o->seg_len < 0) return fail(EBTC_EINVAL, "seg_len must be >= 0");
   return EBTC_OK;
 }
 
-// Schedule of the SpMV for a batch: lanes per row, hub threshold and LDS segment length.
+// Schedule of the SpMV for a batch: the form and its parameters.
 struct SpmvPlan {
-  int lanes, hub, seglen;
+  int form = EBTC_SPMV_STREAM;
+  int lanes = 0, hub = 0;
+  int seglen = 0;   // LDS-staged: segment length
+  int segcols = 0;  // column-segmented: columns per segment
+  int smax = 0;     // column-segmented: segments of the largest realization
 };
 
 SpmvPlan spmv_plan(const ebtc_batch* b, const ebtc_opts* o);
 
-// Lanes per CSR row: the SpMV loads four entries per lane before using them, so L lanes cover 4L
-// entries per trip; pick the smallest power of two with 4L >= mean degree (4..32).
-int auto_lanes(double mean_degree) {
-  int L = 4;
-  while (L < 32 && 4.0 * L < mean_degree) L *= 2;
-  return L;
+int check_plan(const ebtc_batch* b, const SpmvPlan& p) {
+  if (p.form == EBTC_SPMV_SEGMENTED && p.smax > kSegMax)
+    return fail(EBTC_EINVAL, "the column-segmented SpMV needs at most " + std::to_string(kSegMax) +
+                                 " segments: n_max " + std::to_string(b->n_max) + " > " +
+                                 std::to_string(kSegMax) + " x " + std::to_string(p.segcols));
+  return EBTC_OK;
 }
 
-Layout make_layout(const ebtc_batch* b, const ebtc_opts* o) {
+Layout make_layout(const ebtc_batch* b, const ebtc_opts* o, const SpmvPlan& sp) {
   Layout L;
   L.m_slots = (o->m > 0 ? o->m : o->m_max) + 1;
   const size_t es = elem_size(b->dtype);
@@ -144,6 +153,17 @@ Layout make_layout(const ebtc_batch* b, const ebtc_opts* o) {
   off = align_up(off + es * rows);
   L.off_U = off;
   off = align_up(off + es * rows);
+  if (sp.form == EBTC_SPMV_SEGMENTED) {
+    const size_t z = (size_t)b->nnz_off[b->R];
+    L.off_segflag = off;
+    off = align_up(off + sizeof(int32_t) * blocks);
+    L.off_segcnt = off;
+    off = align_up(off + (size_t)sp.smax * kRowsPerBlock * blocks);
+    L.off_segcol = off;
+    off = align_up(off + sizeof(uint16_t) * z);
+    L.off_segval = off;
+    if (b->values) off = align_up(off + es * z);
+  }
   L.total = off;
   return L;
 }
@@ -183,26 +203,31 @@ int upload_tables(ebtc_batch* b, char* ws, const Layout& L, hipStream_t s) {
   return EBTC_OK;
 }
 
-SpmvPlan spmv_plan(const ebtc_batch* b, const ebtc_opts* o) {
+SpmvPlan spmv_form(const ebtc_batch* b, int form, int lanes, int seg_len, int hub) {
   SpmvPlan p;
-  const int maxseg = staged_max_seglen(b->dtype);
-  int seg = o->seg_len;
-  if (seg == 0) {
-    // Stage when the vector passes through LDS in at most four segments (the per-workgroup staging
-    // traffic, n elements, then stays near the CSR bytes the workgroup streams) and rows are short
-    // enough for their entries to sit in registers (mean degree <= 24 for 32 register slots).
-    const int nseg = (b->n_max + maxseg - 1) / maxseg;
-    seg = -1;  // measured: the CSR-stream SpMV is the faster default; staging stays selectable
-    (void)nseg;
+  p.form = form;
+  if (form == EBTC_SPMV_LANE_GROUPS) p.lanes = lanes ? lanes : 8;
+  if (form == EBTC_SPMV_LDS_STAGED) {
+    const int maxseg = staged_max_seglen(b->dtype);
+    p.seglen = seg_len > 0 ? std::min(seg_len, maxseg) : maxseg;
   }
-  p.seglen = seg > 0 ? std::min(seg, maxseg) : 0;
-  // lanes 0 = the CSR-stream SpMV (default); explicit lanes select the lane-group SpMV
-  p.lanes = o->lanes_per_row;
-  p.hub = o->hub_threshold ? o->hub_threshold : 16 * (p.lanes ? p.lanes : 8);
+  if (form == EBTC_SPMV_SEGMENTED) {
+    const int dflt = b->dtype == EBTC_F64 ? 8192 : 16384;
+    p.segcols = std::min(seg_len > 0 ? seg_len : dflt, seg_max_cols(b->dtype));
+    p.smax = (b->n_max + p.segcols - 1) / p.segcols;
+  }
+  p.hub = hub ? hub : 16 * (p.lanes ? p.lanes : 8);
   return p;
 }
 
-LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, int hub) {
+// The CSR-stream form unless the caller names one or ebtc_tune measured another on this batch.
+SpmvPlan spmv_plan(const ebtc_batch* b, const ebtc_opts* o) {
+  if (o->spmv != EBTC_SPMV_AUTO) return spmv_form(b, o->spmv, o->lanes_per_row, o->seg_len, o->hub_threshold);
+  if (b->tuned_form) return spmv_form(b, b->tuned_form, b->tuned_lanes, b->tuned_seglen, o->hub_threshold);
+  return spmv_form(b, EBTC_SPMV_STREAM, 0, 0, o->hub_threshold);
+}
+
+LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, const SpmvPlan& sp) {
   LzArgs a{};
   a.row_ptr = b->row_ptr;
   a.col_idx = b->col_idx;
@@ -210,7 +235,7 @@ LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout
   a.tasks = (const Task*)(ws + L.off_tasks);
   a.blkmap = (const int32_t*)(ws + L.off_blkmap);
   a.single_task = 0;
-  a.hub_threshold = hub;
+  a.hub_threshold = sp.hub;
   a.state = (RState*)(ws + L.off_state);
   a.V = ws + L.off_V;
   a.W = ws + L.off_W;
@@ -218,10 +243,25 @@ LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout
   a.part = (double*)(ws + L.off_part);
   a.npart = (double*)(ws + L.off_npart);
   a.m_fixed = o->m;
-  a.seglen = spmv_plan(b, o).seglen;
+  a.seglen = sp.seglen;
   a.m_max = o->m > 0 ? o->m : o->m_max;
   a.eps = b->dtype == EBTC_F64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+  if (sp.form == EBTC_SPMV_SEGMENTED) {
+    a.seg_cols = sp.segcols;
+    a.seg_stride = sp.smax * kRowsPerBlock;
+    a.seg_flag = (int32_t*)(ws + L.off_segflag);
+    a.seg_cnt = (uint8_t*)(ws + L.off_segcnt);
+    a.seg_col = (uint16_t*)(ws + L.off_segcol);
+    a.seg_val = b->values ? (void*)(ws + L.off_segval) : nullptr;
+  }
   return a;
+}
+
+// Kernel opt-ins to the full LDS; once per process, before any stream capture.
+int prepare_kernels(const SpmvPlan& sp) {
+  if (sp.seglen > 0) EBTC_HIP(prepare_staged_kernels());
+  if (sp.segcols > 0) EBTC_HIP(prepare_seg_kernels());
+  return EBTC_OK;
 }
 
 // Optional per-launch event recording (ebtc_profile_phases).
@@ -283,12 +323,22 @@ int run_steps(const ebtc_batch* b, const ebtc_opts* o, const LzArgs& a, int64_t 
   return EBTC_OK;
 }
 
+// The column-segmented form's once-per-call sort of the entries (no-op for the other forms).
+int enqueue_prepare(const ebtc_batch* b, const SpmvPlan& sp, const LzArgs& a, int64_t nblocks, hipStream_t s,
+                    Prof* prof) {
+  if (sp.form != EBTC_SPMV_SEGMENTED) return EBTC_OK;
+  EBTC_PHASE(prof, EBTC_PHASE_PREPARE, launch_seg_prepare(b->dtype, b->values != nullptr, a, nblocks, sp.smax, s));
+  return EBTC_OK;
+}
+
 int enqueue_batched(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, void* scores, double* log_scale,
-                    void* ckpt, ebtc_diag* diag, int lanes, int hub, hipStream_t s, Prof* prof = nullptr) {
-  LzArgs a = make_args(b, o, ws, L, hub);
+                    void* ckpt, ebtc_diag* diag, const SpmvPlan& sp, hipStream_t s, Prof* prof = nullptr) {
+  LzArgs a = make_args(b, o, ws, L, sp);
   a.diag = diag;
   EBTC_LAUNCH(launch_blkmap(a.tasks, b->R, (int32_t*)(ws + L.off_blkmap), s));
-  int rc = run_steps(b, o, a, L.total_blocks, 0, b->R, lanes, s, prof);
+  int rc = enqueue_prepare(b, sp, a, L.total_blocks, s, prof);
+  if (rc) return rc;
+  rc = run_steps(b, o, a, L.total_blocks, 0, b->R, sp.lanes, s, prof);
   if (rc) return rc;
   const int steps = o->m > 0 ? o->m : o->m_max;
   EBTC_PHASE(prof, EBTC_PHASE_TRIDIAG,
@@ -301,14 +351,16 @@ int enqueue_batched(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L
 }
 
 int enqueue_plain(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, void* scores, double* log_scale,
-                  void* ckpt, ebtc_diag* diag, int lanes, int hub, hipStream_t s) {
-  LzArgs a = make_args(b, o, ws, L, hub);
+                  void* ckpt, ebtc_diag* diag, const SpmvPlan& sp, hipStream_t s) {
+  LzArgs a = make_args(b, o, ws, L, sp);
   a.blkmap = nullptr;
   a.diag = diag;
   for (int64_t r = 0; r < b->R; ++r) {
     a.single_task = (int32_t)r;
     const int64_t nb = b->tasks[r].nblk;
-    int rc = run_steps(b, o, a, nb, r, 1, lanes, s, nullptr);
+    int rc = enqueue_prepare(b, sp, a, nb, s, nullptr);
+    if (rc) return rc;
+    rc = run_steps(b, o, a, nb, r, 1, sp.lanes, s, nullptr);
     if (rc) return rc;
     EBTC_LAUNCH(launch_tridiag_state(a, r, 1, 0, 0, o->m > 0 ? o->m : o->m_max, o->shift, o->tol, diag,
                                      (double*)ckpt, s));
@@ -334,7 +386,7 @@ struct BwdLayout {
 
 BwdLayout make_bwd_layout(const ebtc_batch* b, const ebtc_opts* o) {
   BwdLayout B;
-  B.fwd = make_layout(b, o);
+  B.fwd = make_layout(b, o, spmv_plan(b, o));
   const size_t es = elem_size(b->dtype);
   const int steps = o->m > 0 ? o->m : o->m_max;
   B.ld = (steps + 7) / 8 * 8;
@@ -397,6 +449,7 @@ void ebtc_default_opts(ebtc_opts* o) {
   o->schedule = EBTC_SCHED_AUTO;
   o->use_hipgraph = 1;
   o->shift = 1;
+  o->spmv = EBTC_SPMV_AUTO;
   o->lanes_per_row = 0;
   o->hub_threshold = 0;
   o->seg_len = 0;
@@ -500,7 +553,10 @@ int ebtc_plan(ebtc_batch* b, const ebtc_opts* o, size_t* ws_bytes, size_t* ckpt_
   if (!b || !ws_bytes) return fail(EBTC_EINVAL, "NULL batch or output");
   int rc = check_opts(o);
   if (rc) return rc;
-  *ws_bytes = make_layout(b, o).total;
+  const SpmvPlan sp = spmv_plan(b, o);
+  rc = check_plan(b, sp);
+  if (rc) return rc;
+  *ws_bytes = make_layout(b, o, sp).total;
   if (ckpt_bytes) *ckpt_bytes = sizeof(double) * kCkptDoubles * (size_t)b->R;
   return EBTC_OK;
 }
@@ -512,23 +568,26 @@ int ebtc_scores(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, vo
   int rc = check_opts(o);
   if (rc) return rc;
   if (!ws || !scores_out || !log_scale_out) return fail(EBTC_EINVAL, "NULL workspace, scores or log_scale output");
-  const Layout L = make_layout(b, o);
+  const SpmvPlan sp = spmv_plan(b, o);
+  rc = check_plan(b, sp);
+  if (rc) return rc;
+  const Layout L = make_layout(b, o, sp);
   if (ws_bytes < L.total)
     return fail(EBTC_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(L.total));
   if (((uintptr_t)ws & 255) != 0) return fail(EBTC_EINVAL, "workspace must be 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  const SpmvPlan sp = spmv_plan(b, o);
-  const int lanes = sp.lanes, hub = sp.hub;
-  if (sp.seglen > 0) EBTC_HIP(prepare_staged_kernels());
+  rc = prepare_kernels(sp);
+  if (rc) return rc;
   char* w = (char*)ws;
   rc = upload_tables(b, w, L, s);
   if (rc) return rc;
   if (o->schedule == EBTC_SCHED_PLAIN)
-    return enqueue_plain(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, lanes, hub, s);
+    return enqueue_plain(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, sp, s);
   if (!o->use_hipgraph)
-    return enqueue_batched(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, lanes, hub, s);
-  const ExecKey key{ws,       scores_out, log_scale_out, ckpt_out, diag_out,  o->m, o->m_max,
-                    o->reorth, o->shift, lanes,         hub,      sp.seglen, o->tol};
+    return enqueue_batched(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, sp, s);
+  const ExecKey key{ws,        scores_out, log_scale_out, ckpt_out, diag_out, o->m,
+                    o->m_max,  o->reorth,  o->shift,      sp.form,  sp.lanes, sp.hub,
+                    sp.seglen + sp.segcols, o->tol};
   for (auto& e : b->execs) {
     if (e.key == key) {
       EBTC_HIP(hipGraphLaunch(e.exec, s));
@@ -537,7 +596,7 @@ int ebtc_scores(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, vo
   }
   if (!b->capture_stream) EBTC_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
   EBTC_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
-  rc = enqueue_batched(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, lanes, hub, b->capture_stream);
+  rc = enqueue_batched(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, sp, b->capture_stream);
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(b->capture_stream, &graph);
   if (rc) {
@@ -568,19 +627,21 @@ int ebtc_profile_phases(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_b
   int rc = check_opts(o);
   if (rc) return rc;
   if (!ws || !scores_out || !log_scale_out) return fail(EBTC_EINVAL, "NULL workspace, scores or log_scale output");
-  const Layout L = make_layout(b, o);
+  const SpmvPlan sp = spmv_plan(b, o);
+  rc = check_plan(b, sp);
+  if (rc) return rc;
+  const Layout L = make_layout(b, o, sp);
   if (ws_bytes < L.total) return fail(EBTC_EWORKSPACE, "workspace too small");
   if (((uintptr_t)ws & 255) != 0) return fail(EBTC_EINVAL, "workspace must be 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  const SpmvPlan sp = spmv_plan(b, o);
-  const int lanes = sp.lanes, hub = sp.hub;
-  if (sp.seglen > 0) EBTC_HIP(prepare_staged_kernels());
+  rc = prepare_kernels(sp);
+  if (rc) return rc;
   char* w = (char*)ws;
   rc = upload_tables(b, w, L, s);
   if (rc) return rc;
   Prof prof;
   prof.s = s;
-  rc = enqueue_batched(b, o, w, L, scores_out, log_scale_out, nullptr, nullptr, lanes, hub, s, &prof);
+  rc = enqueue_batched(b, o, w, L, scores_out, log_scale_out, nullptr, nullptr, sp, s, &prof);
   if (rc) return rc;
   EBTC_HIP(hipStreamSynchronize(s));
   for (int p = 0; p < EBTC_PHASE_COUNT; ++p) {
@@ -596,10 +657,102 @@ int ebtc_profile_phases(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_b
   return EBTC_OK;
 }
 
+int ebtc_tune(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, int32_t* form_out, int32_t* lanes_out,
+              int32_t* seglen_out, double* ms_out, void* stream) {
+  g_err.clear();
+  if (!b) return fail(EBTC_EINVAL, "NULL batch");
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (!ws) return fail(EBTC_EINVAL, "NULL workspace");
+  const SpmvPlan base = spmv_form(b, EBTC_SPMV_STREAM, 0, 0, o->hub_threshold);
+  const Layout L = make_layout(b, o, base);
+  if (ws_bytes < L.total)
+    return fail(EBTC_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(L.total));
+  if (((uintptr_t)ws & 255) != 0) return fail(EBTC_EINVAL, "workspace must be 256-byte aligned");
+  struct Cand {
+    SpmvPlan p;
+    int slot;
+  };
+  std::vector<Cand> cands;
+  cands.push_back({base, 0});
+  for (int i = 0; i < 4; ++i) cands.push_back({spmv_form(b, EBTC_SPMV_LANE_GROUPS, 4 << i, 0, o->hub_threshold), 1 + i});
+  const int maxseg = staged_max_seglen(b->dtype);
+  if ((b->n_max + maxseg - 1) / maxseg <= 8) cands.push_back({spmv_form(b, EBTC_SPMV_LDS_STAGED, 0, 0, 0), 5});
+  const int small_seg = b->dtype == EBTC_F64 ? 4096 : 8192;
+  for (int i = 0; i < 2; ++i) {
+    const SpmvPlan p = spmv_form(b, EBTC_SPMV_SEGMENTED, 0, small_seg << i, 0);
+    if (p.smax <= kSegMax && make_layout(b, o, p).total <= ws_bytes) cands.push_back({p, 6 + i});
+  }
+  for (const Cand& c : cands) {
+    rc = prepare_kernels(c.p);
+    if (rc) return rc;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  rc = upload_tables(b, w, L, s);
+  if (rc) return rc;
+  LzArgs a0 = make_args(b, o, w, L, base);
+  EBTC_LAUNCH(launch_blkmap(a0.tasks, b->R, (int32_t*)(w + L.off_blkmap), s));
+  EBTC_LAUNCH(launch_start(b->dtype, a0, L.total_blocks, s));
+  double ms[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (auto& e : ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto& f : ev)
+        if (f) (void)hipEventDestroy(f);
+      return fail(EBTC_EHIP, "hipEventCreate failed");
+    }
+  }
+  const bool has_val = b->values != nullptr;
+  const int steps = o->m > 0 ? o->m : o->m_max;
+  constexpr int kReps = 3;
+  int best = -1;
+  for (size_t c = 0; c < cands.size(); ++c) {
+    const SpmvPlan& p = cands[c].p;
+    const Layout Lc = make_layout(b, o, p);  // the form's arenas follow the common ones
+    const LzArgs a = make_args(b, o, w, Lc, p);
+    // [ev0, ev1): the once-per-call sort (segmented form only); [ev2, ev3): kReps products after a
+    // warm-up. Step 0 reads only the start vector and the state k_start wrote, so every launch
+    // does the same work.
+    hipError_t e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess && p.form == EBTC_SPMV_SEGMENTED)
+      e = launch_seg_prepare(b->dtype, has_val, a, L.total_blocks, p.smax, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess) e = launch_spmv_step(b->dtype, has_val, p.lanes, 0, a, L.total_blocks, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[2], s);
+    for (int r = 0; r < kReps && e == hipSuccess; ++r) e = launch_spmv_step(b->dtype, has_val, p.lanes, 0, a, L.total_blocks, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[3], s);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+    float t_prep = 0.f, t_spmv = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t_prep, ev[0], ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t_spmv, ev[2], ev[3]);
+    if (e != hipSuccess) {
+      rc = fail(EBTC_EHIP, std::string("tuning launch: ") + hipGetErrorString(e));
+      break;
+    }
+    ms[cands[c].slot] = t_spmv / kReps + (p.form == EBTC_SPMV_SEGMENTED ? t_prep / steps : 0.0);
+    if (best < 0 || ms[cands[c].slot] < ms[cands[best].slot]) best = (int)c;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (rc) return rc;
+  const SpmvPlan& p = cands[best].p;
+  b->tuned_form = p.form;
+  b->tuned_lanes = p.lanes;
+  b->tuned_seglen = p.form == EBTC_SPMV_SEGMENTED ? p.segcols : p.seglen;
+  if (form_out) *form_out = b->tuned_form;
+  if (lanes_out) *lanes_out = b->tuned_lanes;
+  if (seglen_out) *seglen_out = b->tuned_seglen;
+  if (ms_out)
+    for (int i = 0; i < 8; ++i) ms_out[i] = ms[i];
+  return EBTC_OK;
+}
+
 int ebtc_plan_backward(ebtc_batch* b, const ebtc_opts* o, size_t* ws_bytes) {
   g_err.clear();
   if (!b || !ws_bytes) return fail(EBTC_EINVAL, "NULL batch or output");
   int rc = check_bwd_opts(o);
+  if (rc) return rc;
+  rc = check_plan(b, spmv_plan(b, o));
   if (rc) return rc;
   *ws_bytes = make_bwd_layout(b, o).total;
   return EBTC_OK;
@@ -613,19 +766,24 @@ int ebtc_scores_backward(ebtc_batch* b, const ebtc_opts* o, const double* log_sc
   if (rc) return rc;
   if (!log_scale || !grad_scores || !grad_values || !ws)
     return fail(EBTC_EINVAL, "NULL log_scale, grad_scores, grad_values or workspace");
+  const SpmvPlan sp = spmv_plan(b, o);
+  rc = check_plan(b, sp);
+  if (rc) return rc;
   const BwdLayout B = make_bwd_layout(b, o);
   if (ws_bytes < B.total)
     return fail(EBTC_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(B.total));
   if (((uintptr_t)ws & 255) != 0) return fail(EBTC_EINVAL, "workspace must be 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  const SpmvPlan sp = spmv_plan(b, o);
-  if (sp.seglen > 0) EBTC_HIP(prepare_staged_kernels());
+  rc = prepare_kernels(sp);
+  if (rc) return rc;
   char* w = (char*)ws;
   rc = upload_tables(b, w, B.fwd, s);
   if (rc) return rc;
   // 1. forward recomputation (same kernels and order as ebtc_scores: bitwise the same basis)
-  LzArgs fa = make_args(b, o, w, B.fwd, sp.hub);
+  LzArgs fa = make_args(b, o, w, B.fwd, sp);
   EBTC_LAUNCH(launch_blkmap(fa.tasks, b->R, (int32_t*)(w + B.fwd.off_blkmap), s));
+  rc = enqueue_prepare(b, sp, fa, B.fwd.total_blocks, s, nullptr);  // the sorted entries serve both solves
+  if (rc) return rc;
   rc = run_steps(b, o, fa, B.fwd.total_blocks, 0, b->R, sp.lanes, s, nullptr);
   if (rc) return rc;
   const int steps = o->m > 0 ? o->m : o->m_max;

@@ -84,12 +84,20 @@ struct LzArgs {
   int32_t m_max;
   double eps;              // unit roundoff of the working precision
   ebtc_diag* diag;         // optional diagnostics output (combine flags non-finite results there)
+  // column-segmented SpMV (seg_cols > 0): the entries of every row block sorted by column segment
+  int32_t seg_cols;        // columns per segment
+  int32_t seg_stride;      // bytes of per-(segment, row) counts per row block: max segments x kRowsPerBlock
+  int32_t* seg_flag;       // [row blocks] 1 = sorted, 0 = the block uses the CSR-stream form
+  uint8_t* seg_cnt;        // [row blocks][seg_stride] entries of row r in segment s at [s * rows + r]
+  uint16_t* seg_col;       // [entries] column - s * seg_cols, a block's entries ordered by (segment, row)
+  void* seg_val;           // [entries] values in the same order (nullptr for pattern-only graphs)
 };
 
 // ---- launchers (k_lanczos.hip, k_spmv.hip)
 hipError_t launch_blkmap(const Task* tasks, int64_t R, int32_t* blkmap, hipStream_t s);
 hipError_t launch_start(int dtype, const LzArgs& a, int64_t nblocks, hipStream_t s);
-// Phase A: the SpMV kernel (direct gathers, or LDS-staged when a.seglen > 0), then the dots kernel.
+// Phase A: the SpMV kernel (column-segmented when a.seg_cols > 0, LDS-staged when a.seglen > 0, else
+// the CSR stream for lanes == 0 and lane groups otherwise).
 hipError_t launch_spmv_step(int dtype, bool has_val, int lanes, int j, const LzArgs& a, int64_t nblocks,
                             hipStream_t s);
 hipError_t launch_dots_step(int dtype, int j, const LzArgs& a, int64_t nblocks, hipStream_t s);
@@ -105,6 +113,12 @@ hipError_t launch_spmv(int dtype, bool has_val, int lanes, int hub, int seglen, 
 int staged_max_seglen(int dtype);
 // Opts the staged kernels in to the full LDS once per process (call before any stream capture).
 hipError_t prepare_staged_kernels();
+// Column-segmented SpMV: at most kSegMax segments per realization; largest segment that fits in LDS.
+constexpr int kSegMax = 32;
+int seg_max_cols(int dtype);
+hipError_t prepare_seg_kernels();
+// Sorts every row block's entries by column segment (a.seg_* arrays); smax = max segments in the launch.
+hipError_t launch_seg_prepare(int dtype, bool has_val, const LzArgs& a, int64_t nblocks, int smax, hipStream_t s);
 
 // ---- launchers (k_tridiag.hip)
 // mode 0: final (closes step m_steps-1 when still open; writes y/theta/est, diag, checkpoint);

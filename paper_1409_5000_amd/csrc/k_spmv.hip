@@ -16,6 +16,8 @@
 //                           overflows and by the whole workgroup for hub rows.
 // Both write w for their kRowsPerBlock rows with coalesced stores; the dot products run in a
 // separate streaming kernel.
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace ebtc {
@@ -165,13 +167,13 @@ struct StreamShape {
   static constexpr int CAP = sizeof(T) == 8 ? 3072 : 6144;  // product slots (24 KB)
 };
 
-template <typename T, bool HAS_VAL>
+template <typename T, bool HAS_VAL, int NT = kBlock, int CAP = StreamShape<T>::CAP>
 __device__ inline void spmv_stream_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                         const T* __restrict__ va, const T* __restrict__ x, int r0, int rows,
                                         double scale, int* rp_lds, T* prod, T* w_out, double* red) {
-  constexpr int CAP = StreamShape<T>::CAP, U = kStreamU;
+  constexpr int U = kStreamU;
   const int tid = threadIdx.x;
-  for (int i = tid; i <= rows; i += kBlock) rp_lds[i] = rp[r0 + i];
+  for (int i = tid; i <= rows; i += NT) rp_lds[i] = rp[r0 + i];
   __syncthreads();
   int ra = 0;
   while (ra < rows) {
@@ -179,11 +181,11 @@ __device__ inline void spmv_stream_rows(const int32_t* __restrict__ rp, const in
     if (rp_lds[ra + 1] - nz0 > CAP) {  // hub row: whole workgroup, direct gathers
       const int e = rp_lds[ra + 1];
       T acc = 0;
-      for (int k = nz0 + tid; k < e; k += kBlock) {
+      for (int k = nz0 + tid; k < e; k += NT) {
         const T xv = x[ci[k]];
         if constexpr (HAS_VAL) acc += va[k] * xv; else acc += xv;
       }
-      const double tot = block_sum<kBlock>((double)acc, red);
+      const double tot = block_sum<NT>((double)acc, red);
       if (tid == 0) w_out[ra] = (T)(tot * scale);
       ++ra;
       continue;
@@ -196,12 +198,12 @@ __device__ inline void spmv_stream_rows(const int32_t* __restrict__ rp, const in
     }
     const int rb = lo;
     const int cnt = rp_lds[rb] - nz0;
-    for (int k0 = tid; k0 < cnt; k0 += kBlock * U) {
+    for (int k0 = tid; k0 < cnt; k0 += NT * U) {
       int c[U];
       T v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int k = k0 + u * kBlock;
+        const int k = k0 + u * NT;
         c[u] = k < cnt ? ci[nz0 + k] : -1;
         if constexpr (HAS_VAL) v[u] = k < cnt ? va[nz0 + k] : (T)0;
       }
@@ -210,14 +212,14 @@ __device__ inline void spmv_stream_rows(const int32_t* __restrict__ rp, const in
       for (int u = 0; u < U; ++u) xv[u] = c[u] >= 0 ? x[c[u]] : (T)0;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int k = k0 + u * kBlock;
+        const int k = k0 + u * NT;
         if (k < cnt) {
           if constexpr (HAS_VAL) prod[k] = v[u] * xv[u]; else prod[k] = xv[u];
         }
       }
     }
     __syncthreads();
-    for (int r = ra + tid; r < rb; r += kBlock) {
+    for (int r = ra + tid; r < rb; r += NT) {
       double acc = 0.0;  // FP64: sequential sums over long (BA hub) rows stay accurate
       const int e = rp_lds[r + 1] - nz0;
       for (int k = rp_lds[r] - nz0; k < e; ++k) acc += (double)prod[k];
@@ -397,6 +399,346 @@ __global__ __launch_bounds__(kStagedThreads) void k_spmv_staged(LzArgs a, int j)
   for (int i = threadIdx.x; i < rows; i += kStagedThreads) W[i] = w_lds[i];
 }
 
+// ------------------------------------------------------------------------------- column-segmented
+// The random gathers of the CSR-stream form each cost an L1 miss: a row block's entries touch the
+// whole vector. Here every call first sorts each row block's entries by column segment
+// (k_seg_prepare, once per call: stable, so a row keeps its order inside a segment); each step then
+// walks the segments in order: it stages v_j[segment] in LDS, streams the segment's entries (16-bit
+// in-segment column, value) with coalesced loads, serves every gather from LDS into a product
+// buffer, and adds each row's products to that row's FP64 sum in a register. The loads of segment
+// s + 1 (vector slice, per-row counts, entries) are issued into registers before the gathers of
+// segment s, so one segment's memory latency hides behind the previous segment's LDS work.
+// A row's products are added segment by segment and in entry order within a segment, so for rows
+// stored with ascending columns the sums are those of the CSR-stream form, bit for bit.
+constexpr int kSegThreads = 1024;
+template <typename T>
+struct SegShape {
+  static constexpr int CAP = sizeof(T) == 8 ? 4096 : 8192;  // product slots (32 KB)
+  static constexpr int UE = CAP / kSegThreads;              // prefetched entries per thread
+  static constexpr int XP = sizeof(T) == 8 ? 8 : 16;         // prefetched vector elements per thread
+  static constexpr int MAXCOLS = XP * kSegThreads;           // largest segment (64 KB of LDS)
+};
+
+// Exclusive prefix sum of one int per thread over the workgroup; *total = the sum of all. wtot:
+// NT/64 ints. Ends with a barrier, so wtot may be reused by the next call.
+template <int NT>
+__device__ inline int block_excl_scan(int v, int* wtot, int* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) wtot[w] = inc;
+  __syncthreads();
+  int before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    const int t = wtot[i];
+    before += i < w ? t : 0;
+    all += t;
+  }
+  *total = all;
+  __syncthreads();
+  return before + inc - v;
+}
+
+// Visits the rows [0, rows) of a row block in chunks whose entries fit `cap` LDS slots: loads each
+// chunk's columns (and values when HAS_VAL) with coalesced loads, then calls row_fn(r, cols, vals,
+// first, last) with the row's entries at [first, last) of the staged arrays, each row on one
+// thread. A row longer than cap is passed straight from global memory (cols = ci, vals = va).
+template <typename T, bool HAS_VAL, int NT, typename F>
+__device__ inline void for_rows_staged(const int32_t* __restrict__ ci, const T* __restrict__ va, const int* rp_lds,
+                                       int rows, int cap, int* lci, T* lva, F row_fn) {
+  const int tid = threadIdx.x;
+  int ra = 0;
+  while (ra < rows) {
+    const int k0 = rp_lds[ra];
+    if (rp_lds[ra + 1] - k0 > cap) {
+      if (tid == 0) row_fn(ra, ci, va, k0, rp_lds[ra + 1]);
+      __syncthreads();
+      ++ra;
+      continue;
+    }
+    int lo = ra + 1, hi = rows;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (rp_lds[mid] - k0 <= cap) lo = mid; else hi = mid - 1;
+    }
+    const int rb = lo, ce = rp_lds[rb] - k0;
+    for (int q0 = tid; q0 < ce; q0 += NT * 8) {
+      int c[8];
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = q0 + u * NT;
+        c[u] = k < ce ? ci[k0 + k] : 0;
+        if constexpr (HAS_VAL) v[u] = k < ce ? va[k0 + k] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = q0 + u * NT;
+        if (k < ce) {
+          lci[k] = c[u];
+          if constexpr (HAS_VAL) lva[k] = v[u];
+        }
+      }
+    }
+    __syncthreads();
+    for (int r = ra + tid; r < rb; r += NT) row_fn(r, lci, lva, rp_lds[r] - k0, rp_lds[r + 1] - k0);
+    __syncthreads();
+    ra = rb;
+  }
+}
+
+// One workgroup per row block. Dynamic LDS: the per-(segment, row) counters (16-bit, smax x 2048),
+// then a staging area for `cap` entries (columns, and values for weighted graphs).
+template <typename T, bool HAS_VAL>
+__global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NT = kSegThreads;
+  __shared__ int rp_lds[kRowsPerBlock + 1];
+  __shared__ int wtot[NT / 64];
+  __shared__ int bad;
+  const Ref ref = resolve(a);
+  const Task tk = a.tasks[ref.task];
+  const int n = tk.n, r0 = ref.blk * kRowsPerBlock, rows = min(n - r0, kRowsPerBlock);
+  const int blk = tk.blk_begin + ref.blk, tid = threadIdx.x;
+  const int SEG = a.seg_cols, S = (n + SEG - 1) / SEG, tot = S * rows;
+  uint16_t* cnt = (uint16_t*)smem;  // [S * rows]: counts, then insertion cursors
+  const size_t cnt_bytes = ((size_t)(a.seg_stride) * 2 + 15) / 16 * 16;
+  int* lci = (int*)(smem + cnt_bytes);
+  T* lva = (T*)(smem + cnt_bytes + (size_t)cap * 4);
+  const int32_t* rp = a.row_ptr + tk.rowptr_off;
+  for (int i = tid; i <= rows; i += NT) rp_lds[i] = rp[r0 + i];
+  for (int i = tid; i < tot; i += NT) cnt[i] = 0;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  const int e0 = rp_lds[0];
+  if (rp_lds[rows] - e0 > 65535 || S > kSegMax) {  // offsets must fit 16 bits
+    if (tid == 0) a.seg_flag[blk] = 0;
+    return;
+  }
+  const int32_t* ci = a.col_idx + tk.nnz_off + e0;
+  const T* va = HAS_VAL ? (const T*)a.values + tk.nnz_off + e0 : nullptr;
+  __syncthreads();  // every thread has read rp_lds[0] and rp_lds[rows]
+  for (int i = tid; i <= rows; i += NT) rp_lds[i] -= e0;
+  __syncthreads();
+  // counts per (segment, row): a row is visited by one thread, so no counter has two writers
+  for_rows_staged<T, HAS_VAL, NT>(ci, va, rp_lds, rows, cap, lci, lva,
+                                  [&](int r, const int* cs, const T*, int k, int e) {
+                                    for (; k < e; ++k) {
+                                      const int c = cs[k];
+                                      if ((unsigned)c >= (unsigned)n) {
+                                        bad = 1;
+                                        return;
+                                      }
+                                      const int idx = (c / SEG) * rows + r;
+                                      if (cnt[idx] == 255) {  // the step kernel reads 8-bit counts
+                                        bad = 1;
+                                        return;
+                                      }
+                                      cnt[idx] = (uint16_t)(cnt[idx] + 1);
+                                    }
+                                  });
+  if (bad) {
+    if (tid == 0) a.seg_flag[blk] = 0;
+    return;
+  }
+  uint8_t* cnt_out = a.seg_cnt + (size_t)blk * a.seg_stride;
+  for (int i = tid; i < tot; i += NT) cnt_out[i] = (uint8_t)cnt[i];
+  // exclusive scan in (segment, row) order: thread t owns counters [b, e)
+  const int per = (tot + NT - 1) / NT;
+  const int b = min(tid * per, tot), e = min(b + per, tot);
+  int sum = 0;
+  for (int i = b; i < e; ++i) sum += cnt[i];
+  int total;
+  int run = block_excl_scan<NT>(sum, wtot, &total);
+  for (int i = b; i < e; ++i) {
+    const int c = cnt[i];
+    cnt[i] = (uint16_t)run;
+    run += c;
+  }
+  __syncthreads();
+  uint16_t* pc = a.seg_col + tk.nnz_off + e0;
+  T* pv = HAS_VAL ? (T*)a.seg_val + tk.nnz_off + e0 : nullptr;
+  for_rows_staged<T, HAS_VAL, NT>(ci, va, rp_lds, rows, cap, lci, lva,
+                                  [&](int r, const int* cs, const T* vs, int k, int e) {
+                                    for (; k < e; ++k) {
+                                      const int c = cs[k];
+                                      const int sg = c / SEG;
+                                      const int pos = cnt[sg * rows + r];
+                                      cnt[sg * rows + r] = (uint16_t)(pos + 1);
+                                      pc[pos] = (uint16_t)(c - sg * SEG);
+                                      if constexpr (HAS_VAL) pv[pos] = vs[k];
+                                    }
+                                  });
+  if (tid == 0) a.seg_flag[blk] = 1;
+}
+
+template <typename T, bool HAS_VAL>
+__global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  using SS = SegShape<T>;
+  constexpr int CAP = SS::CAP, NT = kSegThreads, UE = SS::UE, XP = SS::XP, U = kStreamU;
+  T* xs = (T*)smem;  // [seg_cols]
+  __shared__ T prod[CAP];
+  __shared__ int p_lds[kRowsPerBlock + 1];
+  __shared__ int wtot[NT / 64];
+  __shared__ double chunks[kMaxChunks];
+  __shared__ double red[NT / 64];
+  const Ref ref = resolve(a);
+  const Task tk = a.tasks[ref.task];
+  RState* st = a.state + ref.task;
+  double sj;
+  if (!open_step(a, tk, st, ref.blk, j, chunks, &sj)) return;
+  const int n = tk.n, r0 = ref.blk * kRowsPerBlock, rows = min(n - r0, kRowsPerBlock);
+  const int blk = tk.blk_begin + ref.blk, tid = threadIdx.x;
+  const T* x = (const T*)a.V + tk.vec_off + (size_t)j * n;
+  T* w_out = (T*)a.W + tk.w_off + r0;
+  const int32_t* rp = a.row_ptr + tk.rowptr_off;
+  if (a.seg_flag[blk] == 0) {
+    const T* va = HAS_VAL ? (const T*)a.values + tk.nnz_off : nullptr;
+    spmv_stream_rows<T, HAS_VAL, NT, CAP>(rp, a.col_idx + tk.nnz_off, va, x, r0, rows, sj, p_lds, prod, w_out, red);
+    return;
+  }
+  const int SEG = a.seg_cols, S = (n + SEG - 1) / SEG;
+  const int e0 = rp[r0], E = rp[r0 + rows] - e0;
+  const uint8_t* cnt = a.seg_cnt + (size_t)blk * a.seg_stride;
+  const uint16_t* pc = a.seg_col + tk.nnz_off + e0;
+  const T* pv = HAS_VAL ? (const T*)a.seg_val + tk.nnz_off + e0 : nullptr;
+  const int rr = 2 * tid;  // the two rows whose counts this thread scans
+  // registers holding the next segment: vector slice, two counts, the first CAP entries
+  T xr[XP];
+  int cr0, cr1;
+  int ec[UE];
+  T ev[UE];
+  auto prefetch = [&](int s, int start) {
+    const int base = s * SEG, len = min(SEG, n - base);
+#pragma unroll
+    for (int u = 0; u < XP; ++u) {
+      const int i = tid + u * NT;
+      xr[u] = i < len ? x[base + i] : (T)0;
+    }
+    cr0 = rr < rows ? cnt[s * rows + rr] : 0;
+    cr1 = rr + 1 < rows ? cnt[s * rows + rr + 1] : 0;
+#pragma unroll
+    for (int u = 0; u < UE; ++u) {
+      const int k = start + tid + u * NT;
+      ec[u] = k < E ? (int)pc[k] : 0;
+      if constexpr (HAS_VAL) ev[u] = k < E ? pv[k] : (T)0;
+    }
+  };
+  prefetch(0, 0);
+  double acc0 = 0.0, acc1 = 0.0;  // rows tid and tid + NT
+  int seg_start = 0;
+  for (int s = 0; s < S; ++s) {
+    // the previous segment's last barrier ordered every read of xs, prod and p_lds before this
+    const int len = min(SEG, n - s * SEG);
+#pragma unroll
+    for (int u = 0; u < XP; ++u) {
+      const int i = tid + u * NT;
+      if (i < len) xs[i] = xr[u];
+    }
+    int ce;
+    const int c0 = cr0;
+    const int ex = block_excl_scan<NT>(cr0 + cr1, wtot, &ce);
+    if (rr < rows) p_lds[rr] = ex;
+    if (rr + 1 < rows) p_lds[rr + 1] = ex + c0;
+    if (tid == 0) p_lds[rows] = ce;
+    int cc[UE];
+    T cv[UE];
+#pragma unroll
+    for (int u = 0; u < UE; ++u) {
+      cc[u] = ec[u];
+      if constexpr (HAS_VAL) cv[u] = ev[u];
+    }
+    __syncthreads();
+    if (s + 1 < S) prefetch(s + 1, seg_start + ce);
+    if (ce <= CAP) {
+#pragma unroll
+      for (int u = 0; u < UE; ++u) {
+        const int k = tid + u * NT;
+        if (k < ce) {
+          const T xv = xs[cc[u]];
+          if constexpr (HAS_VAL) prod[k] = cv[u] * xv; else prod[k] = xv;
+        }
+      }
+      __syncthreads();
+      if (tid < rows) {
+        const int e = p_lds[tid + 1];
+        for (int k = p_lds[tid]; k < e; ++k) acc0 += (double)prod[k];
+      }
+      if (tid + NT < rows) {
+        const int e = p_lds[tid + NT + 1];
+        for (int k = p_lds[tid + NT]; k < e; ++k) acc1 += (double)prod[k];
+      }
+      __syncthreads();
+    } else {
+      // more entries than product slots: row chunks, loads straight from memory
+      int ra = 0;
+      while (ra < rows) {
+        const int k0 = p_lds[ra];
+        int lo = ra + 1, hi = rows;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (p_lds[mid] - k0 <= CAP) lo = mid; else hi = mid - 1;
+        }
+        const int rb = lo, cn = p_lds[rb] - k0;
+        for (int q0 = tid; q0 < cn; q0 += NT * U) {
+          int c[U];
+          T v[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int k = q0 + u * NT;
+            c[u] = k < cn ? (int)pc[seg_start + k0 + k] : 0;
+            if constexpr (HAS_VAL) v[u] = k < cn ? pv[seg_start + k0 + k] : (T)0;
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int k = q0 + u * NT;
+            if (k < cn) {
+              const T xv = xs[c[u]];
+              if constexpr (HAS_VAL) prod[k] = v[u] * xv; else prod[k] = xv;
+            }
+          }
+        }
+        __syncthreads();
+        if (tid >= ra && tid < rb) {
+          const int e = p_lds[tid + 1] - k0;
+          for (int k = p_lds[tid] - k0; k < e; ++k) acc0 += (double)prod[k];
+        }
+        if (tid + NT >= ra && tid + NT < rb) {
+          const int e = p_lds[tid + NT + 1] - k0;
+          for (int k = p_lds[tid + NT] - k0; k < e; ++k) acc1 += (double)prod[k];
+        }
+        __syncthreads();
+        ra = rb;
+      }
+    }
+    seg_start += ce;
+  }
+  if (tid < rows) w_out[tid] = (T)(acc0 * sj);
+  if (tid + NT < rows) w_out[tid + NT] = (T)(acc1 * sj);
+}
+
+template <typename T>
+constexpr size_t seg_static_bytes() {
+  return (size_t)SegShape<T>::CAP * sizeof(T) + (size_t)(kRowsPerBlock + 1) * 4 + (kSegThreads / 64) * 12 +
+         kMaxChunks * 8 + 512;
+}
+
+// Staging capacity (entries) of k_seg_prepare next to smax x kRowsPerBlock 16-bit counters.
+template <typename T, bool HAS_VAL>
+int seg_prepare_cap(int smax) {
+  const size_t fixed = (size_t)(kRowsPerBlock + 1) * 4 + 1024;
+  const size_t cnt = ((size_t)smax * kRowsPerBlock * 2 + 15) / 16 * 16;
+  const size_t per = 4 + (HAS_VAL ? sizeof(T) : 0);
+  const size_t cap = (kLdsBytes - fixed - cnt) / per;
+  return (int)std::min<size_t>(16384, cap / 256 * 256);
+}
+
 // ------------------------------------------------------------------------------- standalone y = A x
 template <typename T, bool HAS_VAL, int L>
 __global__ __launch_bounds__(kBlock) void k_spmv_direct_1(int32_t n, const int32_t* rp, const int32_t* ci,
@@ -462,6 +804,11 @@ hipError_t step_direct(int lanes, int j, const LzArgs& a, int64_t nb, hipStream_
 
 template <typename T, bool HAS_VAL>
 hipError_t step_any(int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
+  if (a.seg_cols > 0) {
+    hipLaunchKernelGGL((k_spmv_seg<T, HAS_VAL>), dim3((unsigned)nb), dim3(kSegThreads),
+                       (size_t)a.seg_cols * sizeof(T), s, a, j);
+    return hipGetLastError();
+  }
   if (a.seglen > 0) {
     hipLaunchKernelGGL((k_spmv_staged<T, HAS_VAL>), dim3((unsigned)nb), dim3(kStagedThreads),
                        (size_t)a.seglen * sizeof(T), s, a, j);
@@ -509,6 +856,51 @@ hipError_t prepare_staged_kernels() {
     return r;
   }();
   return e;
+}
+
+namespace {
+
+template <typename T>
+hipError_t prepare_seg_t() {
+  const size_t dyn = kLdsBytes - seg_static_bytes<T>();
+  const size_t dyn_prep = kLdsBytes - (size_t)(kRowsPerBlock + 1) * 4 - 1024;
+  hipError_t e = allow_lds(k_spmv_seg<T, true>, dyn);
+  if (e == hipSuccess) e = allow_lds(k_spmv_seg<T, false>, dyn);
+  if (e == hipSuccess) e = allow_lds(k_seg_prepare<T, true>, dyn_prep);
+  if (e == hipSuccess) e = allow_lds(k_seg_prepare<T, false>, dyn_prep);
+  return e;
+}
+
+template <typename T, bool HAS_VAL>
+hipError_t seg_prepare_t(const LzArgs& a, int64_t nb, int smax, hipStream_t s) {
+  if (a.seg_stride != smax * kRowsPerBlock) return hipErrorInvalidValue;
+  const int cap = seg_prepare_cap<T, HAS_VAL>(smax);
+  if (cap < 256) return hipErrorInvalidValue;
+  const size_t dyn = ((size_t)smax * kRowsPerBlock * 2 + 15) / 16 * 16 + (size_t)cap * (4 + (HAS_VAL ? sizeof(T) : 0));
+  hipLaunchKernelGGL((k_seg_prepare<T, HAS_VAL>), dim3((unsigned)nb), dim3(kSegThreads), dyn, s, a, cap);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t prepare_seg_kernels() {
+  static hipError_t e = [] {
+    hipError_t r = prepare_seg_t<float>();
+    if (r == hipSuccess) r = prepare_seg_t<double>();
+    return r;
+  }();
+  return e;
+}
+
+int seg_max_cols(int dtype) {
+  return dtype == EBTC_F64 ? SegShape<double>::MAXCOLS : SegShape<float>::MAXCOLS;
+}
+
+hipError_t launch_seg_prepare(int dtype, bool has_val, const LzArgs& a, int64_t nb, int smax, hipStream_t s) {
+  if (smax < 1 || smax > kSegMax || a.seg_cols <= 0) return hipErrorInvalidValue;
+  if (dtype == EBTC_F64)
+    return has_val ? seg_prepare_t<double, true>(a, nb, smax, s) : seg_prepare_t<double, false>(a, nb, smax, s);
+  return has_val ? seg_prepare_t<float, true>(a, nb, smax, s) : seg_prepare_t<float, false>(a, nb, smax, s);
 }
 
 int staged_max_seglen(int dtype) {

@@ -151,11 +151,30 @@ def test_plan_workspace_arithmetic(dtype, es):
     A.lib().ebtc_batch_destroy(h)
 
 
+def test_plan_segmented_workspace_arithmetic():
+    # the column-segmented form appends: block flags (int32), per-(segment, row) counts (8 bits,
+    # max segments x 2048 per block), in-segment columns (16 bits per entry); no value copy for a
+    # pattern-only batch
+    d, keep = make_desc(G=2, nreal=(2, 3), n=(3000, 70), nnz=(10, 10, 10, 10, 10))
+    rc, h = create(d)
+    rc, ws, _ = plan(h, m=30, spmv=4, seg_len=1000)
+    assert rc == 0
+    blocks = 2 * 2 + 3 * 1
+    off = expected_ws(2, (2, 3), (3000, 70), 31, 4, RSTATE_BYTES)
+    off = align(off + 4 * blocks)
+    off = align(off + 3 * 2048 * blocks)
+    off = align(off + 2 * 50)
+    assert ws == off
+    rc, _, _ = plan(h, m=30, spmv=4, seg_len=50)  # 60 segments
+    assert rc == A.EBTC_EINVAL and "segments" in A.lib().ebtc_last_error().decode()
+    A.lib().ebtc_batch_destroy(h)
+
+
 @pytest.mark.parametrize("kw,text", [
     (dict(m=65), "m must be"), (dict(m=-1), "m must be"), (dict(m=0, m_max=0), "m_max"),
     (dict(m=0, tol=0.0), "tol"), (dict(reorth=3), "reorth"), (dict(schedule=9), "schedule"),
     (dict(lanes_per_row=5), "lanes_per_row"), (dict(hub_threshold=-1), "hub_threshold"),
-    (dict(seg_len=-3), "seg_len"),
+    (dict(seg_len=-1), "seg_len"), (dict(spmv=5), "spmv form"), (dict(spmv=-1), "spmv form"),
 ])
 def test_plan_rejects_bad_opts(kw, text):
     d, keep = make_desc()
@@ -203,6 +222,19 @@ def test_component_entry_points_validate():
     assert L.ebtc_tridiag_expv(1, 65, FAKE_DEV, FAKE_DEV, FAKE_DEV, FAKE_DEV, 1, None) == A.EBTC_EINVAL
     assert L.ebtc_tridiag_expv(-1, 5, FAKE_DEV, FAKE_DEV, FAKE_DEV, FAKE_DEV, 1, None) == A.EBTC_EINVAL
     assert L.ebtc_tridiag_expv(0, 5, None, None, None, None, 1, None) == A.EBTC_OK
+
+
+def test_tune_validates_before_any_launch():
+    d, keep = make_desc()
+    rc, h = create(d)
+    o = A.default_opts(m=10)
+    L = A.lib()
+    assert L.ebtc_tune(None, ctypes.byref(o), FAKE_DEV, 1 << 40, None, None, None, None, None) == A.EBTC_EINVAL
+    assert L.ebtc_tune(h, ctypes.byref(o), None, 1 << 40, None, None, None, None, None) == A.EBTC_EINVAL
+    assert L.ebtc_tune(h, ctypes.byref(o), FAKE_DEV, 16, None, None, None, None, None) == A.EBTC_EWORKSPACE
+    o.spmv = 9
+    assert L.ebtc_tune(h, ctypes.byref(o), FAKE_DEV, 1 << 40, None, None, None, None, None) == A.EBTC_EINVAL
+    A.lib().ebtc_batch_destroy(h)
 
 
 def test_last_error_cleared_on_success():

@@ -282,16 +282,17 @@ def test_schedules_agree_bitwise(gpu_lib):
         assert np.array_equal(o, outs[0])  # fixed-order reductions: deterministic across schedules
 
 
-@pytest.mark.parametrize("seg_len,lanes", [(-1, 0), (-1, 8), (3001, 0), (9000, 0)])
-def test_gather_modes_agree(gpu_lib, seg_len, lanes):
-    # staged (auto: one segment) vs direct gathers (-1) vs several staged segments: same step arithmetic
+@pytest.mark.parametrize("form,seg_len,lanes", [("lanes", 0, 0), ("lanes", 0, 16), ("staged", 3001, 0),
+                                                 ("staged", 0, 0)])
+def test_gather_modes_agree(gpu_lib, form, seg_len, lanes):
+    # CSR stream (default) vs lane groups vs LDS-staged in three segments or one: same step arithmetic
     # up to the order of the per-row sums
     torch = torch_mod()
     w = C.scaled(C.workload(1), n=9000, N=3)
     hb = C.build(w)
     b = api().Batch.from_host(hb)
     ref = b.scores(m=w.m)
-    alt = b.scores(m=w.m, seg_len=seg_len, lanes=lanes)
+    alt = b.scores(m=w.m, spmv=form, seg_len=seg_len, lanes=lanes)
     torch.cuda.synchronize()
     r, a = ref.scores.cpu().numpy(), alt.scores.cpu().numpy()
     assert np.max(np.abs(r - a)) <= 1e-6 * np.max(np.abs(r))
@@ -419,3 +420,26 @@ def test_validate_detects_bad_realization(gpu_lib):
     assert b.validate() == 2
     hb2 = DenseBatch([[good, good]], "f64")
     assert api().Batch.from_host(hb2).validate() == -1
+
+
+def test_tuner_choice_used_and_equivalent(gpu_lib):
+    # ebtc_tune times every form on the batch; the auto form then follows the choice (a different
+    # hipGraph key) and its scores match the explicit form's bit for bit
+    torch = torch_mod()
+    w = C.scaled(C.workload(1), n=20000, N=4)
+    hb = C.build(w)
+    b = api().Batch.from_host(hb)
+    before = b.scores(m=w.m)
+    t = b.tune(m=w.m)
+    assert t["form"] in ("stream", "lanes", "staged")
+    assert set(t["ms_per_launch"]) >= {"stream", "lanes4", "lanes8", "lanes16", "lanes32"}
+    assert all(v > 0 for v in t["ms_per_launch"].values())
+    chosen = min(t["ms_per_launch"], key=t["ms_per_launch"].get)
+    assert chosen.startswith(t["form"] if t["form"] != "lanes" else "lanes")
+    auto = b.scores(m=w.m)
+    explicit = b.scores(m=w.m, spmv=t["form"], lanes=t["lanes"], seg_len=t["seg_len"])
+    torch.cuda.synchronize()
+    assert np.array_equal(auto.scores.cpu().numpy(), explicit.scores.cpu().numpy())
+    r = before.scores.cpu().numpy()
+    assert np.max(np.abs(auto.scores.cpu().numpy() - r)) <= 1e-6 * np.max(np.abs(r))
+    check_against_oracle(hb, auto, b, w.m, "f32", K=50)
