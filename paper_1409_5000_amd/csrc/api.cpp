@@ -253,6 +253,10 @@ LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout
     a.seg_cnt = (uint8_t*)(ws + L.off_segcnt);
     a.seg_col = (uint16_t*)(ws + L.off_segcol);
     a.seg_val = b->values ? (void*)(ws + L.off_segval) : nullptr;
+    const int vw = 16 / elem_size(b->dtype);
+    a.seg_vec = 1;
+    for (int32_t g = 0; g < b->G; ++g)
+      if (b->n[g] % vw != 0) a.seg_vec = 0;
   }
   return a;
 }

@@ -91,6 +91,7 @@ struct LzArgs {
   uint8_t* seg_cnt;        // [row blocks][seg_stride] entries of row r in segment s at [s * rows + r]
   uint16_t* seg_col;       // [entries] column - s * seg_cols, a block's entries ordered by (segment, row)
   void* seg_val;           // [entries] values in the same order (nullptr for pattern-only graphs)
+  int32_t seg_vec;         // 1: every n is a multiple of 16 bytes / element size (16-byte slice loads)
 };
 
 // ---- launchers (k_lanczos.hip, k_spmv.hip)

@@ -17,6 +17,7 @@
 // Both write w for their kRowsPerBlock rows with coalesced stores; the dot products run in a
 // separate streaming kernel.
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 
@@ -577,7 +578,38 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
   if (tid == 0) a.seg_flag[blk] = 1;
 }
 
-template <typename T, bool HAS_VAL>
+// Wave-level part of block_excl_scan: inclusive prefix of v within the wave; lane 63 stores the
+// wave total in wtot. The workgroup prefix follows after a barrier (scan_finish).
+__device__ inline int scan_start(int v, int* wtot) {
+  const int lane = threadIdx.x & 63;
+  int inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) wtot[threadIdx.x >> 6] = inc;
+  return inc;
+}
+
+template <int NT>
+__device__ inline int scan_finish(int inc, int v, const int* wtot, int* total) {
+  const int w = threadIdx.x >> 6;
+  int before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    const int t = wtot[i];
+    before += i < w ? t : 0;
+    all += t;
+  }
+  *total = all;
+  return before + inc - v;
+}
+
+// Per segment three barriers: (A) row offsets published, (B) products formed, (C) row sums done and
+// the next segment's vector slice and count scan staged. The loads of segment s + 1 are issued at
+// the top of segment s; the first segment's loads are issued before the step is opened.
+template <typename T, bool HAS_VAL, bool VEC>
 __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
   extern __shared__ __align__(16) unsigned char smem[];
   using SS = SegShape<T>;
@@ -585,44 +617,60 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
   T* xs = (T*)smem;  // [seg_cols]
   __shared__ T prod[CAP];
   __shared__ int p_lds[kRowsPerBlock + 1];
-  __shared__ int wtot[NT / 64];
+  __shared__ int wtot[2][NT / 64];
   __shared__ double chunks[kMaxChunks];
   __shared__ double red[NT / 64];
   const Ref ref = resolve(a);
   const Task tk = a.tasks[ref.task];
   RState* st = a.state + ref.task;
-  double sj;
-  if (!open_step(a, tk, st, ref.blk, j, chunks, &sj)) return;
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, rows = min(n - r0, kRowsPerBlock);
   const int blk = tk.blk_begin + ref.blk, tid = threadIdx.x;
   const T* x = (const T*)a.V + tk.vec_off + (size_t)j * n;
   T* w_out = (T*)a.W + tk.w_off + r0;
   const int32_t* rp = a.row_ptr + tk.rowptr_off;
-  if (a.seg_flag[blk] == 0) {
-    const T* va = HAS_VAL ? (const T*)a.values + tk.nnz_off : nullptr;
-    spmv_stream_rows<T, HAS_VAL, NT, CAP>(rp, a.col_idx + tk.nnz_off, va, x, r0, rows, sj, p_lds, prod, w_out, red);
-    return;
-  }
-  const int SEG = a.seg_cols, S = (n + SEG - 1) / SEG;
+  const int flag = a.seg_flag[blk];
   const int e0 = rp[r0], E = rp[r0 + rows] - e0;
+  const int SEG = a.seg_cols, S = (n + SEG - 1) / SEG;
   const uint8_t* cnt = a.seg_cnt + (size_t)blk * a.seg_stride;
   const uint16_t* pc = a.seg_col + tk.nnz_off + e0;
   const T* pv = HAS_VAL ? (const T*)a.seg_val + tk.nnz_off + e0 : nullptr;
   const int rr = 2 * tid;  // the two rows whose counts this thread scans
   // registers holding the next segment: vector slice, two counts, the first CAP entries
-  T xr[XP];
-  int cr0, cr1;
+  T xr[VEC ? 1 : XP];                   // the slice, element by element
+  typename std::conditional<sizeof(T) == 8, double2, float4>::type xq[VEC ? XP * sizeof(T) / 16 : 1];
+  int cr0 = 0, cr1 = 0;
   int ec[UE];
   T ev[UE];
+  // VEC: 16-byte vector loads and LDS stores for the slice (the host selects it when every
+  // realization's n is a multiple of the vector width, so that x and every segment start are
+  // 16-byte aligned and every segment length is a multiple of it); elements otherwise
+  constexpr int VW = 16 / sizeof(T);
+  using VT = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+  constexpr bool vec = VEC;
+  const bool even = (rows % 2) == 0;  // the two counts of a thread then form one aligned 16-bit word
   auto prefetch = [&](int s, int start) {
     const int base = s * SEG, len = min(SEG, n - base);
+    if constexpr (vec) {
 #pragma unroll
-    for (int u = 0; u < XP; ++u) {
-      const int i = tid + u * NT;
-      xr[u] = i < len ? x[base + i] : (T)0;
+      for (int u = 0; u < XP / VW; ++u) {
+        const int i = (tid + u * NT) * VW;
+        xq[u] = i < len ? *(const VT*)(x + base + i) : VT{};
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < XP; ++u) {
+        const int i = tid + u * NT;
+        xr[u] = i < len ? x[base + i] : (T)0;
+      }
     }
-    cr0 = rr < rows ? cnt[s * rows + rr] : 0;
-    cr1 = rr + 1 < rows ? cnt[s * rows + rr + 1] : 0;
+    if (even) {
+      const uint32_t c2 = rr < rows ? *(const uint16_t*)(cnt + s * rows + rr) : 0u;
+      cr0 = c2 & 0xFF;
+      cr1 = c2 >> 8;
+    } else {
+      cr0 = rr < rows ? cnt[s * rows + rr] : 0;
+      cr1 = rr + 1 < rows ? cnt[s * rows + rr + 1] : 0;
+    }
 #pragma unroll
     for (int u = 0; u < UE; ++u) {
       const int k = start + tid + u * NT;
@@ -630,32 +678,55 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
       if constexpr (HAS_VAL) ev[u] = k < E ? pv[k] : (T)0;
     }
   };
-  prefetch(0, 0);
-  double acc0 = 0.0, acc1 = 0.0;  // rows tid and tid + NT
-  int seg_start = 0;
-  for (int s = 0; s < S; ++s) {
-    // the previous segment's last barrier ordered every read of xs, prod and p_lds before this
+  if (flag) prefetch(0, 0);  // in bounds whatever the step's state; consumed only if the step runs
+  double sj;
+  if (!open_step(a, tk, st, ref.blk, j, chunks, &sj)) return;
+  if (!flag) {
+    const T* va = HAS_VAL ? (const T*)a.values + tk.nnz_off : nullptr;
+    spmv_stream_rows<T, HAS_VAL, NT, CAP>(rp, a.col_idx + tk.nnz_off, va, x, r0, rows, sj, p_lds, prod, w_out, red);
+    return;
+  }
+  // stage segment 0: vector slice, wave part of the count scan, the entries in hand
+  int cc[UE];
+  T cv[UE];
+  int inc, own, c0;
+  auto stage = [&](int s, int buf) {
     const int len = min(SEG, n - s * SEG);
+    if constexpr (vec) {
 #pragma unroll
-    for (int u = 0; u < XP; ++u) {
-      const int i = tid + u * NT;
-      if (i < len) xs[i] = xr[u];
+      for (int u = 0; u < XP / VW; ++u) {
+        const int i = (tid + u * NT) * VW;
+        if (i < len) *(VT*)(xs + i) = xq[u];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < XP; ++u) {
+        const int i = tid + u * NT;
+        if (i < len) xs[i] = xr[u];
+      }
     }
-    int ce;
-    const int c0 = cr0;
-    const int ex = block_excl_scan<NT>(cr0 + cr1, wtot, &ce);
-    if (rr < rows) p_lds[rr] = ex;
-    if (rr + 1 < rows) p_lds[rr + 1] = ex + c0;
-    if (tid == 0) p_lds[rows] = ce;
-    int cc[UE];
-    T cv[UE];
+    c0 = cr0;
+    own = cr0 + cr1;
+    inc = scan_start(own, wtot[buf]);
 #pragma unroll
     for (int u = 0; u < UE; ++u) {
       cc[u] = ec[u];
       if constexpr (HAS_VAL) cv[u] = ev[u];
     }
-    __syncthreads();
+  };
+  stage(0, 0);
+  __syncthreads();
+  double acc0 = 0.0, acc1 = 0.0;  // rows tid and tid + NT
+  int seg_start = 0;
+  for (int s = 0; s < S; ++s) {
+    // (C of the previous segment) published xs, wtot[s & 1]; p_lds and prod are free
+    int ce;
+    const int ex = scan_finish<NT>(inc, own, wtot[s & 1], &ce);
+    if (rr < rows) p_lds[rr] = ex;
+    if (rr + 1 < rows) p_lds[rr + 1] = ex + c0;
+    if (tid == 0) p_lds[rows] = ce;
     if (s + 1 < S) prefetch(s + 1, seg_start + ce);
+    __syncthreads();  // (A)
     if (ce <= CAP) {
 #pragma unroll
       for (int u = 0; u < UE; ++u) {
@@ -665,7 +736,7 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
           if constexpr (HAS_VAL) prod[k] = cv[u] * xv; else prod[k] = xv;
         }
       }
-      __syncthreads();
+      __syncthreads();  // (B)
       if (tid < rows) {
         const int e = p_lds[tid + 1];
         for (int k = p_lds[tid]; k < e; ++k) acc0 += (double)prod[k];
@@ -674,7 +745,6 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
         const int e = p_lds[tid + NT + 1];
         for (int k = p_lds[tid + NT]; k < e; ++k) acc1 += (double)prod[k];
       }
-      __syncthreads();
     } else {
       // more entries than product slots: row chunks, loads straight from memory
       int ra = 0;
@@ -713,11 +783,13 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
           const int e = p_lds[tid + NT + 1] - k0;
           for (int k = p_lds[tid + NT] - k0; k < e; ++k) acc1 += (double)prod[k];
         }
-        __syncthreads();
         ra = rb;
+        if (ra < rows) __syncthreads();  // the next chunk overwrites prod
       }
     }
     seg_start += ce;
+    if (s + 1 < S) stage(s + 1, (s + 1) & 1);  // xs is no longer read: its last reads were before (B)
+    __syncthreads();  // (C)
   }
   if (tid < rows) w_out[tid] = (T)(acc0 * sj);
   if (tid + NT < rows) w_out[tid + NT] = (T)(acc1 * sj);
@@ -805,8 +877,12 @@ hipError_t step_direct(int lanes, int j, const LzArgs& a, int64_t nb, hipStream_
 template <typename T, bool HAS_VAL>
 hipError_t step_any(int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
   if (a.seg_cols > 0) {
-    hipLaunchKernelGGL((k_spmv_seg<T, HAS_VAL>), dim3((unsigned)nb), dim3(kSegThreads),
-                       (size_t)a.seg_cols * sizeof(T), s, a, j);
+    if (a.seg_vec)
+      hipLaunchKernelGGL((k_spmv_seg<T, HAS_VAL, true>), dim3((unsigned)nb), dim3(kSegThreads),
+                         (size_t)a.seg_cols * sizeof(T), s, a, j);
+    else
+      hipLaunchKernelGGL((k_spmv_seg<T, HAS_VAL, false>), dim3((unsigned)nb), dim3(kSegThreads),
+                         (size_t)a.seg_cols * sizeof(T), s, a, j);
     return hipGetLastError();
   }
   if (a.seglen > 0) {
@@ -864,8 +940,10 @@ template <typename T>
 hipError_t prepare_seg_t() {
   const size_t dyn = kLdsBytes - seg_static_bytes<T>();
   const size_t dyn_prep = kLdsBytes - (size_t)(kRowsPerBlock + 1) * 4 - 1024;
-  hipError_t e = allow_lds(k_spmv_seg<T, true>, dyn);
-  if (e == hipSuccess) e = allow_lds(k_spmv_seg<T, false>, dyn);
+  hipError_t e = allow_lds(k_spmv_seg<T, true, true>, dyn);
+  if (e == hipSuccess) e = allow_lds(k_spmv_seg<T, false, true>, dyn);
+  if (e == hipSuccess) e = allow_lds(k_spmv_seg<T, true, false>, dyn);
+  if (e == hipSuccess) e = allow_lds(k_spmv_seg<T, false, false>, dyn);
   if (e == hipSuccess) e = allow_lds(k_seg_prepare<T, true>, dyn_prep);
   if (e == hipSuccess) e = allow_lds(k_seg_prepare<T, false>, dyn_prep);
   return e;

@@ -46,11 +46,14 @@ def assert_bitwise(ref, seg):
     assert np.array_equal(dr["m_used"], ds["m_used"]) and np.array_equal(dr["flags"], ds["flags"])
 
 
-@pytest.mark.parametrize("dtype,seg_len", [("f32", 1000), ("f32", 4096), ("f32", 0), ("f64", 777), ("f64", 0)])
+@pytest.mark.parametrize("dtype,seg_len", [("f32", 500), ("f32", 1000), ("f32", 4096), ("f32", 0), ("f64", 400),
+                                           ("f64", 777), ("f64", 0)])
 @pytest.mark.parametrize("weighted", [False, True])
 def test_segmented_equals_stream_bitwise(gpu_lib, dtype, seg_len, weighted):
-    # n = 9000: four full row blocks and a ragged one of 808 rows; seg_len 1000 / 777 give 9 / 12
-    # segments with a ragged last segment; the defaults give one or two segments
+    # n = 9000: four full row blocks and a ragged one of 808 rows; seg_len 500 / 1000 / 400 / 777
+    # give 18 / 9 / 23 / 12 segments with a ragged last one (500 and 400 keep a segment's entries
+    # within the prefetched product slots, the others take the row-chunk path); the defaults give
+    # one or two segments, row-chunked
     w = dataclasses.replace(C.scaled(C.workload(1), n=9000, N=3), dtype=dtype)
     hb = C.build(w, with_values=weighted)
     if weighted:
@@ -59,6 +62,17 @@ def test_segmented_equals_stream_bitwise(gpu_lib, dtype, seg_len, weighted):
     assert_bitwise(ref, seg)
     if seg_len == 0:
         check_against_oracle(hb, seg, b, w.m, dtype, K=50)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_segmented_large_segments_prefetched_bitwise(gpu_lib, dtype):
+    # n = 40000, degree 8: the default segment (16384 FP32 / 8192 FP64 columns, 1024 threads) holds
+    # about 3.4k-6.7k entries of a row block, within the prefetched product slots
+    spec = C.er_spec(40000, 8.0, target="er", t=50, int_p=4 / 49, N=2, K=50)
+    w = C.Workload(92, "segmented-large", (spec,), dtype, 20)
+    hb = C.build(w)
+    b, ref, seg = run_pair(hb, w.m)
+    assert_bitwise(ref, seg)
 
 
 def test_segmented_fallback_blocks_bitwise(gpu_lib):
