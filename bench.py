@@ -32,7 +32,8 @@ if ROOT not in sys.path:
 METRIC = "graph-realizations/s for Krylov exp(A)·1 + achieved HBM GB/s; batched vs plain"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c1.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1409_5000_amd", "csrc", f) for f in ("k_lanczos.hip", "internal.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1409_5000_amd", "csrc", f)
+                  for f in ("k_lanczos.hip", "k_spmv.hip", "device_common.h", "internal.h")]
 
 
 def log(msg: str) -> None:
@@ -101,7 +102,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (realizations and graphs "
-              "are independent, so a multi-GPU run would shard them; this build runs on one GPU).", file=sys.stderr)
+              "are independent, so several GPUs would shard them; this benchmark runs on one GPU).", file=sys.stderr)
         return 2
 
     import numpy as np
@@ -130,24 +131,25 @@ def main() -> int:
     has_val = hb.values is not None
     K = hb.K
 
-    if args.profile_run:
-        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)  # calibration: reads and writes exactly 1 GiB
-        out = {}
-        for label, form in (("stream", "stream"), ("lane_groups", "lanes"), ("lds_staged", "staged"),
-                            ("column_segmented", "segmented")):
-            rr = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=False, diag=False, spmv=form)
-            out[label] = rr.profile()
-        torch.cuda.synchronize()
-        print(json.dumps({"profile_run": w.name, "realizations": hb.R, "phases": out}), flush=True)
-        return 0
-
     form = {"spmv": "auto" if args.spmv == "tuned" else args.spmv, "lanes": args.lanes, "seg_len": args.seg_len}
     tuned = None
     if args.spmv == "tuned":
         tuned = b.tune(m=m, tol=tol, m_max=m_max)
         log(f"tuned SpMV form: {tuned}")
+
+    if args.profile_run:
+        # for counter runs: a 1 GiB device copy (calibration of the byte counters), then one eager
+        # batched pass in the configuration the timed steps use
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)  # reads and writes exactly 1 GiB
+        torch.cuda.synchronize()
+        rr = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=False, diag=False, **form)
+        ph = rr.profile()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": w.name, "realizations": hb.R, "spmv_form": tuned or form, "phases": ph}),
+              flush=True)
+        return 0
     run = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=True, diag=True, **form)
 
     def step(r):

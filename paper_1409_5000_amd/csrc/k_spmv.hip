@@ -578,6 +578,20 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
   if (tid == 0) a.seg_flag[blk] = 1;
 }
 
+// Raw buffer resource over [p, p + bytes): loads through it take 32-bit byte offsets and return 0
+// past the end.
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ inline T load_elem(__amdgpu_buffer_rsrc_t r, int i) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8, 0, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, 0));
+}
+
 // Wave-level part of block_excl_scan: inclusive prefix of v within the wave; lane 63 stores the
 // wave total in wtot. The workgroup prefix follows after a barrier (scan_finish).
 __device__ inline int scan_start(int v, int* wtot) {
@@ -635,47 +649,50 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
   const uint16_t* pc = a.seg_col + tk.nnz_off + e0;
   const T* pv = HAS_VAL ? (const T*)a.seg_val + tk.nnz_off + e0 : nullptr;
   const int rr = 2 * tid;  // the two rows whose counts this thread scans
+  // Buffer resources (scalar registers) over the block's entries, its counts and the vector: loads
+  // take 32-bit byte offsets, and an offset past the end reads 0, which is what every guard wants.
+  const __amdgpu_buffer_rsrc_t r_pc = make_rsrc(pc, 2 * E);
+  const __amdgpu_buffer_rsrc_t r_pv = make_rsrc(pv, HAS_VAL ? (int)sizeof(T) * E : 0);
+  const __amdgpu_buffer_rsrc_t r_cnt = make_rsrc(cnt, S * rows);
+  const __amdgpu_buffer_rsrc_t r_x = make_rsrc(x, (int)sizeof(T) * n);
   // registers holding the next segment: vector slice, two counts, the first CAP entries
-  T xr[VEC ? 1 : XP];                   // the slice, element by element
-  typename std::conditional<sizeof(T) == 8, double2, float4>::type xq[VEC ? XP * sizeof(T) / 16 : 1];
+  // VEC: 16-byte slice loads and LDS stores (the host selects it when every realization's n is a
+  // multiple of the vector width, so that every segment start and length is one too)
+  constexpr int VW = 16 / sizeof(T);
+  using VT = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+  T xr[VEC ? 1 : XP];
+  VT xq[VEC ? XP / VW : 1];
   int cr0 = 0, cr1 = 0;
   int ec[UE];
   T ev[UE];
-  // VEC: 16-byte vector loads and LDS stores for the slice (the host selects it when every
-  // realization's n is a multiple of the vector width, so that x and every segment start are
-  // 16-byte aligned and every segment length is a multiple of it); elements otherwise
-  constexpr int VW = 16 / sizeof(T);
-  using VT = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
-  constexpr bool vec = VEC;
-  const bool even = (rows % 2) == 0;  // the two counts of a thread then form one aligned 16-bit word
   auto prefetch = [&](int s, int start) {
     const int base = s * SEG, len = min(SEG, n - base);
-    if constexpr (vec) {
+    if constexpr (VEC) {
 #pragma unroll
       for (int u = 0; u < XP / VW; ++u) {
-        const int i = (tid + u * NT) * VW;
-        xq[u] = i < len ? *(const VT*)(x + base + i) : VT{};
+        const int i = (tid + u * NT) * VW;  // past the segment: the next one's or zeros, never stored
+        xq[u] = __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b128(r_x, (base + i) * (int)sizeof(T), 0, 0));
       }
     } else {
 #pragma unroll
       for (int u = 0; u < XP; ++u) {
         const int i = tid + u * NT;
-        xr[u] = i < len ? x[base + i] : (T)0;
+        xr[u] = i < len ? load_elem<T>(r_x, base + i) : (T)0;
       }
     }
-    if (even) {
-      const uint32_t c2 = rr < rows ? *(const uint16_t*)(cnt + s * rows + rr) : 0u;
+    if ((rows & 1) == 0) {  // an even row count keeps the pair 2-byte aligned
+      const uint32_t c2 = rr < rows ? __builtin_amdgcn_raw_buffer_load_b16(r_cnt, s * rows + rr, 0, 0) : 0u;
       cr0 = c2 & 0xFF;
       cr1 = c2 >> 8;
     } else {
-      cr0 = rr < rows ? cnt[s * rows + rr] : 0;
-      cr1 = rr + 1 < rows ? cnt[s * rows + rr + 1] : 0;
+      cr0 = rr < rows ? __builtin_amdgcn_raw_buffer_load_b8(r_cnt, s * rows + rr, 0, 0) : 0;
+      cr1 = rr + 1 < rows ? __builtin_amdgcn_raw_buffer_load_b8(r_cnt, s * rows + rr + 1, 0, 0) : 0;
     }
 #pragma unroll
     for (int u = 0; u < UE; ++u) {
       const int k = start + tid + u * NT;
-      ec[u] = k < E ? (int)pc[k] : 0;
-      if constexpr (HAS_VAL) ev[u] = k < E ? pv[k] : (T)0;
+      ec[u] = __builtin_amdgcn_raw_buffer_load_b16(r_pc, 2 * k, 0, 0);
+      if constexpr (HAS_VAL) ev[u] = load_elem<T>(r_pv, k);
     }
   };
   if (flag) prefetch(0, 0);  // in bounds whatever the step's state; consumed only if the step runs
@@ -692,7 +709,7 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
   int inc, own, c0;
   auto stage = [&](int s, int buf) {
     const int len = min(SEG, n - s * SEG);
-    if constexpr (vec) {
+    if constexpr (VEC) {
 #pragma unroll
       for (int u = 0; u < XP / VW; ++u) {
         const int i = (tid + u * NT) * VW;
