@@ -77,8 +77,8 @@ def run_gpu(hb, **kw):
     return b, out
 
 
-def check_against_oracle(hb, out, b, m, tol_key, K=None, tol=0.0, m_max=60, reorth_ref=2, check_m=True):
-    ref = oscores.batch_scores(hb, m=m, tol=tol, m_max=m_max, reorth=reorth_ref)
+def check_against_oracle(hb, out, b, m, tol_key, K=None, tol=0.0, m_max=60, reorth_ref=2, check_m=True, workers=1):
+    ref = oscores.batch_scores(hb, m=m, tol=tol, m_max=m_max, reorth=reorth_ref, workers=workers)
     s_all = out.scores.double().cpu().numpy()
     ls = out.log_scale.cpu().numpy()
     diag = out.diag_numpy()
