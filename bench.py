@@ -96,6 +96,8 @@ def main() -> int:
     ap.add_argument("--lanes", type=int, default=0, help="lane-group form: lanes per row (0 = 8)")
     ap.add_argument("--seg-len", type=int, default=0, help="LDS-staged form: segment length (0 = largest)")
     ap.add_argument("--realizations", type=int, default=0, help="limit realizations per graph (0 = all)")
+    ap.add_argument("--oracle-graphs", type=int, default=0,
+                    help="oracle (cpu_baseline and parity) on the first G graphs only (0 = all)")
     ap.add_argument("--adjoint", action="store_true", help="also time the adjoint (always on for workload 3)")
     ap.add_argument("--profile-run", action="store_true",
                     help="for rocprofv3: one eager batched pass per gather form plus a 1 GiB copy (counter calibration)")
@@ -123,7 +125,10 @@ def main() -> int:
 
     w = C.workload(args.config)
     t0 = time.time()
-    hb = C.build_parallel(w, workers=workers, realizations=args.realizations or None)
+    # the uneven workload (about 1e10 entries) is unweighted and carried as a pattern (values NULL =
+    # all ones, FP32 arithmetic), which halves its host and device footprint
+    hb = C.build_parallel(w, workers=workers, realizations=args.realizations or None, with_values=w.ci != 4,
+                          progress=lambda i, t: log(f"generated {i}/{t} realizations ({time.time() - t0:.0f}s)"))
     log(f"generated {w.name}: R={hb.R} nnz={hb.nnz_off[-1]} in {time.time() - t0:.1f}s")
     m, tol, m_max = w.m, (w.tol or 1e-6), (w.m_max or 60)
     b = api.Batch.from_host(hb)
@@ -288,19 +293,22 @@ def main() -> int:
 
     if not args.no_cpu_baseline:
         from oracle import scores as oscores
+        G_or = args.oracle_graphs or int(hb.n.size)
+        reals = [r for r in range(hb.R) if int(hb.graph_of[r]) < G_or]
         t0 = time.perf_counter()
-        ref = oscores.batch_scores(hb, m=m, tol=w.tol, m_max=m_max, workers=P)
+        ref = oscores.batch_scores(hb, m=m, tol=w.tol, m_max=m_max, workers=P, realizations=reals)
         cpu_wall = time.perf_counter() - t0
-        result["cpu_baseline"] = {"value": round(hb.R / cpu_wall, 3), "unit": "graph-realizations/s", "cores": P,
-                                  "kind": "oracle",
-                                  "sample": f"all {hb.R} realizations of {w.name}, FP64 Lanczos (CGS2), "
+        what = f"all {hb.R} realizations" if len(reals) == hb.R else f"the {len(reals)} realizations of the first {G_or} graphs"
+        result["cpu_baseline"] = {"value": round(len(reals) / cpu_wall, 3), "unit": "graph-realizations/s",
+                                  "cores": P, "kind": "oracle",
+                                  "sample": f"{what} of {w.name}, FP64 Lanczos (CGS2), "
                                             f"{P} single-threaded worker processes, {cpu_wall:.1f}s wall"}
         errs = []
         top_ok = True
         idx_all, _ = b.topk(run.scores, K)
         idx_all = idx_all.cpu().numpy()
-        off = 0
-        for g, gsc in enumerate(ref):
+        koff = np.concatenate([[0], np.cumsum(K)])
+        for g, gsc in enumerate(ref):  # graphs 0 .. G_or - 1, in order
             sl = b.graph_slice(g)
             s_hat = gpu_scores[sl] * np.exp(gpu_ls[g] - gsc.log_scale)
             en = float(np.max(np.abs(s_hat - gsc.s)) / np.max(np.abs(gsc.s)))
@@ -308,8 +316,8 @@ def main() -> int:
             top2 = oscores.topk(gsc.s, min(2 * kk, gsc.s.size))
             et = float(np.max(np.abs(s_hat[top2] - gsc.s[top2]) / np.abs(gsc.s[top2])))
             errs.append((en, et))
+            off = int(koff[g])
             top_ok &= set(idx_all[off:off + kk].tolist()) == set(oscores.topk(gsc.s, kk).tolist())
-            off += kk
         result["parity"] = {"err_norm_max": max(e[0] for e in errs), "err_top_max": max(e[1] for e in errs),
                             "topk_sets_identical": bool(top_ok), "tolerance": 1e-5 if w.dtype == "f32" else 1e-12}
         log(f"oracle: {cpu_wall:.1f}s on {P} cores; parity {result['parity']}")

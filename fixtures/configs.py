@@ -29,7 +29,7 @@ class GraphSpec:
     family: str          # "er" | "ws" | "ba"
     n: int
     bg: float            # ER: edge probability p; WS: lattice degree k; BA: edges per new node m
-    target: str = "er"   # "er" (fixed random pattern) or "clique"
+    target: str = "er"   # "er" (fixed random pattern), "sparse" (connected, hubs of degree 4) or "clique"
     t: int = 10          # target size
     int_p: float = 0.3   # internal edge probability of an "er" target pattern
     N: int = 1           # background realizations
@@ -115,6 +115,8 @@ def draw_graph(ci: int, g: int, spec: GraphSpec) -> GraphDraw:
     targets = rng.choice(spec.n, size=spec.t, replace=False).astype(np.int64)
     if spec.target == "clique":
         pattern = G.complete_pattern(spec.t)
+    elif spec.target == "sparse":  # int_p carries the average internal degree; hubs of degree 4
+        pattern = G.sparse_target_keys(spec.t, int(round(spec.int_p * spec.t / 2)), 4, rng)
     else:
         pattern = G.er_keys(spec.t, spec.int_p, rng)
     return GraphDraw(spec, targets, pattern)
@@ -213,8 +215,9 @@ def _gen_one(args):
 
 
 def build_parallel(w: Workload, workers: int = 8, with_values: bool = True,
-                   realizations: int | None = None) -> HostBatch:
-    """build() with the realizations generated by a process pool (same seeds, same result)."""
+                   realizations: int | None = None, progress=None) -> HostBatch:
+    """build() with the realizations generated by a process pool (same seeds, same result).
+    progress(done, total), if given, is called after every twentieth of the realizations."""
     import multiprocessing as mp
     draws = [draw_graph(w.ci, g, spec) for g, spec in enumerate(w.graphs)]
     jobs = []
@@ -222,8 +225,13 @@ def build_parallel(w: Workload, workers: int = 8, with_values: bool = True,
         N = spec.N if realizations is None else min(spec.N, realizations)
         jobs += [(w.ci, g, k, d) for k in range(N)]
     if workers > 1 and len(jobs) > 1:
+        out = []
+        every = max(1, len(jobs) // 20)
         with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
-            out = pool.map(_gen_one, jobs, chunksize=1)
+            for i, res in enumerate(pool.imap(_gen_one, jobs, chunksize=1)):
+                out.append(res)
+                if progress is not None and (i + 1) % every == 0:
+                    progress(i + 1, len(jobs))
     else:
         out = [_gen_one(j) for j in jobs]
     parts = []

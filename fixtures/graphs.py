@@ -130,6 +130,43 @@ def complete_pattern(t: int) -> np.ndarray:
     return canon(a, b, t)
 
 
+def sparse_target_keys(t: int, edges: int, max_deg: int, rng: np.random.Generator) -> np.ndarray:
+    """A connected t-node pattern with exactly `edges` edges, every degree <= max_deg and at least one
+    node of degree max_deg (the sparse target of the multiple-backgrounds experiments: 20 nodes,
+    average degree 2.1, hubs of degree 4; its exact topology is not published). A random tree grown
+    by attaching nodes, in random order, to a uniform earlier node below the cap; then uniform extra
+    edges below the cap; redrawn until some node reaches the cap."""
+    if not (t - 1 <= edges <= t * max_deg // 2):
+        raise ValueError("edge count out of range")
+    while True:
+        deg = np.zeros(t, np.int64)
+        order = rng.permutation(t)
+        keys = set()
+        ok = True
+        for idx in range(1, t):
+            a = int(order[idx])
+            cand = [int(b) for b in order[:idx] if deg[b] < max_deg]
+            if not cand:
+                ok = False
+                break
+            b = cand[int(rng.integers(len(cand)))]
+            keys.add(min(a, b) * t + max(a, b))
+            deg[a] += 1
+            deg[b] += 1
+        tries = 0
+        while ok and len(keys) < edges and tries < 10000:
+            tries += 1
+            a, b = (int(v) for v in rng.integers(0, t, size=2))
+            k = min(a, b) * t + max(a, b)
+            if a == b or k in keys or deg[a] >= max_deg or deg[b] >= max_deg:
+                continue
+            keys.add(k)
+            deg[a] += 1
+            deg[b] += 1
+        if ok and len(keys) == edges and deg.max() == max_deg:
+            return np.array(sorted(keys), np.int64)
+
+
 def embed(bg: np.ndarray, n: int, targets: np.ndarray, pattern_local: np.ndarray) -> np.ndarray:
     """Remove background edges inside the target set and add the fixed target pattern."""
     t = targets.size

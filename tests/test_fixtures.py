@@ -103,3 +103,36 @@ def test_host_batch_offsets():
     for r in range(b.R):
         n, rp, ci, v = b.csr(r)
         assert rp[0] == 0 and rp[-1] == ci.size and v.dtype == np.float64
+
+
+def test_sparse_target_pattern_statistics():
+    # connected, exactly 21 edges on 20 nodes (average degree 2.1), degrees <= 4 with a hub of 4
+    for s in range(20):
+        keys = G.sparse_target_keys(20, 21, 4, G.rng_for(300, s, 0))
+        a, b = keys // 20, keys % 20
+        assert keys.size == 21 and np.all(a < b)
+        deg = np.bincount(np.concatenate([a, b]), minlength=20)
+        assert deg.max() == 4 and deg.min() >= 1
+        seen, stack = {0}, [0]
+        adj = {i: set() for i in range(20)}
+        for i, j in zip(a.tolist(), b.tolist()):
+            adj[i].add(j)
+            adj[j].add(i)
+        while stack:
+            for v in adj[stack.pop()]:
+                if v not in seen:
+                    seen.add(v)
+                    stack.append(v)
+        assert len(seen) == 20
+
+
+def test_identification_rate_bookkeeping():
+    from paper_1409_5000_amd import idrate
+    idx = np.array([3, 1, 2, 9, 8, 7])  # K = 3 per run
+    rates = idrate.run_rates(idx, [np.array([1, 2, 3]), np.array([7, 10, 11])], 3)
+    assert np.allclose(rates, [1.0, 1 / 3])
+    w = idrate.column_workload(idrate.COLUMNS[0], 5, 11)
+    assert len(w.graphs) == 5 and w.graphs[0].N == 40 and w.graphs[0].target == "sparse"
+    assert abs(w.graphs[0].bg * 1023 - 2.0) < 1e-12
+    hb = C.build(idrate.column_workload(idrate.COLUMNS[10], 2, 12), with_values=False)
+    assert [t.size for t in hb.targets] == [20, 20] and not np.array_equal(hb.targets[0], hb.targets[1])
