@@ -208,6 +208,25 @@ int ebtc_spmv(int32_t dtype, int32_t n, const int32_t* row_ptr, const int32_t* c
 int ebtc_tridiag_expv(int32_t count, int32_t k, const double* alpha, const double* beta, double* y_out,
                       double* theta_out, int32_t shift, void* stream);
 
+/* ---------------------------------------------------------------- subgraph centrality            */
+/* Subgraph centrality SC(i) = [exp(A)]_ii (eq. 3) of selected nodes of one graph, by the Gauss
+ * quadrature rule of the m-step Lanczos process started at e_i: SC(i) ~ e1^T exp(T_m) e1 = e^{theta*}
+ * y_0 (theta* = lambda_max(T_m), y = exp(T_m - theta* I) e1 in FP64). The m-point rule bounds SC(i)
+ * from below and is exact once the Krylov space of e_i closes (breakdown stops the process there).
+ * Every node's process is one realization of a batched launch over the same CSR (stream SpMV form,
+ * one classical Gram-Schmidt pass), so the cost is that of `count` realizations of m steps.
+ *   dtype, n, row_ptr, col_idx, values  the graph, device CSR as for ebtc_spmv (values NULL = ones)
+ *   count, nodes   device int32 [count] node ids; an id outside [0, n) yields NaN
+ *   m              Krylov dimension, 1..EBTC_M_LIMIT
+ *   sc_out         device double [count]
+ *   ws, ws_bytes   device workspace of ebtc_subgraph_centrality_ws_bytes() bytes, 256-byte aligned
+ * Synchronises `stream` once (after uploading its task table), then enqueues the rest
+ * asynchronously. Errors: EINVAL, EWORKSPACE, ENOTSUPPORTED (too many row blocks), EHIP. */
+int ebtc_subgraph_centrality_ws_bytes(int32_t dtype, int32_t n, int32_t count, int32_t m, size_t* ws_bytes);
+int ebtc_subgraph_centrality(int32_t dtype, int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                             const void* values, int32_t count, const int32_t* nodes, int32_t m, double* sc_out,
+                             void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- autotuning                     */
 /* Times the SpMV forms on this batch with HIP events -- the CSR stream, lane groups of 4, 8, 16 and
  * 32 lanes per row, and the LDS-staged form when the largest vector passes through LDS in at most

@@ -24,7 +24,7 @@ EXPORTED = [
     "ebtc_version", "ebtc_status_str", "ebtc_last_error", "ebtc_default_opts", "ebtc_batch_create",
     "ebtc_batch_destroy", "ebtc_plan", "ebtc_scores", "ebtc_topk_ws_bytes", "ebtc_topk", "ebtc_spmv",
     "ebtc_tridiag_expv", "ebtc_validate_ws_bytes", "ebtc_validate", "ebtc_profile_phases", "ebtc_plan_backward",
-    "ebtc_scores_backward", "ebtc_tune",
+    "ebtc_scores_backward", "ebtc_tune", "ebtc_subgraph_centrality_ws_bytes", "ebtc_subgraph_centrality",
 ]
 SPMV_FORMS = {"auto": 0, "stream": 1, "lanes": 2, "staged": 3, "segmented": 4}
 PHASES = ["start", "spmv", "dots", "update", "tridiag", "combine", "sum", "prepare"]
@@ -88,6 +88,8 @@ def lib() -> ctypes.CDLL:
         "ebtc_scores_backward": (c_int, [vp, POINTER(Opts), vp, vp, vp, vp, sz, vp]),
         "ebtc_tune": (c_int, [vp, POINTER(Opts), vp, sz, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
                               POINTER(c_double), vp]),
+        "ebtc_subgraph_centrality_ws_bytes": (c_int, [c_int32, c_int32, c_int32, c_int32, POINTER(sz)]),
+        "ebtc_subgraph_centrality": (c_int, [c_int32, c_int32, vp, vp, vp, c_int32, vp, c_int32, vp, vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -234,6 +234,23 @@ def spmv(row_ptr: torch.Tensor, col_idx: torch.Tensor, values: torch.Tensor | No
     return y
 
 
+def subgraph_centrality(row_ptr: torch.Tensor, col_idx: torch.Tensor, values: torch.Tensor | None,
+                        nodes, m: int = 20, dtype: str = "f32") -> torch.Tensor:
+    """[exp(A)]_ii for the given nodes of one graph (device CSR), by the m-point Gauss rule of the
+    Lanczos process started at e_i (eq. 3); FP64 results on the device."""
+    code = _DT[dtype][0]
+    n = int(row_ptr.numel()) - 1
+    dev = row_ptr.device
+    nd = torch.as_tensor(np.asarray(nodes, dtype=np.int32)).to(dev)
+    ws = ctypes.c_size_t()
+    A.check(A.lib().ebtc_subgraph_centrality_ws_bytes(code, n, int(nd.numel()), m, ctypes.byref(ws)))
+    wst = torch.empty(max(1, ws.value), dtype=torch.uint8, device=dev)
+    out = torch.empty(int(nd.numel()), dtype=torch.float64, device=dev)
+    A.check(A.lib().ebtc_subgraph_centrality(code, n, _vp(row_ptr), _vp(col_idx), _vp(values), int(nd.numel()),
+                                             _vp(nd), m, _vp(out), _vp(wst), ws.value, current_stream()))
+    return out
+
+
 def tridiag_expv(alpha: torch.Tensor, beta: torch.Tensor, shift: bool = True) -> tuple[torch.Tensor, torch.Tensor]:
     """For a [count, k] stack of FP64 tridiagonals: (y = exp(T - theta I) e1 [count, k], theta [count])."""
     count, k = alpha.shape

@@ -810,6 +810,95 @@ int ebtc_scores_backward(ebtc_batch* b, const ebtc_opts* o, const double* log_sc
   return EBTC_OK;
 }
 
+// One graph, `count` Lanczos processes over its CSR (every task shares the graph's arrays).
+namespace {
+void shared_batch(ebtc_batch& b, int32_t dtype, int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                  const void* values, int32_t count) {
+  b.dtype = dtype;
+  b.G = 1;
+  b.R = count;
+  b.n = {n};
+  b.nreal = {count};
+  b.first = {0};
+  b.rowptr_off.assign(count, 0);
+  b.nnz_off.assign((size_t)count + 1, 0);
+  b.score_off = {0, n};
+  b.row_ptr = row_ptr;
+  b.col_idx = col_idx;
+  b.values = values;
+  b.total_scores = n;
+  b.total_rows = (int64_t)n * count;
+  b.n_max = n;
+  b.graphs.resize(1);
+  b.graphs[0] = GraphInfo{0, n, 0, count, 0};
+}
+
+int check_sc_args(int32_t dtype, int32_t n, int32_t count, int32_t m) {
+  if (dtype != EBTC_F32 && dtype != EBTC_F64) return fail(EBTC_EINVAL, "dtype must be EBTC_F32 or EBTC_F64");
+  if (n < 1) return fail(EBTC_EINVAL, "n must be >= 1");
+  if (count < 1) return fail(EBTC_EINVAL, "count must be >= 1");
+  if (m < 1 || m > EBTC_M_LIMIT) return fail(EBTC_EINVAL, "m must be in [1, 64]");
+  if ((int64_t)count * ((n + kRowsPerBlock - 1) / kRowsPerBlock) >= ((int64_t)1 << 31))
+    return fail(EBTC_ENOTSUPPORTED, "too many row blocks for one launch");
+  return EBTC_OK;
+}
+
+ebtc_opts sc_opts(int32_t m) {
+  ebtc_opts o;
+  ebtc_default_opts(&o);
+  o.m = m;
+  o.reorth = 1;
+  o.schedule = EBTC_SCHED_BATCHED;
+  o.use_hipgraph = 0;
+  o.spmv = EBTC_SPMV_STREAM;
+  return o;
+}
+}  // namespace
+
+int ebtc_subgraph_centrality_ws_bytes(int32_t dtype, int32_t n, int32_t count, int32_t m, size_t* ws_bytes) {
+  g_err.clear();
+  if (!ws_bytes) return fail(EBTC_EINVAL, "NULL output");
+  int rc = check_sc_args(dtype, n, count, m);
+  if (rc) return rc;
+  ebtc_batch b;
+  shared_batch(b, dtype, n, nullptr, nullptr, nullptr, count);
+  const ebtc_opts o = sc_opts(m);
+  *ws_bytes = make_layout(&b, &o, spmv_plan(&b, &o)).total;
+  return EBTC_OK;
+}
+
+int ebtc_subgraph_centrality(int32_t dtype, int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                             const void* values, int32_t count, const int32_t* nodes, int32_t m, double* sc_out,
+                             void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int rc = check_sc_args(dtype, n, count, m);
+  if (rc) return rc;
+  if (!row_ptr || !col_idx || !nodes || !sc_out || !ws)
+    return fail(EBTC_EINVAL, "NULL row_ptr, col_idx, nodes, output or workspace");
+  ebtc_batch b;
+  shared_batch(b, dtype, n, row_ptr, col_idx, values, count);
+  const ebtc_opts o = sc_opts(m);
+  const SpmvPlan sp = spmv_plan(&b, &o);
+  const Layout L = make_layout(&b, &o, sp);
+  if (ws_bytes < L.total)
+    return fail(EBTC_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(L.total));
+  if (((uintptr_t)ws & 255) != 0) return fail(EBTC_EINVAL, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  rc = upload_tables(&b, w, L, s);
+  if (rc) return rc;
+  // the task table lives on this call's stack: wait until the copy has read it
+  EBTC_HIP(hipStreamSynchronize(s));
+  LzArgs a = make_args(&b, &o, w, L, sp);
+  EBTC_LAUNCH(launch_blkmap(a.tasks, b.R, (int32_t*)(w + L.off_blkmap), s));
+  EBTC_LAUNCH(launch_start_unit(dtype, a, nodes, L.total_blocks, s));
+  rc = run_steps(&b, &o, a, L.total_blocks, 0, b.R, sp.lanes, s, nullptr, false);
+  if (rc) return rc;
+  EBTC_LAUNCH(launch_tridiag_state(a, 0, b.R, 0, 0, m, 1, 0.0, nullptr, nullptr, s));
+  EBTC_LAUNCH(launch_sc_out(a.state, a.tasks, nodes, b.R, sc_out, s));
+  return EBTC_OK;
+}
+
 int ebtc_topk_ws_bytes(ebtc_batch* b, size_t* ws_bytes) {
   g_err.clear();
   if (!b || !ws_bytes) return fail(EBTC_EINVAL, "NULL batch or output");

@@ -97,6 +97,10 @@ struct LzArgs {
 // ---- launchers (k_lanczos.hip, k_spmv.hip)
 hipError_t launch_blkmap(const Task* tasks, int64_t R, int32_t* blkmap, hipStream_t s);
 hipError_t launch_start(int dtype, const LzArgs& a, int64_t nblocks, hipStream_t s);
+// Subgraph centrality: processes started at e_{nodes[r]}, and SC = e^{theta} y_0 per process.
+hipError_t launch_start_unit(int dtype, const LzArgs& a, const int32_t* nodes, int64_t nblocks, hipStream_t s);
+hipError_t launch_sc_out(const RState* state, const Task* tasks, const int32_t* nodes, int64_t count, double* out,
+                         hipStream_t s);
 // Phase A: the SpMV kernel (column-segmented when a.seg_cols > 0, LDS-staged when a.seglen > 0, else
 // the CSR stream for lanes == 0 and lane groups otherwise).
 hipError_t launch_spmv_step(int dtype, bool has_val, int lanes, int j, const LzArgs& a, int64_t nblocks,

@@ -187,6 +187,40 @@ __global__ __launch_bounds__(kBlock) void k_start(LzArgs a) {
   }
 }
 
+// Start of the Gauss-quadrature processes of subgraph centrality: task r starts at e_{nodes[r]}
+// (raw basis vector 0 = e_i with scale s_0 = 1, beta0 = ||e_i|| = 1). A node id outside [0, n)
+// leaves v_0 = 0, which the first step closes as a breakdown; k_sc_out reports it as NaN.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_start_unit(LzArgs a, const int32_t* nodes) {
+  const Ref ref = resolve(a);
+  const Task tk = a.tasks[ref.task];
+  const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
+  const int node = nodes[ref.task];
+  T* v0 = (T*)a.V + tk.vec_off;
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) v0[r] = r == node ? (T)1 : (T)0;
+  if (ref.blk == 0 && threadIdx.x == 0) {
+    RState* st = a.state + ref.task;
+    st->beta0 = 1.0;
+    st->s[0] = 1.0;
+    st->theta = 0.0;
+    st->est = 0.0;
+    st->m_used = 0;
+    st->flags = 0;
+    st->done = 0;
+  }
+}
+
+// SC(i) ~ e1^T exp(T) e1 = e^{theta*} y_0 (eq. 3 by the Gauss rule of the process started at e_i).
+__global__ __launch_bounds__(kBlock) void k_sc_out(const RState* state, const Task* tasks, const int32_t* nodes,
+                                                   int64_t count, double* out) {
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= count) return;
+  const RState* st = state + r;
+  const int node = nodes[r];
+  const bool ok = node >= 0 && node < tasks[r].n && st->m_used >= 1;
+  out[r] = ok ? exp(st->theta) * st->y[0] : __builtin_nan("");
+}
+
 // u = beta0 * sum_i y_i v_i = sum_i (beta0 y_i s_i) Vraw_i, so exp(A) 1 ~ e^{theta*} u.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_combine(LzArgs a) {
@@ -291,6 +325,21 @@ hipError_t launch_start(int dtype, const LzArgs& a, int64_t nb, hipStream_t s) {
     hipLaunchKernelGGL(k_start<double>, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
   else
     hipLaunchKernelGGL(k_start<float>, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_start_unit(int dtype, const LzArgs& a, const int32_t* nodes, int64_t nb, hipStream_t s) {
+  if (dtype == EBTC_F64)
+    hipLaunchKernelGGL(k_start_unit<double>, dim3((unsigned)nb), dim3(kBlock), 0, s, a, nodes);
+  else
+    hipLaunchKernelGGL(k_start_unit<float>, dim3((unsigned)nb), dim3(kBlock), 0, s, a, nodes);
+  return hipGetLastError();
+}
+
+hipError_t launch_sc_out(const RState* state, const Task* tasks, const int32_t* nodes, int64_t count, double* out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_sc_out, dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, state, tasks,
+                     nodes, count, out);
   return hipGetLastError();
 }
 

@@ -245,3 +245,19 @@ def test_last_error_cleared_on_success():
     rc, h = create(d2)
     assert rc == 0 and A.lib().ebtc_last_error() == b""
     A.lib().ebtc_batch_destroy(h)
+
+
+def test_subgraph_centrality_validates_and_sizes():
+    L = A.lib()
+    ws = ctypes.c_size_t()
+    assert L.ebtc_subgraph_centrality_ws_bytes(0, 5000, 3, 20, ctypes.byref(ws)) == 0 and ws.value > 0
+    w1 = ws.value
+    assert L.ebtc_subgraph_centrality_ws_bytes(0, 5000, 6, 20, ctypes.byref(ws)) == 0 and ws.value > w1
+    for args, text in [((7, 10, 1, 5), "dtype"), ((0, 0, 1, 5), "n must"), ((0, 10, 0, 5), "count"),
+                       ((0, 10, 1, 0), "m must"), ((0, 10, 1, 65), "m must")]:
+        assert L.ebtc_subgraph_centrality_ws_bytes(*args, ctypes.byref(ws)) == A.EBTC_EINVAL
+        assert text in L.ebtc_last_error().decode()
+    assert L.ebtc_subgraph_centrality(0, 10, None, FAKE_DEV, None, 1, FAKE_DEV, 5, FAKE_DEV, FAKE_DEV, 1 << 30,
+                                      None) == A.EBTC_EINVAL
+    assert L.ebtc_subgraph_centrality(0, 10, FAKE_DEV, FAKE_DEV, None, 1, FAKE_DEV, 5, FAKE_DEV, FAKE_DEV, 16,
+                                      None) == A.EBTC_EWORKSPACE

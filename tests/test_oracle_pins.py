@@ -258,3 +258,51 @@ def test_adaptive_stop_and_cap():
     # the estimate is monotone enough to stop earlier for a looser tolerance
     r_loose = lanczos.lanczos_expv(A, m=0, tol=1e-3, m_max=60)
     assert r_loose.m_used < r.m_used
+
+
+# ------------------------------------------------------------------ subgraph centrality (Gauss rule)
+
+def test_gauss_subgraph_centrality_exact_when_the_krylov_space_closes():
+    from oracle import centrality
+    rng = np.random.default_rng(5)
+    A = (rng.random((30, 30)) < 0.15).astype(float)
+    A = np.triu(A, 1)
+    A = A + A.T
+    nodes = np.arange(30)
+    exact = np.diag(sla.expm(A))
+    got = centrality.gauss_subgraph_centrality(sp.csr_matrix(A), nodes, m=30)
+    assert np.max(np.abs(got - exact) / exact) < 1e-12
+
+
+def test_gauss_subgraph_centrality_closed_forms():
+    from oracle import centrality
+    n = 9
+    K = np.ones((n, n)) - np.eye(n)
+    sc = centrality.gauss_subgraph_centrality(sp.csr_matrix(K), [0, 4], m=5)
+    want = (np.exp(n - 1) + (n - 1) * np.exp(-1.0)) / n   # K_n: eigenvalues n-1 and -1 (n-1 times)
+    assert np.allclose(sc, want, rtol=1e-13)
+    S = np.zeros((n, n))
+    S[0, 1:] = S[1:, 0] = 1.0                               # star: eigenvalues +-sqrt(n-1), 0
+    sc = centrality.gauss_subgraph_centrality(sp.csr_matrix(S), [0, 3], m=5)
+    c = np.cosh(np.sqrt(n - 1))
+    assert np.allclose(sc, [c, (n - 2 + c) / (n - 1)], rtol=1e-13)
+    Z = sp.csr_matrix((5, 5))                               # isolated nodes: SC = 1
+    assert np.allclose(centrality.gauss_subgraph_centrality(Z, [0, 4], m=3), 1.0)
+
+
+def test_gauss_rule_is_a_monotone_lower_bound():
+    # exp has positive even derivatives, so every m-point Gauss rule underestimates [exp(A)]_ii and
+    # the estimates increase with m
+    from oracle import centrality
+    rng = np.random.default_rng(9)
+    A = (rng.random((60, 60)) < 0.1).astype(float)
+    A = np.triu(A, 1)
+    A = sp.csr_matrix(A + A.T)
+    exact = dense.subgraph_centrality(A)
+    nodes = [0, 7, 33]
+    prev = np.zeros(3)
+    for m in (1, 2, 3, 5, 8):
+        sc = centrality.gauss_subgraph_centrality(A, nodes, m=m)
+        assert np.all(sc <= exact[nodes] * (1 + 1e-12)) and np.all(sc >= prev * (1 - 1e-12))
+        prev = sc
+    assert np.allclose(prev, exact[nodes], rtol=1e-6)
