@@ -98,6 +98,9 @@ def main() -> int:
     ap.add_argument("--realizations", type=int, default=0, help="limit realizations per graph (0 = all)")
     ap.add_argument("--oracle-graphs", type=int, default=0,
                     help="oracle (cpu_baseline and parity) on the first G graphs only (0 = all)")
+    ap.add_argument("--reorth", type=int, default=1, choices=[0, 1, 2],
+                    help="Gram-Schmidt passes against the whole basis; 0 = three-term recurrence, two passes, "
+                         "three stored basis vectors (memory-bounded form)")
     ap.add_argument("--adjoint", action="store_true", help="also time the adjoint (always on for workload 3)")
     ap.add_argument("--profile-run", action="store_true",
                     help="for rocprofv3: one eager batched pass per gather form plus a 1 GiB copy (counter calibration)")
@@ -136,10 +139,11 @@ def main() -> int:
     has_val = hb.values is not None
     K = hb.K
 
-    form = {"spmv": "auto" if args.spmv == "tuned" else args.spmv, "lanes": args.lanes, "seg_len": args.seg_len}
+    form = {"spmv": "auto" if args.spmv == "tuned" else args.spmv, "lanes": args.lanes, "seg_len": args.seg_len,
+            "reorth": args.reorth}
     tuned = None
     if args.spmv == "tuned":
-        tuned = b.tune(m=m, tol=tol, m_max=m_max)
+        tuned = b.tune(m=m, tol=tol, m_max=m_max, reorth=args.reorth)
         log(f"tuned SpMV form: {tuned}")
 
     if args.profile_run:
@@ -182,7 +186,9 @@ def main() -> int:
     gpu_ls = run.log_scale.cpu().numpy()
 
     adjoint = None
-    if args.config == 3 or args.adjoint:
+    if (args.config == 3 or args.adjoint) and args.reorth == 0:
+        log("adjoint skipped: it needs the stored basis (reorth 1 or 2)")
+    elif args.config == 3 or args.adjoint:
         # forward alone (scores, no top-K) vs the adjoint (recompute + adjoint Lanczos + SDDMM);
         # cotangent: the loss sums the summed scores over each graph's target nodes
         g = torch.zeros(hb.n.sum(), dtype=b.tdtype, device="cuda")
@@ -247,13 +253,19 @@ def main() -> int:
     torch.cuda.synchronize()
     m_used = d["m_used"]
     sp_bytes = dt_bytes = up_bytes = 0.0
+    passes = max(1, args.reorth)  # Gram-Schmidt passes per step
     for r in range(hb.R):
         n, rp, ci, _ = hb.csr(r)
         z = ci.size
-        for j in range(int(m_used[r])):
-            sp_bytes += spmv_bytes(n, z, es, has_val)
-            dt_bytes += dots_bytes(n, j, es)
-            up_bytes += update_bytes(n, j, es)
+        k = int(m_used[r])
+        # the memory-bounded form orthogonalises against v_{j-1}, v_j only and runs the steps twice
+        # (the second pass stops one step earlier: its last vector is v_{k-1})
+        for steps in ([k] if args.reorth else [k, k - 1]):
+            for j in range(steps):
+                jj = j if args.reorth else min(j, 1)  # newest basis index in the Gram-Schmidt window
+                sp_bytes += spmv_bytes(n, z, es, has_val)
+                dt_bytes += passes * dots_bytes(n, jj, es)
+                up_bytes += passes * update_bytes(n, jj, es)
     alg = {"spmv": sp_bytes, "dots": dt_bytes, "update": up_bytes}
     if phases["dots"][1] == 0:  # vector staged in LDS: SpMV and dots are one kernel (w read counted once extra)
         alg = {"spmv": sp_bytes + dt_bytes, "update": up_bytes}
@@ -283,7 +295,7 @@ def main() -> int:
         "data": "synthetic (seeded ER/WS/BA realizations with an embedded target, generated on the host)",
         "config": {"workload": w.name, "graphs": int(hb.n.size), "realizations": hb.R,
                    "n": [int(x) for x in hb.n], "nnz_total": int(hb.nnz_off[-1]), "m": m,
-                   "adaptive_tol": w.tol if m == 0 else None, "reorth": 1, "K": [int(x) for x in K[:4]],
+                   "adaptive_tol": w.tol if m == 0 else None, "reorth": args.reorth, "K": [int(x) for x in K[:4]],
                    "schedule": "batched, hipGraph replay", "parallelism": "1 GPU",
                    "spmv_form": tuned if tuned is not None else form},
         "plain": {"value": round(plain_value, 2), "ms_per_step": round(1000 * plain_wall / args.plain_steps, 3),

@@ -89,7 +89,12 @@ typedef struct {
   int32_t m;             /* fixed Krylov dimension 1..EBTC_M_LIMIT; 0 = adaptive                  */
   int32_t m_max;         /* adaptive cap 1..EBTC_M_LIMIT                                          */
   double tol;            /* adaptive stop: Saad's relative estimate beta_j |y_j| / ||y|| < tol     */
-  int32_t reorth;        /* classical Gram-Schmidt passes per step against the whole basis: 1 or 2 */
+  int32_t reorth;        /* classical Gram-Schmidt passes per step against the whole basis: 1 or 2;
+                            0 = memory-bounded form: one pass against v_{j-1} and v_j only (the
+                            three-term recurrence), three basis vectors per realization in the
+                            workspace, and a second run of the same steps that regenerates the
+                            basis bit for bit and accumulates u = beta0 V y (about twice the work
+                            of reorth 1 at m / 3 of its basis memory; no adjoint)               */
   int32_t schedule;      /* enum ebtc_schedule                                                    */
   int32_t use_hipgraph;  /* batched schedule: capture the launch sequence once, replay it after    */
   int32_t shift;         /* 1 (default): factor out theta*; 0: theta* = 0 (overflow-prone, tests)  */
@@ -152,8 +157,9 @@ int ebtc_plan(ebtc_batch* batch, const ebtc_opts* opts, size_t* ws_bytes, size_t
  *   log_scale_out  device [G] double: Sigma_g; the summed score is e^{Sigma_g} S~_g
  *   ckpt_out       device checkpoint of the planned size for ebtc_scores_backward, or NULL
  *   diag_out       device [R] ebtc_diag, or NULL
- * Lanczos: start vector 1/sqrt(n), full reorthogonalisation against the whole basis, FP64
- * tridiagonal exponential; breakdown (beta_j <= 64 eps max(|alpha|, beta)) ends a realization early.
+ * Lanczos: start vector 1/sqrt(n), full reorthogonalisation against the whole basis (reorth 0: the
+ * three-term recurrence, two passes), FP64 tridiagonal exponential; breakdown
+ * (beta_j <= 64 eps max(|alpha|, beta)) ends a realization early.
  * Realizations of a graph are summed in k order with FP64 weights e^{theta*_k - Sigma_g}. */
 int ebtc_scores(ebtc_batch* batch, const ebtc_opts* opts, void* ws, size_t ws_bytes, void* scores_out,
                 double* log_scale_out, void* ckpt_out, ebtc_diag* diag_out, void* stream);

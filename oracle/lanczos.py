@@ -16,6 +16,11 @@ realization (0-based indices):
              -- adaptive: Saad's estimate beta_j |y_j| / ||y|| < tol, or j + 1 == m_max (capped)
        v_{j+1} = w / beta_j
   3. T = tridiag(beta_0..k-2; alpha_0..k-1; beta_0..k-2), k = number of steps taken
+
+  window = 2 (the memory-bounded variant): step 2 orthogonalises against v_{j-1} and v_j only, with
+  the coefficients computed as dot products (in exact arithmetic V_j^T w has no other nonzero entry,
+  since A is symmetric: this is the three-term recurrence of Lanczos' method), so only the last two
+  basis vectors are needed to continue; the basis is still kept here to form u.
   4. theta* = lambda_max(T); y = exp(T - theta* I) e1                (tridiag.expv_e1)
   5. u = beta0 V_k y, so exp(A) v ~ e^{theta*} u.
 """
@@ -45,8 +50,10 @@ class LanczosResult:
 
 
 def lanczos_expv(A, m: int = 0, tol: float = 0.0, m_max: int = 60, shift: bool = True, reorth: int = 2,
-                 eps: float = 2.0 ** -53, v: np.ndarray | None = None, keep_basis: bool = False) -> LanczosResult:
-    """m > 0: fixed dimension m; m == 0: adaptive with tolerance tol and cap m_max."""
+                 eps: float = 2.0 ** -53, v: np.ndarray | None = None, keep_basis: bool = False,
+                 window: int = 0) -> LanczosResult:
+    """m > 0: fixed dimension m; m == 0: adaptive with tolerance tol and cap m_max. window > 0:
+    orthogonalise against the last `window` basis vectors only (2 = the three-term recurrence)."""
     n = A.shape[0]
     start = np.ones(n) if v is None else np.asarray(v, dtype=np.float64)
     beta0 = float(np.linalg.norm(start))
@@ -60,14 +67,14 @@ def lanczos_expv(A, m: int = 0, tol: float = 0.0, m_max: int = 60, shift: bool =
     k = 0
     for j in range(limit):
         w = A @ V[:, j]
-        Vj = V[:, : j + 1]
+        Vj = V[:, (max(0, j - window + 1) if window > 0 else 0): j + 1]
         h = Vj.T @ w
         w = w - Vj @ h
         for _ in range(reorth - 1):
             h2 = Vj.T @ w
             w = w - Vj @ h2
             h = h + h2
-        a = float(h[j])
+        a = float(h[-1])  # the coefficient of v_j
         b = float(np.linalg.norm(w))
         scale = max(scale, abs(a))
         alpha.append(a)

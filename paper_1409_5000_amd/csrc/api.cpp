@@ -92,7 +92,8 @@ int check_opts(const ebtc_opts* o) {
   if (o->m < 0 || o->m > EBTC_M_LIMIT) return fail(EBTC_EINVAL, "m must be in [0, 64] (0 = adaptive)");
   if (o->m == 0 && (o->m_max < 1 || o->m_max > EBTC_M_LIMIT)) return fail(EBTC_EINVAL, "m_max must be in [1, 64]");
   if (o->m == 0 && !(o->tol > 0.0)) return fail(EBTC_EINVAL, "adaptive mode needs tol > 0");
-  if (o->reorth != 1 && o->reorth != 2) return fail(EBTC_EINVAL, "reorth must be 1 or 2");
+  if (o->reorth < 0 || o->reorth > 2)
+    return fail(EBTC_EINVAL, "reorth must be 0 (memory-bounded two-pass), 1 or 2");
   if (o->schedule < EBTC_SCHED_AUTO || o->schedule > EBTC_SCHED_BATCHED) return fail(EBTC_EINVAL, "unknown schedule");
   if (o->spmv < EBTC_SPMV_AUTO || o->spmv > EBTC_SPMV_SEGMENTED) return fail(EBTC_EINVAL, "unknown spmv form");
   if (o->lanes_per_row != 0 && o->lanes_per_row != 4 && o->lanes_per_row != 8 && o->lanes_per_row != 16 &&
@@ -124,7 +125,8 @@ int check_plan(const ebtc_batch* b, const SpmvPlan& p) {
 
 Layout make_layout(const ebtc_batch* b, const ebtc_opts* o, const SpmvPlan& sp) {
   Layout L;
-  L.m_slots = (o->m > 0 ? o->m : o->m_max) + 1;
+  // the memory-bounded form keeps the last three basis vectors only
+  L.m_slots = o->reorth == 0 ? 3 : (o->m > 0 ? o->m : o->m_max) + 1;
   const size_t es = elem_size(b->dtype);
   int64_t blocks = 0;
   int64_t rows = 0;
@@ -246,6 +248,8 @@ LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout
   a.seglen = sp.seglen;
   a.m_max = o->m > 0 ? o->m : o->m_max;
   a.eps = b->dtype == EBTC_F64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+  a.window = o->reorth == 0 ? 2 : 0;
+  a.stop_mused = 0;
   if (sp.form == EBTC_SPMV_SEGMENTED) {
     a.seg_cols = sp.segcols;
     a.seg_stride = sp.smax * kRowsPerBlock;
@@ -335,6 +339,26 @@ int enqueue_prepare(const ebtc_batch* b, const SpmvPlan& sp, const LzArgs& a, in
   return EBTC_OK;
 }
 
+// Second pass of the memory-bounded form (reorth 0): the first pass kept only a ring of three basis
+// vectors, so u = beta0 V y is accumulated while the same kernels regenerate the same basis (same
+// launches in the same order: bitwise the same vectors), one term before each step.
+int run_pass2(const ebtc_batch* b, const ebtc_opts* o, const LzArgs& a1, int64_t nblocks, int lanes, hipStream_t s,
+              Prof* prof) {
+  LzArgs a = a1;
+  a.stop_mused = 1;
+  const bool has_val = b->values != nullptr;
+  const int steps = o->m > 0 ? o->m : o->m_max;
+  EBTC_PHASE(prof, EBTC_PHASE_START, launch_restart(b->dtype, a, nblocks, s));
+  for (int j = 0; j < steps; ++j) {
+    EBTC_PHASE(prof, EBTC_PHASE_COMBINE, launch_accum(b->dtype, a, j, nblocks, s));
+    if (j + 1 == steps) break;  // the last vector needed is v_{steps-1}
+    EBTC_PHASE(prof, EBTC_PHASE_SPMV, launch_spmv_step(b->dtype, has_val, lanes, j, a, nblocks, s));
+    EBTC_PHASE(prof, EBTC_PHASE_DOTS, launch_dots_step(b->dtype, j, a, nblocks, s));
+    EBTC_PHASE(prof, EBTC_PHASE_UPDATE, launch_update(b->dtype, j, true, true, false, a, nblocks, s));
+  }
+  return EBTC_OK;
+}
+
 int enqueue_batched(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, void* scores, double* log_scale,
                     void* ckpt, ebtc_diag* diag, const SpmvPlan& sp, hipStream_t s, Prof* prof = nullptr) {
   LzArgs a = make_args(b, o, ws, L, sp);
@@ -347,7 +371,12 @@ int enqueue_batched(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L
   const int steps = o->m > 0 ? o->m : o->m_max;
   EBTC_PHASE(prof, EBTC_PHASE_TRIDIAG,
              launch_tridiag_state(a, 0, b->R, 0, 0, steps, o->shift, o->tol, diag, (double*)ckpt, s));
-  EBTC_PHASE(prof, EBTC_PHASE_COMBINE, launch_combine(b->dtype, a, L.total_blocks, s));
+  if (o->reorth == 0) {
+    rc = run_pass2(b, o, a, L.total_blocks, sp.lanes, s, prof);
+    if (rc) return rc;
+  } else {
+    EBTC_PHASE(prof, EBTC_PHASE_COMBINE, launch_combine(b->dtype, a, L.total_blocks, s));
+  }
   const int32_t maxblk = (b->n_max + kRowsPerBlock - 1) / kRowsPerBlock;
   EBTC_PHASE(prof, EBTC_PHASE_SUM, launch_sum(b->dtype, (const GraphInfo*)(ws + L.off_graphs), b->G, maxblk, a.tasks,
                                               a.state, a.U, scores, log_scale, s));
@@ -368,7 +397,12 @@ int enqueue_plain(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, 
     if (rc) return rc;
     EBTC_LAUNCH(launch_tridiag_state(a, r, 1, 0, 0, o->m > 0 ? o->m : o->m_max, o->shift, o->tol, diag,
                                      (double*)ckpt, s));
-    EBTC_LAUNCH(launch_combine(b->dtype, a, nb, s));
+    if (o->reorth == 0) {
+      rc = run_pass2(b, o, a, nb, sp.lanes, s, nullptr);
+      if (rc) return rc;
+    } else {
+      EBTC_LAUNCH(launch_combine(b->dtype, a, nb, s));
+    }
   }
   const int32_t maxblk = (b->n_max + kRowsPerBlock - 1) / kRowsPerBlock;
   EBTC_LAUNCH(launch_sum(b->dtype, (const GraphInfo*)(ws + L.off_graphs), b->G, maxblk, a.tasks, a.state, a.U, scores,
@@ -413,6 +447,8 @@ int check_bwd_opts(const ebtc_opts* o) {
   int rc = check_opts(o);
   if (rc) return rc;
   const int steps = o->m > 0 ? o->m : o->m_max;
+  if (o->reorth == 0)
+    return fail(EBTC_ENOTSUPPORTED, "the adjoint needs the stored basis: reorth 1 or 2");
   if (steps > adjoint_max_m())
     return fail(EBTC_ENOTSUPPORTED, "the adjoint supports Krylov dimensions up to " + std::to_string(adjoint_max_m()));
   return EBTC_OK;

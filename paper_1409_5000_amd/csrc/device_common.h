@@ -22,6 +22,12 @@ struct Ref {
   int blk;
 };
 
+// True when a realization takes no part in step j: finished, or (second pass of the memory-bounded
+// form) past the last step whose basis vector the combination needs.
+__device__ inline bool step_skipped(const LzArgs& a, const RState* st, int j) {
+  return st->done || (a.stop_mused && j + 1 >= st->m_used);
+}
+
 __device__ inline Ref resolve(const LzArgs& a) {
   const int lb = logical_block();
   if (a.blkmap == nullptr) return {a.single_task, lb};

@@ -92,7 +92,16 @@ struct LzArgs {
   uint16_t* seg_col;       // [entries] column - s * seg_cols, a block's entries ordered by (segment, row)
   void* seg_val;           // [entries] values in the same order (nullptr for pattern-only graphs)
   int32_t seg_vec;         // 1: every n is a multiple of 16 bytes / element size (16-byte slice loads)
+  // memory-bounded form (window > 0): Gram-Schmidt against the last `window` basis vectors only, the
+  // raw basis kept in a ring of window + 1 slots (vector i in slot i % (window + 1))
+  int32_t window;
+  int32_t stop_mused;      // second pass of the memory-bounded form: steps j >= m_used - 1 are skipped
 };
+
+// Slot of basis vector i in a realization's V block.
+__host__ __device__ inline size_t vslot(const LzArgs& a, int i) {
+  return a.window > 0 ? (size_t)(i % (a.window + 1)) : (size_t)i;
+}
 
 // ---- launchers (k_lanczos.hip, k_spmv.hip)
 hipError_t launch_blkmap(const Task* tasks, int64_t R, int32_t* blkmap, hipStream_t s);
@@ -110,6 +119,10 @@ hipError_t launch_dots_again(int dtype, int j, const LzArgs& a, int64_t nblocks,
 hipError_t launch_update(int dtype, int j, bool from_w, bool final_pass, bool second_pass, const LzArgs& a,
                          int64_t nblocks, hipStream_t s);
 hipError_t launch_combine(int dtype, const LzArgs& a, int64_t nblocks, hipStream_t s);
+// Memory-bounded form, second pass: restart from the start vector keeping theta, y, m_used, flags;
+// before step j, u (+)= beta0 y_j s_j Vraw_j (j = 0 assigns) and the realization stops after m_used.
+hipError_t launch_restart(int dtype, const LzArgs& a, int64_t nblocks, hipStream_t s);
+hipError_t launch_accum(int dtype, const LzArgs& a, int j, int64_t nblocks, hipStream_t s);
 hipError_t launch_sum(int dtype, const GraphInfo* graphs, int32_t G, int32_t max_blocks, const Task* tasks,
                       const RState* state, const void* U, void* scores, double* log_scale, hipStream_t s);
 hipError_t launch_spmv(int dtype, bool has_val, int lanes, int hub, int seglen, int32_t n, const int32_t* row_ptr,

@@ -15,20 +15,23 @@
 //
 // Memory layout: basis vectors are vector-major (V[i][0..n)), so every phase streams them with
 // fully coalesced loads; the SpMV gathers from the one contiguous vector v_j.
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace ebtc {
 namespace {
 
-// Partial dots p_i = sum_rows Vraw_i[r] * w[r] (i <= j) of this workgroup's rows, reduced over the
-// workgroup (NT threads) and stored to part_blk[i]. Basis loads are issued eight vectors at a time
-// (clamped to slot j, whose contribution is masked) so that many loads are in flight per thread.
-// red: (NT / 64) * P doubles of LDS.
+// Partial dots p_d = sum_rows Vraw_{lo+d}[r] * w[r] (d < cnt = j - lo + 1) of this workgroup's rows,
+// reduced over the workgroup (NT threads) and stored to part_blk[d]. Basis loads are issued eight
+// vectors at a time (clamped to the last one, whose extra contributions are masked) so that many
+// loads are in flight per thread. ring > 0: vector i lives in slot i % ring. red: (NT / 64) * P
+// doubles of LDS.
 template <typename T, int P, int NT>
-__device__ inline void block_dots(const T* __restrict__ Vr, int n, int j, int r0, int r1, const T* wsrc_lds,
-                                  const T* wsrc_glob, T* wstore, double* part_blk, double* red) {
+__device__ inline void block_dots(const T* __restrict__ Vr, int n, int lo, int j, int ring, int r0, int r1,
+                                  const T* wsrc_lds, const T* wsrc_glob, T* wstore, double* part_blk, double* red) {
   constexpr int RPT = kRowsPerBlock / NT;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, cnt = j - lo + 1;
   T p[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) p[i] = 0;
@@ -39,13 +42,16 @@ __device__ inline void block_dots(const T* __restrict__ Vr, int n, int j, int r0
       const T wv = wsrc_lds ? wsrc_lds[r - r0] : wsrc_glob[r];
       if (wstore) wstore[r] = wv;
 #pragma unroll
-      for (int i0 = 0; i0 < P; i0 += 8) {
-        if (i0 <= j) {
+      for (int d0 = 0; d0 < P; d0 += 8) {
+        if (d0 < cnt) {
           T v[8];
 #pragma unroll
-          for (int c = 0; c < 8; ++c) v[c] = Vr[(size_t)min(i0 + c, j) * n + r];
+          for (int c = 0; c < 8; ++c) {
+            const int i = lo + min(d0 + c, cnt - 1);
+            v[c] = Vr[(size_t)(ring ? i % ring : i) * n + r];
+          }
 #pragma unroll
-          for (int c = 0; c < 8; ++c) p[i0 + c] += (i0 + c <= j) ? v[c] * wv : (T)0;
+          for (int c = 0; c < 8; ++c) p[d0 + c] += (d0 + c < cnt) ? v[c] * wv : (T)0;
         }
       }
     }
@@ -57,7 +63,7 @@ __device__ inline void block_dots(const T* __restrict__ Vr, int n, int j, int r0
   ReduceScatter<P, 32>::run(pd, lane);
   if (P == 64 || (lane & 1) == 0) red[wave * P + (P == 64 ? lane : (lane >> 1))] = pd[0];
   __syncthreads();
-  if (tid < P && tid <= j) {
+  if (tid < P && tid < cnt) {
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < NT / 64; ++w) s += red[w * P + tid];
@@ -65,38 +71,42 @@ __device__ inline void block_dots(const T* __restrict__ Vr, int n, int j, int r0
   }
 }
 
-// k_dots_step: dot partials of w (written by k_spmv_step) against Vraw_0..j.
+// First basis vector of the Gram-Schmidt window of step j (all of v_0..v_j without a window).
+__device__ inline int window_lo(const LzArgs& a, int j) { return a.window > 0 ? max(0, j - a.window + 1) : 0; }
+__device__ inline int ring_of(const LzArgs& a) { return a.window > 0 ? a.window + 1 : 0; }
+
+// k_dots_step: dot partials of w (written by the SpMV) against the window of Vraw_0..j.
 template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_dots_step(LzArgs a, int j) {
   __shared__ double red[kWaves * P];
   const Ref ref = resolve(a);
   const Task tk = a.tasks[ref.task];
   const RState* st = a.state + ref.task;
-  if (st->done) return;
+  if (step_skipped(a, st, j)) return;
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
   const T* Vr = (const T*)a.V + tk.vec_off;
-  block_dots<T, P, kBlock>(Vr, n, j, r0, r1, nullptr, (const T*)a.W + tk.w_off, nullptr,
-                           a.part + tk.part_off + (size_t)ref.blk * kPartStride, red);
+  block_dots<T, P, kBlock>(Vr, n, window_lo(a, j), j, ring_of(a), r0, r1, nullptr, (const T*)a.W + tk.w_off,
+                           nullptr, a.part + tk.part_off + (size_t)ref.blk * kPartStride, red);
 }
 
-// Second Gram-Schmidt pass: dots of the once-orthogonalised vector (stored in slot j+1).
+// Second Gram-Schmidt pass: dots of the once-orthogonalised vector (stored in the slot of j+1).
 template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_dots_again(LzArgs a, int j) {
   __shared__ double red[kWaves * P];
   const Ref ref = resolve(a);
   const Task tk = a.tasks[ref.task];
   const RState* st = a.state + ref.task;
-  if (st->done) return;
+  if (step_skipped(a, st, j)) return;
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
   const T* Vr = (const T*)a.V + tk.vec_off;
-  block_dots<T, P, kBlock>(Vr, n, j, r0, r1, nullptr, Vr + (size_t)(j + 1) * n, nullptr,
-                           a.part + tk.part_off + (size_t)ref.blk * kPartStride, red);
+  block_dots<T, P, kBlock>(Vr, n, window_lo(a, j), j, ring_of(a), r0, r1, nullptr, Vr + vslot(a, j + 1) * n,
+                           nullptr, a.part + tk.part_off + (size_t)ref.blk * kPartStride, red);
 }
 
 // Phase B of step j: every workgroup reduces the dot partials of all workgroups of its realization
 // in the canonical order (identical coefficients everywhere, no inter-workgroup synchronisation),
-// then v~_{j+1} = src - sum_i c_i Vraw_i (FP64 accumulation, rounded once), plus the partial
-// squared norm on the final pass.
+// then v~_{j+1} = src - sum_i c_i Vraw_i over the window (FP64 accumulation, rounded once), plus
+// the partial squared norm on the final pass.
 template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, int final_pass, int second) {
   __shared__ double cs[P];
@@ -105,27 +115,27 @@ __global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, 
   const Ref ref = resolve(a);
   const Task tk = a.tasks[ref.task];
   RState* st = a.state + ref.task;
-  if (st->done) return;
-  const int tid = threadIdx.x;
+  if (step_skipped(a, st, j)) return;
+  const int tid = threadIdx.x, lo = window_lo(a, j), cnt = j - lo + 1, ring = ring_of(a);
   const double* part = a.part + tk.part_off;
   const int nblk = tk.nblk, chunk = part_chunk(nblk), nch = (nblk + chunk - 1) / chunk;
-  for (int item = tid; item < nch * (j + 1); item += kBlock) {
-    const int c = item / (j + 1), i = item - c * (j + 1);
+  for (int item = tid; item < nch * cnt; item += kBlock) {
+    const int c = item / cnt, d = item - c * cnt;
     double s = 0.0;
     const int b1 = min(nblk, (c + 1) * chunk);
-    for (int b = c * chunk; b < b1; ++b) s += part[(size_t)b * kPartStride + i];
-    csum[i][c] = s;
+    for (int b = c * chunk; b < b1; ++b) s += part[(size_t)b * kPartStride + d];
+    csum[d][c] = s;
   }
   __syncthreads();
   if (tid < P) {
     double coef = 0.0;
-    if (tid <= j) {
+    if (tid < cnt) {
       double t = 0.0;
       for (int c = 0; c < nch; ++c) t += csum[tid][c];
-      const double si = st->s[tid];
+      const double si = st->s[lo + tid];
       const double h = si * t;
       coef = h * si;
-      if (tid == j && ref.blk == 0) {
+      if (lo + tid == j && ref.blk == 0) {
         const double alpha = second ? st->alpha[j] + h : h;
         st->alpha[j] = alpha;
         if (final_pass) {  // breakdown reference of step j: max(|alpha_0..j|, beta_0..j-1)
@@ -140,8 +150,8 @@ __global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, 
   __syncthreads();
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
   T* Vr = (T*)a.V + tk.vec_off;
-  const T* src = from_w ? (const T*)a.W + tk.w_off : Vr + (size_t)(j + 1) * n;
-  T* dst = Vr + (size_t)(j + 1) * n;
+  const T* src = from_w ? (const T*)a.W + tk.w_off : Vr + vslot(a, j + 1) * n;
+  T* dst = Vr + vslot(a, j + 1) * n;
   double nrm = 0.0;
 #pragma unroll
   for (int q = 0; q < kRowsPerThread; ++q) {
@@ -149,13 +159,16 @@ __global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, 
     if (r < r1) {
       double acc = (double)src[r];
 #pragma unroll
-      for (int i0 = 0; i0 < P; i0 += 8) {
-        if (i0 <= j) {
+      for (int d0 = 0; d0 < P; d0 += 8) {
+        if (d0 < cnt) {
           T v[8];
 #pragma unroll
-          for (int c = 0; c < 8; ++c) v[c] = Vr[(size_t)min(i0 + c, j) * n + r];
+          for (int c = 0; c < 8; ++c) {
+            const int i = lo + min(d0 + c, cnt - 1);
+            v[c] = Vr[(size_t)(ring ? i % ring : i) * n + r];
+          }
 #pragma unroll
-          for (int c = 0; c < 8; ++c) acc -= cs[i0 + c] * (double)v[c];
+          for (int c = 0; c < 8; ++c) acc -= cs[d0 + c] * (double)v[c];
         }
       }
       const T out = (T)acc;
@@ -185,6 +198,38 @@ __global__ __launch_bounds__(kBlock) void k_start(LzArgs a) {
     st->flags = 0;
     st->done = 0;
   }
+}
+
+// Second pass of the memory-bounded form: the same start vector and scale as k_start, keeping
+// theta, y, est, m_used and flags of the first pass.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restart(LzArgs a) {
+  const Ref ref = resolve(a);
+  const Task tk = a.tasks[ref.task];
+  const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
+  T* v0 = (T*)a.V + tk.vec_off;
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) v0[r] = (T)1;
+  if (ref.blk == 0 && threadIdx.x == 0) {
+    RState* st = a.state + ref.task;
+    st->s[0] = 1.0 / st->beta0;
+    st->done = 0;
+  }
+}
+
+// Before step j of the second pass: u = beta0 sum_{i <= j} y_i s_i Vraw_i, one term per step (the
+// vector of step j is in its ring slot now and is overwritten three steps later), for j < m_used.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_accum(LzArgs a, int j) {
+  const Ref ref = resolve(a);
+  const Task tk = a.tasks[ref.task];
+  const RState* st = a.state + ref.task;
+  if (st->done || j >= st->m_used) return;
+  const double d = st->beta0 * st->y[j] * st->s[j];
+  const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
+  const T* v = (const T*)a.V + tk.vec_off + vslot(a, j) * n;
+  T* u = (T*)a.U + tk.u_off;
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock)
+    u[r] = (T)((j == 0 ? 0.0 : (double)u[r]) + d * (double)v[r]);
 }
 
 // Start of the Gauss-quadrature processes of subgraph centrality: task r starts at e_{nodes[r]}
@@ -343,13 +388,32 @@ hipError_t launch_sc_out(const RState* state, const Task* tasks, const int32_t* 
   return hipGetLastError();
 }
 
+// Basis vectors in the Gram-Schmidt window of step j.
+int window_count(const LzArgs& a, int j) { return a.window > 0 ? std::min(j + 1, (int)a.window) : j + 1; }
+
+hipError_t launch_restart(int dtype, const LzArgs& a, int64_t nb, hipStream_t s) {
+  if (dtype == EBTC_F64)
+    hipLaunchKernelGGL(k_restart<double>, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_restart<float>, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_accum(int dtype, const LzArgs& a, int j, int64_t nb, hipStream_t s) {
+  if (dtype == EBTC_F64)
+    hipLaunchKernelGGL(k_accum<double>, dim3((unsigned)nb), dim3(kBlock), 0, s, a, j);
+  else
+    hipLaunchKernelGGL(k_accum<float>, dim3((unsigned)nb), dim3(kBlock), 0, s, a, j);
+  return hipGetLastError();
+}
+
 hipError_t launch_dots_step(int dtype, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
   const dim3 g((unsigned)nb), b(kBlock);
   if (dtype == EBTC_F64) {
-    if (j + 1 <= 32) hipLaunchKernelGGL((k_dots_step<double, 32>), g, b, 0, s, a, j);
+    if (window_count(a, j) <= 32) hipLaunchKernelGGL((k_dots_step<double, 32>), g, b, 0, s, a, j);
     else hipLaunchKernelGGL((k_dots_step<double, 64>), g, b, 0, s, a, j);
   } else {
-    if (j + 1 <= 32) hipLaunchKernelGGL((k_dots_step<float, 32>), g, b, 0, s, a, j);
+    if (window_count(a, j) <= 32) hipLaunchKernelGGL((k_dots_step<float, 32>), g, b, 0, s, a, j);
     else hipLaunchKernelGGL((k_dots_step<float, 64>), g, b, 0, s, a, j);
   }
   return hipGetLastError();
@@ -358,10 +422,10 @@ hipError_t launch_dots_step(int dtype, int j, const LzArgs& a, int64_t nb, hipSt
 hipError_t launch_dots_again(int dtype, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
   const dim3 g((unsigned)nb), b(kBlock);
   if (dtype == EBTC_F64) {
-    if (j + 1 <= 32) hipLaunchKernelGGL((k_dots_again<double, 32>), g, b, 0, s, a, j);
+    if (window_count(a, j) <= 32) hipLaunchKernelGGL((k_dots_again<double, 32>), g, b, 0, s, a, j);
     else hipLaunchKernelGGL((k_dots_again<double, 64>), g, b, 0, s, a, j);
   } else {
-    if (j + 1 <= 32) hipLaunchKernelGGL((k_dots_again<float, 32>), g, b, 0, s, a, j);
+    if (window_count(a, j) <= 32) hipLaunchKernelGGL((k_dots_again<float, 32>), g, b, 0, s, a, j);
     else hipLaunchKernelGGL((k_dots_again<float, 64>), g, b, 0, s, a, j);
   }
   return hipGetLastError();
@@ -372,10 +436,10 @@ hipError_t launch_update(int dtype, int j, bool from_w, bool final_pass, bool se
   const dim3 g((unsigned)nb), b(kBlock);
   const int fw = from_w ? 1 : 0, fp = final_pass ? 1 : 0, sp = second_pass ? 1 : 0;
   if (dtype == EBTC_F64) {
-    if (j + 1 <= 32) hipLaunchKernelGGL((k_update<double, 32>), g, b, 0, s, a, j, fw, fp, sp);
+    if (window_count(a, j) <= 32) hipLaunchKernelGGL((k_update<double, 32>), g, b, 0, s, a, j, fw, fp, sp);
     else hipLaunchKernelGGL((k_update<double, 64>), g, b, 0, s, a, j, fw, fp, sp);
   } else {
-    if (j + 1 <= 32) hipLaunchKernelGGL((k_update<float, 32>), g, b, 0, s, a, j, fw, fp, sp);
+    if (window_count(a, j) <= 32) hipLaunchKernelGGL((k_update<float, 32>), g, b, 0, s, a, j, fw, fp, sp);
     else hipLaunchKernelGGL((k_update<float, 64>), g, b, 0, s, a, j, fw, fp, sp);
   }
   return hipGetLastError();

@@ -29,7 +29,7 @@ namespace {
 // realization is finished; *sj = 1/beta_{j-1} (or s_0 at j = 0).
 __device__ inline bool open_step(const LzArgs& a, const Task& tk, RState* st, int blk, int j, double* chunks,
                                  double* sj) {
-  if (st->done) return false;
+  if (step_skipped(a, st, j)) return false;
   if (j == 0) {
     *sj = st->s[0];
     return true;
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_step(LzArgs a, int j) {
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, rows = min(n - r0, kRowsPerBlock);
   const T* va = HAS_VAL ? (const T*)a.values + tk.nnz_off : nullptr;
   spmv_direct_block<T, HAS_VAL, L>(a.row_ptr + tk.rowptr_off, a.col_idx + tk.nnz_off, va,
-                                   (const T*)a.V + tk.vec_off + (size_t)j * n, r0, rows, a.hub_threshold, sj, rp_lds,
+                                   (const T*)a.V + tk.vec_off + vslot(a, j) * n, r0, rows, a.hub_threshold, sj, rp_lds,
                                    w_lds, hubs, &hub_count, chunks);
   T* W = (T*)a.W + tk.w_off + r0;
   for (int i = threadIdx.x; i < rows; i += kBlock) W[i] = w_lds[i];
@@ -259,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream(LzArgs a, int j) {
   const int rows = min(n - r0, kStreamRows);
   const T* va = HAS_VAL ? (const T*)a.values + tk.nnz_off : nullptr;
   spmv_stream_rows<T, HAS_VAL>(a.row_ptr + tk.rowptr_off, a.col_idx + tk.nnz_off, va,
-                               (const T*)a.V + tk.vec_off + (size_t)j * n, r0, rows, sj, rp_lds, prod,
+                               (const T*)a.V + tk.vec_off + vslot(a, j) * n, r0, rows, sj, rp_lds, prod,
                                (T*)a.W + tk.w_off + r0, chunks);
 }
 
@@ -394,7 +394,7 @@ __global__ __launch_bounds__(kStagedThreads) void k_spmv_staged(LzArgs a, int j)
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, rows = min(n - r0, kRowsPerBlock);
   const T* va = HAS_VAL ? (const T*)a.values + tk.nnz_off : nullptr;
   spmv_staged_block<T, HAS_VAL>(a.row_ptr + tk.rowptr_off, a.col_idx + tk.nnz_off, va,
-                                (const T*)a.V + tk.vec_off + (size_t)j * n, n, a.seglen, r0, rows, sj, (T*)smem,
+                                (const T*)a.V + tk.vec_off + vslot(a, j) * n, n, a.seglen, r0, rows, sj, (T*)smem,
                                 rp_lds, w_lds, hubs, &hub_count, red);
   T* W = (T*)a.W + tk.w_off + r0;
   for (int i = threadIdx.x; i < rows; i += kStagedThreads) W[i] = w_lds[i];
@@ -639,7 +639,7 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
   RState* st = a.state + ref.task;
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, rows = min(n - r0, kRowsPerBlock);
   const int blk = tk.blk_begin + ref.blk, tid = threadIdx.x;
-  const T* x = (const T*)a.V + tk.vec_off + (size_t)j * n;
+  const T* x = (const T*)a.V + tk.vec_off + vslot(a, j) * n;
   T* w_out = (T*)a.W + tk.w_off + r0;
   const int32_t* rp = a.row_ptr + tk.rowptr_off;
   const int flag = a.seg_flag[blk];

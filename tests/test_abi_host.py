@@ -148,6 +148,8 @@ def test_plan_workspace_arithmetic(dtype, es):
     assert ck == 5 * A.CKPT_DOUBLES * 8
     rc, ws2, _ = plan(h, m=0, m_max=60, tol=1e-6)
     assert rc == 0 and ws2 == expected_ws(2, (2, 3), (3000, 70), 61, es, RSTATE_BYTES)
+    rc, ws3, _ = plan(h, m=30, reorth=0)  # memory-bounded: three basis slots whatever m
+    assert rc == 0 and ws3 == expected_ws(2, (2, 3), (3000, 70), 3, es, RSTATE_BYTES)
     A.lib().ebtc_batch_destroy(h)
 
 

@@ -91,16 +91,22 @@ def b_targets(hb, gi=0):
     return np.asarray(hb.targets[gi], dtype=np.int64)
 
 
+_FD_SHARED = {}  # the batch and cotangent, inherited by the forked workers instead of pickled per job
+
+
 def _fd_job(args):
-    hb, r, i, j, h, gvec, sigma, m = args
+    # central difference of the loss in the weight of one undirected edge: entries e = (i, j) and
+    # e2 = (j, i) of realization r move together
+    r, e, e2, h, sigma, m = args
+    hb, gvec = _FD_SHARED["hb"], _FD_SHARED["g"]
     n, rp, ci, v = hb.csr(r)
-    A = odense.csr_to_scipy(n, rp, ci, v).tolil()
+    base = odense.csr_to_scipy(n, rp, ci, v)
     vals = []
     for sgn in (1.0, -1.0):
-        B = A.copy()
-        B[i, j] = B[i, j] + sgn * h
-        B[j, i] = B[j, i] + sgn * h
-        res = olanczos.lanczos_expv(B.tocsr(), m=m)
+        B = base.copy()
+        B.data[e] += sgn * h
+        B.data[e2] += sgn * h
+        res = olanczos.lanczos_expv(B, m=m)
         vals.append(np.exp(res.theta - sigma) * float(gvec @ res.u))
     return (vals[0] - vals[1]) / (2 * h)
 
@@ -122,9 +128,13 @@ def fd_check(hb, b, out, grad, m, nedges, seed, tol_rel, tol_abs_frac, workers=8
         # entry (j, i) of the same realization
         e2 = int(rp[j] + np.searchsorted(ci[rp[j]:rp[j + 1]], i))
         gpu_vals.append(gpu[hb.nnz_off[r] + e] + gpu[hb.nnz_off[r] + e2])
-        jobs.append((hb, r, i, j, 1e-3, g, sigma, m))
-    with mp.get_context("fork").Pool(workers) as pool:
-        fd = np.array(pool.map(_fd_job, jobs))
+        jobs.append((r, e, e2, 1e-3, sigma, m))
+    _FD_SHARED.update(hb=hb, g=g)
+    try:
+        with mp.get_context("fork").Pool(workers) as pool:
+            fd = np.array(pool.map(_fd_job, jobs))
+    finally:
+        _FD_SHARED.clear()
     gpu_vals = np.array(gpu_vals)
     scale = np.max(np.abs(gpu))
     err = np.abs(gpu_vals - fd)

@@ -78,6 +78,8 @@ def run_gpu(hb, **kw):
 
 
 def check_against_oracle(hb, out, b, m, tol_key, K=None, tol=0.0, m_max=60, reorth_ref=2, check_m=True, workers=1):
+    """Scores against the oracle per graph; check_m: True = equal m_used, False = within one step,
+    None = not compared (a different recurrence that stops elsewhere)."""
     ref = oscores.batch_scores(hb, m=m, tol=tol, m_max=m_max, reorth=reorth_ref, workers=workers)
     s_all = out.scores.double().cpu().numpy()
     ls = out.log_scale.cpu().numpy()
@@ -95,7 +97,7 @@ def check_against_oracle(hb, out, b, m, tol_key, K=None, tol=0.0, m_max=60, reor
         m_gpu = diag["m_used"][r0:r0 + R_g]
         if check_m:
             assert np.array_equal(m_gpu, gsc.m_used), (m_gpu, gsc.m_used)
-        else:
+        elif check_m is not None:
             assert np.max(np.abs(m_gpu - gsc.m_used)) <= 1
         r0 += R_g
     return ref, report

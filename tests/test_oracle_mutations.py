@@ -23,7 +23,7 @@ ORACLE_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file
 MUTATIONS = [
     ("lanczos.py", "beta0 = float(np.linalg.norm(start))", "beta0 = float(np.sum(start))"),
     ("lanczos.py", "        w = w - Vj @ h\n", "        w = w + Vj @ h\n"),
-    ("lanczos.py", "        a = float(h[j])", "        a = float(h[0])"),
+    ("lanczos.py", "        a = float(h[-1])  # the coefficient of v_j", "        a = float(h[0])  # the coefficient of v_j"),
     ("lanczos.py", "y, theta = tridiag.expv_e1(alpha, beta[: k - 1], shift)",
      "y, theta = tridiag.expv_e1(alpha, beta[1:k], shift)"),
     ("lanczos.py", "u = beta0 * (V[:, :k] @ y)", "u = (V[:, :k] @ y)"),

@@ -306,3 +306,49 @@ def test_gauss_rule_is_a_monotone_lower_bound():
         assert np.all(sc <= exact[nodes] * (1 + 1e-12)) and np.all(sc >= prev * (1 - 1e-12))
         prev = sc
     assert np.allclose(prev, exact[nodes], rtol=1e-6)
+
+
+# ------------------------------------------------------------------ memory-bounded (windowed) Lanczos
+
+@pytest.mark.parametrize("n,p,m", [(300, 0.05, 20), (1500, 0.01, 60), (500, 0.1, 40)])
+def test_windowed_lanczos_matches_full_reorthogonalisation(n, p, m):
+    # the three-term recurrence (Gram-Schmidt against v_{j-1}, v_j only) approximates exp(A)1 as well
+    # as full reorthogonalisation does: the loss of orthogonality does not spoil f(A)v (FP64)
+    from fixtures import graphs as G
+    keys = G.er_keys(n, p, G.rng_for(5, n, 1))
+    rp, ci = G.csr_from_keys(keys, n)
+    A = dense.csr_to_scipy(n, rp, ci)
+    full = lanczos.lanczos_expv(A, m=m, reorth=2)
+    win = lanczos.lanczos_expv(A, m=m, reorth=1, window=2)
+    assert win.m_used == full.m_used == m
+    uf, uw = np.exp(full.theta) * full.u, np.exp(win.theta) * win.u
+    assert np.max(np.abs(uw - uf)) / np.max(np.abs(uf)) < 1e-12
+    # the first coefficients agree; later ones drift once orthogonality is lost (ghost Ritz values),
+    # which the approximation of exp(A)1 does not notice
+    assert np.max(np.abs(np.asarray(win.alpha[:5]) - np.asarray(full.alpha[:5]))) < 1e-12 * abs(full.alpha[0])
+
+
+def test_windowed_lanczos_needs_the_previous_vector():
+    # with a window of one vector (v_j only) the recurrence drops the beta_{j-1} v_{j-1} term and the
+    # basis loses orthogonality at once: the approximation is visibly wrong -- the window of two is
+    # what makes the three-term recurrence
+    from fixtures import graphs as G
+    n = 400
+    keys = G.er_keys(n, 0.05, G.rng_for(6, 0, 1))
+    rp, ci = G.csr_from_keys(keys, n)
+    A = dense.csr_to_scipy(n, rp, ci)
+    exact = sla.expm(A.toarray()) @ np.ones(n)
+    full = lanczos.lanczos_expv(A, m=25, reorth=2)
+    w2 = lanczos.lanczos_expv(A, m=25, reorth=1, window=2)
+    w1 = lanczos.lanczos_expv(A, m=25, reorth=1, window=1)
+    err = lambda r: np.max(np.abs(np.exp(r.theta) * r.u - exact)) / np.max(np.abs(exact))
+    assert err(w2) < 1.01 * err(full) + 1e-14 and err(w1) > 1e-3
+
+
+def test_windowed_lanczos_exact_on_a_closing_space():
+    P = np.zeros((8, 8))
+    for i in range(7):
+        P[i, i + 1] = P[i + 1, i] = 1.0
+    r = lanczos.lanczos_expv(sp.csr_matrix(P), m=8, reorth=1, window=2)
+    exact = sla.expm(P) @ np.ones(8)
+    assert np.max(np.abs(np.exp(r.theta) * r.u - exact)) / np.max(exact) < 1e-13
