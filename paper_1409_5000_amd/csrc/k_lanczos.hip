@@ -22,15 +22,17 @@
 namespace ebtc {
 namespace {
 
-// Partial dots p_d = sum_rows Vraw_{lo+d}[r] * w[r] (d < cnt = j - lo + 1) of this workgroup's rows,
-// reduced over the workgroup (NT threads) and stored to part_blk[d]. Basis loads are issued eight
-// vectors at a time (clamped to the last one, whose extra contributions are masked) so that many
-// loads are in flight per thread. ring > 0: vector i lives in slot i % ring. red: (NT / 64) * P
-// doubles of LDS.
-template <typename T, int P, int NT>
-__device__ inline void block_dots(const T* __restrict__ Vr, int n, int lo, int j, int ring, int r0, int r1,
+// Partial dots p_d = sum_rows Vraw_{lo+d}[r] * w[r] (d < cnt = j - lo + 1 <= P) of this workgroup's
+// rows, reduced over the workgroup (NT threads) and stored to part_blk[d]. Basis loads are issued
+// min(P, 8) vectors at a time (clamped to the last one, whose extra contributions are masked) so that
+// many loads are in flight per thread. RING > 0: vector i lives in slot i % RING (the ring of the
+// memory-bounded form). red: (NT / 64) * P doubles of LDS.
+template <typename T, int P, int NT, int RING>
+__device__ inline void block_dots(const T* __restrict__ Vr, int n, int lo, int j, int r0, int r1,
                                   const T* wsrc_lds, const T* wsrc_glob, T* wstore, double* part_blk, double* red) {
+  static_assert(P == 2 || P == 32 || P == 64, "lane layout of ReduceScatter");
   constexpr int RPT = kRowsPerBlock / NT;
+  constexpr int CH = P < 8 ? P : 8;
   const int tid = threadIdx.x, cnt = j - lo + 1;
   T p[P];
 #pragma unroll
@@ -42,16 +44,16 @@ __device__ inline void block_dots(const T* __restrict__ Vr, int n, int lo, int j
       const T wv = wsrc_lds ? wsrc_lds[r - r0] : wsrc_glob[r];
       if (wstore) wstore[r] = wv;
 #pragma unroll
-      for (int d0 = 0; d0 < P; d0 += 8) {
+      for (int d0 = 0; d0 < P; d0 += CH) {
         if (d0 < cnt) {
-          T v[8];
+          T v[CH];
 #pragma unroll
-          for (int c = 0; c < 8; ++c) {
+          for (int c = 0; c < CH; ++c) {
             const int i = lo + min(d0 + c, cnt - 1);
-            v[c] = Vr[(size_t)(ring ? i % ring : i) * n + r];
+            v[c] = Vr[(size_t)(RING ? i % RING : i) * n + r];
           }
 #pragma unroll
-          for (int c = 0; c < 8; ++c) p[d0 + c] += (d0 + c < cnt) ? v[c] * wv : (T)0;
+          for (int c = 0; c < CH; ++c) p[d0 + c] += (d0 + c < cnt) ? v[c] * wv : (T)0;
         }
       }
     }
@@ -61,7 +63,8 @@ __device__ inline void block_dots(const T* __restrict__ Vr, int n, int lo, int j
   for (int i = 0; i < P; ++i) pd[i] = (double)p[i];
   const int lane = tid & 63, wave = tid >> 6;
   ReduceScatter<P, 32>::run(pd, lane);
-  if (P == 64 || (lane & 1) == 0) red[wave * P + (P == 64 ? lane : (lane >> 1))] = pd[0];
+  constexpr int LP = 64 / P;  // lanes per value after the reduce-scatter: lane l holds value l / LP
+  if (lane % LP == 0) red[wave * P + lane / LP] = pd[0];
   __syncthreads();
   if (tid < P && tid < cnt) {
     double s = 0.0;
@@ -73,10 +76,9 @@ __device__ inline void block_dots(const T* __restrict__ Vr, int n, int lo, int j
 
 // First basis vector of the Gram-Schmidt window of step j (all of v_0..v_j without a window).
 __device__ inline int window_lo(const LzArgs& a, int j) { return a.window > 0 ? max(0, j - a.window + 1) : 0; }
-__device__ inline int ring_of(const LzArgs& a) { return a.window > 0 ? a.window + 1 : 0; }
 
 // k_dots_step: dot partials of w (written by the SpMV) against the window of Vraw_0..j.
-template <typename T, int P>
+template <typename T, int P, int RING>
 __global__ __launch_bounds__(kBlock) void k_dots_step(LzArgs a, int j) {
   __shared__ double red[kWaves * P];
   const Ref ref = resolve(a);
@@ -85,12 +87,12 @@ __global__ __launch_bounds__(kBlock) void k_dots_step(LzArgs a, int j) {
   if (step_skipped(a, st, j)) return;
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
   const T* Vr = (const T*)a.V + tk.vec_off;
-  block_dots<T, P, kBlock>(Vr, n, window_lo(a, j), j, ring_of(a), r0, r1, nullptr, (const T*)a.W + tk.w_off,
+  block_dots<T, P, kBlock, RING>(Vr, n, window_lo(a, j), j, r0, r1, nullptr, (const T*)a.W + tk.w_off,
                            nullptr, a.part + tk.part_off + (size_t)ref.blk * kPartStride, red);
 }
 
 // Second Gram-Schmidt pass: dots of the once-orthogonalised vector (stored in the slot of j+1).
-template <typename T, int P>
+template <typename T, int P, int RING>
 __global__ __launch_bounds__(kBlock) void k_dots_again(LzArgs a, int j) {
   __shared__ double red[kWaves * P];
   const Ref ref = resolve(a);
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void k_dots_again(LzArgs a, int j) {
   if (step_skipped(a, st, j)) return;
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
   const T* Vr = (const T*)a.V + tk.vec_off;
-  block_dots<T, P, kBlock>(Vr, n, window_lo(a, j), j, ring_of(a), r0, r1, nullptr, Vr + vslot(a, j + 1) * n,
+  block_dots<T, P, kBlock, RING>(Vr, n, window_lo(a, j), j, r0, r1, nullptr, Vr + vslot(a, j + 1) * n,
                            nullptr, a.part + tk.part_off + (size_t)ref.blk * kPartStride, red);
 }
 
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(kBlock) void k_dots_again(LzArgs a, int j) {
 // in the canonical order (identical coefficients everywhere, no inter-workgroup synchronisation),
 // then v~_{j+1} = src - sum_i c_i Vraw_i over the window (FP64 accumulation, rounded once), plus
 // the partial squared norm on the final pass.
-template <typename T, int P>
+template <typename T, int P, int RING>
 __global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, int final_pass, int second) {
   __shared__ double cs[P];
   __shared__ double csum[P][kMaxChunks];
@@ -116,7 +118,8 @@ __global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, 
   const Task tk = a.tasks[ref.task];
   RState* st = a.state + ref.task;
   if (step_skipped(a, st, j)) return;
-  const int tid = threadIdx.x, lo = window_lo(a, j), cnt = j - lo + 1, ring = ring_of(a);
+  constexpr int CH = P < 8 ? P : 8;
+  const int tid = threadIdx.x, lo = window_lo(a, j), cnt = j - lo + 1;
   const double* part = a.part + tk.part_off;
   const int nblk = tk.nblk, chunk = part_chunk(nblk), nch = (nblk + chunk - 1) / chunk;
   for (int item = tid; item < nch * cnt; item += kBlock) {
@@ -159,16 +162,16 @@ __global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, 
     if (r < r1) {
       double acc = (double)src[r];
 #pragma unroll
-      for (int d0 = 0; d0 < P; d0 += 8) {
+      for (int d0 = 0; d0 < P; d0 += CH) {
         if (d0 < cnt) {
-          T v[8];
+          T v[CH];
 #pragma unroll
-          for (int c = 0; c < 8; ++c) {
+          for (int c = 0; c < CH; ++c) {
             const int i = lo + min(d0 + c, cnt - 1);
-            v[c] = Vr[(size_t)(ring ? i % ring : i) * n + r];
+            v[c] = Vr[(size_t)(RING ? i % RING : i) * n + r];
           }
 #pragma unroll
-          for (int c = 0; c < 8; ++c) acc -= cs[d0 + c] * (double)v[c];
+          for (int c = 0; c < CH; ++c) acc -= cs[d0 + c] * (double)v[c];
         }
       }
       const T out = (T)acc;
@@ -352,12 +355,6 @@ __global__ void k_blkmap(const Task* tasks, int32_t* blkmap) {
   for (int b = threadIdx.x; b < tk.nblk; b += blockDim.x) blkmap[tk.blk_begin + b] = (int32_t)blockIdx.x;
 }
 
-template <typename T, int P>
-hipError_t dots_step_t(int j, const LzArgs& a, int64_t nb, hipStream_t s) {
-  hipLaunchKernelGGL((k_dots_step<T, P>), dim3((unsigned)nb), dim3(kBlock), 0, s, a, j);
-  return hipGetLastError();
-}
-
 }  // namespace
 
 hipError_t launch_blkmap(const Task* tasks, int64_t R, int32_t* blkmap, hipStream_t s) {
@@ -407,27 +404,31 @@ hipError_t launch_accum(int dtype, const LzArgs& a, int j, int64_t nb, hipStream
   return hipGetLastError();
 }
 
+// Gram-Schmidt kernels by basis window: the memory-bounded form (window 2, ring of three slots)
+// takes the two-vector instantiation; the full basis takes 32 or 64 vectors per launch.
+#define EBTC_GS_LAUNCH(KERNEL, T, ...)                                                   \
+  do {                                                                                   \
+    if (a.window > 0) {                                                                  \
+      if (a.window != 2) return hipErrorInvalidValue;                                    \
+      hipLaunchKernelGGL((KERNEL<T, 2, 3>), g, b, 0, s, __VA_ARGS__);                    \
+    } else if (window_count(a, j) <= 32) {                                               \
+      hipLaunchKernelGGL((KERNEL<T, 32, 0>), g, b, 0, s, __VA_ARGS__);                   \
+    } else {                                                                             \
+      hipLaunchKernelGGL((KERNEL<T, 64, 0>), g, b, 0, s, __VA_ARGS__);                   \
+    }                                                                                    \
+  } while (0)
+
 hipError_t launch_dots_step(int dtype, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
   const dim3 g((unsigned)nb), b(kBlock);
-  if (dtype == EBTC_F64) {
-    if (window_count(a, j) <= 32) hipLaunchKernelGGL((k_dots_step<double, 32>), g, b, 0, s, a, j);
-    else hipLaunchKernelGGL((k_dots_step<double, 64>), g, b, 0, s, a, j);
-  } else {
-    if (window_count(a, j) <= 32) hipLaunchKernelGGL((k_dots_step<float, 32>), g, b, 0, s, a, j);
-    else hipLaunchKernelGGL((k_dots_step<float, 64>), g, b, 0, s, a, j);
-  }
+  if (dtype == EBTC_F64) EBTC_GS_LAUNCH(k_dots_step, double, a, j);
+  else EBTC_GS_LAUNCH(k_dots_step, float, a, j);
   return hipGetLastError();
 }
 
 hipError_t launch_dots_again(int dtype, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
   const dim3 g((unsigned)nb), b(kBlock);
-  if (dtype == EBTC_F64) {
-    if (window_count(a, j) <= 32) hipLaunchKernelGGL((k_dots_again<double, 32>), g, b, 0, s, a, j);
-    else hipLaunchKernelGGL((k_dots_again<double, 64>), g, b, 0, s, a, j);
-  } else {
-    if (window_count(a, j) <= 32) hipLaunchKernelGGL((k_dots_again<float, 32>), g, b, 0, s, a, j);
-    else hipLaunchKernelGGL((k_dots_again<float, 64>), g, b, 0, s, a, j);
-  }
+  if (dtype == EBTC_F64) EBTC_GS_LAUNCH(k_dots_again, double, a, j);
+  else EBTC_GS_LAUNCH(k_dots_again, float, a, j);
   return hipGetLastError();
 }
 
@@ -435,15 +436,12 @@ hipError_t launch_update(int dtype, int j, bool from_w, bool final_pass, bool se
                          int64_t nb, hipStream_t s) {
   const dim3 g((unsigned)nb), b(kBlock);
   const int fw = from_w ? 1 : 0, fp = final_pass ? 1 : 0, sp = second_pass ? 1 : 0;
-  if (dtype == EBTC_F64) {
-    if (window_count(a, j) <= 32) hipLaunchKernelGGL((k_update<double, 32>), g, b, 0, s, a, j, fw, fp, sp);
-    else hipLaunchKernelGGL((k_update<double, 64>), g, b, 0, s, a, j, fw, fp, sp);
-  } else {
-    if (window_count(a, j) <= 32) hipLaunchKernelGGL((k_update<float, 32>), g, b, 0, s, a, j, fw, fp, sp);
-    else hipLaunchKernelGGL((k_update<float, 64>), g, b, 0, s, a, j, fw, fp, sp);
-  }
+  if (dtype == EBTC_F64) EBTC_GS_LAUNCH(k_update, double, a, j, fw, fp, sp);
+  else EBTC_GS_LAUNCH(k_update, float, a, j, fw, fp, sp);
   return hipGetLastError();
 }
+
+#undef EBTC_GS_LAUNCH
 
 hipError_t launch_combine(int dtype, const LzArgs& a, int64_t nb, hipStream_t s) {
   if (dtype == EBTC_F64)
