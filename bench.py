@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -60,6 +62,66 @@ def update_bytes(n, j, es):
 
 def combine_bytes(n, k, es):
     return (k + 1) * n * es
+
+
+class DeviceDrawn:
+    """Host-side view of a batch drawn on the device: sizes and offsets, and realizations copied to
+    the host on request (for the oracle's sample)."""
+
+    def __init__(self, b, w, targets):
+        self.b = b
+        self.n = np.asarray(b.graph_n, np.int32)
+        self.nreal = np.asarray(b.graph_nreal, np.int32)
+        self.K = np.array([g.K for g in w.graphs], np.int32)
+        self.targets = targets
+        self.rowptr_off = b.rowptr_off
+        self.nnz_off = b.nnz_off
+        self.graph_of = np.repeat(np.arange(self.n.size, dtype=np.int32), self.nreal)
+        self.values = None
+        self.dtype = np.float64 if w.dtype == "f64" else np.float32
+        self._cache = {}
+
+    @property
+    def R(self) -> int:
+        return int(self.rowptr_off.size)
+
+    def prefetch(self, rs) -> None:
+        for r in rs:
+            self.csr(r)
+
+    def csr(self, r: int):
+        if r not in self._cache:
+            n = int(self.n[int(self.graph_of[r])])
+            o, a, e = int(self.rowptr_off[r]), int(self.nnz_off[r]), int(self.nnz_off[r + 1])
+            self._cache[r] = (n, self.b.row_ptr[o:o + n + 1].cpu().numpy(), self.b.col_idx[a:e].cpu().numpy(), None)
+        return self._cache[r]
+
+
+def device_batch(w, realizations=None):
+    """The workload's realizations drawn on the device: the fixtures' target placement and pattern per
+    graph, one Philox seed per graph derived from the fixtures' root seed."""
+    import torch
+
+    from fixtures import configs as C
+    from paper_1409_5000_amd import api
+    graphs, targets = [], []
+    for g, spec in enumerate(w.graphs):
+        draw = C.draw_graph(w.ci, g, spec)
+        seed = int(C.G.rng_for(w.ci, g, 1 << 30).integers(0, 1 << 62))
+        d = dict(family=spec.family, n=spec.n, count=min(spec.N, realizations or spec.N), seed=seed,
+                 targets=draw.targets, pattern=np.stack([draw.pattern // spec.t, draw.pattern % spec.t], 1))
+        if spec.family == "er":
+            d["p"] = spec.bg
+        else:
+            d["k"] = int(spec.bg)
+            d["beta"] = spec.ws_beta
+        graphs.append(d)
+        targets.append(draw.targets)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = api.generated_batch(graphs, dtype=w.dtype, chunk=64, values=w.ci != 4)
+    torch.cuda.synchronize()
+    return b, DeviceDrawn(b, w, targets), time.perf_counter() - t0
 
 
 def kernel_hash() -> str:
@@ -101,6 +163,8 @@ def main() -> int:
     ap.add_argument("--reorth", type=int, default=1, choices=[0, 1, 2],
                     help="Gram-Schmidt passes against the whole basis; 0 = three-term recurrence, two passes, "
                          "three stored basis vectors (memory-bounded form)")
+    ap.add_argument("--device-gen", action="store_true",
+                    help="draw the realizations on the device (ebtc_generate_*) instead of the host fixtures")
     ap.add_argument("--adjoint", action="store_true", help="also time the adjoint (always on for workload 3)")
     ap.add_argument("--profile-run", action="store_true",
                     help="for rocprofv3: one eager batched pass per gather form plus a 1 GiB copy (counter calibration)")
@@ -128,15 +192,22 @@ def main() -> int:
 
     w = C.workload(args.config)
     t0 = time.time()
-    # the uneven workload (about 1e10 entries) is unweighted and carried as a pattern (values NULL =
-    # all ones, FP32 arithmetic), which halves its host and device footprint
-    hb = C.build_parallel(w, workers=workers, realizations=args.realizations or None, with_values=w.ci != 4,
-                          progress=lambda i, t: log(f"generated {i}/{t} realizations ({time.time() - t0:.0f}s)"))
-    log(f"generated {w.name}: R={hb.R} nnz={hb.nnz_off[-1]} in {time.time() - t0:.1f}s")
+    generation = None
+    if args.device_gen:
+        b, hb, gen_s = device_batch(w, args.realizations or None)
+        generation = {"where": "device", "seconds": round(gen_s, 4)}
+        log(f"drew {w.name} on the device: R={hb.R} nnz={hb.nnz_off[-1]} in {gen_s:.3f}s")
+    else:
+        # the uneven workload (about 1e10 entries) is unweighted and carried as a pattern (values NULL =
+        # all ones, FP32 arithmetic), which halves its host and device footprint
+        hb = C.build_parallel(w, workers=workers, realizations=args.realizations or None, with_values=w.ci != 4,
+                              progress=lambda i, t: log(f"generated {i}/{t} realizations ({time.time() - t0:.0f}s)"))
+        generation = {"where": "host", "seconds": round(time.time() - t0, 2), "workers": workers}
+        log(f"generated {w.name}: R={hb.R} nnz={hb.nnz_off[-1]} in {time.time() - t0:.1f}s")
+        b = api.Batch.from_host(hb)
     m, tol, m_max = w.m, (w.tol or 1e-6), (w.m_max or 60)
-    b = api.Batch.from_host(hb)
     es = 8 if w.dtype == "f64" else 4
-    has_val = hb.values is not None
+    has_val = b.values is not None
     K = hb.K
 
     form = {"spmv": "auto" if args.spmv == "tuned" else args.spmv, "lanes": args.lanes, "seg_len": args.seg_len,
@@ -255,8 +326,8 @@ def main() -> int:
     sp_bytes = dt_bytes = up_bytes = 0.0
     passes = max(1, args.reorth)  # Gram-Schmidt passes per step
     for r in range(hb.R):
-        n, rp, ci, _ = hb.csr(r)
-        z = ci.size
+        n = int(hb.n[int(hb.graph_of[r])])
+        z = int(hb.nnz_off[r + 1] - hb.nnz_off[r])
         k = int(m_used[r])
         # the memory-bounded form orthogonalises against v_{j-1}, v_j only and runs the steps twice
         # (the second pass stops one step earlier: its last vector is v_{k-1})
@@ -292,7 +363,9 @@ def main() -> int:
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": w.dtype,
-        "data": "synthetic (seeded ER/WS/BA realizations with an embedded target, generated on the host)",
+        "data": "synthetic (seeded ER/WS/BA realizations with an embedded target, generated on the "
+                + ("device" if args.device_gen else "host") + ")",
+        "generation": generation,
         "config": {"workload": w.name, "graphs": int(hb.n.size), "realizations": hb.R,
                    "n": [int(x) for x in hb.n], "nnz_total": int(hb.nnz_off[-1]), "m": m,
                    "adaptive_tol": w.tol if m == 0 else None, "reorth": args.reorth, "K": [int(x) for x in K[:4]],
@@ -317,6 +390,8 @@ def main() -> int:
         from oracle import scores as oscores
         G_or = args.oracle_graphs or int(hb.n.size)
         reals = [r for r in range(hb.R) if int(hb.graph_of[r]) < G_or]
+        if args.device_gen:
+            hb.prefetch(reals)  # host copies before the oracle's worker processes fork
         t0 = time.perf_counter()
         ref = oscores.batch_scores(hb, m=m, tol=w.tol, m_max=m_max, workers=P, realizations=reals)
         cpu_wall = time.perf_counter() - t0

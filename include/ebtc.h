@@ -280,6 +280,66 @@ int ebtc_profile_phases(ebtc_batch* batch, const ebtc_opts* opts, void* ws, size
 int ebtc_validate_ws_bytes(ebtc_batch* batch, size_t* ws_bytes);
 int ebtc_validate(ebtc_batch* batch, void* ws, size_t ws_bytes, int64_t* first_bad, void* stream);
 
+/* ---------------------------------------------------------------- realization generator          */
+/* Background graphs drawn on the device and written as the batch's CSR: the families of the
+ * experiments (Introduction, "Multiple backgrounds scenario", "Single background scenario",
+ * Tables 1-3), N independent draws on one node set ("Signal processing on graphs"), the target
+ * pattern embedded (edges among the target nodes replaced by the pattern). Random numbers:
+ * Philox4x32-10 (Salmon et al., SC 2011) keyed by `seed`, counter (c0, c1, realization, family tag),
+ * so the result depends only on the spec, never on launch shapes. Definitions:
+ *   ER  row i visits j > i by geometric skips j <- j + 1 + floor(ln U / ln(1 - p)), U = (w + 1/2) 2^-32
+ *       for the words of counters (i, 0, r, 1), (i, 1, r, 1), ... in order; ln is evaluated with
+ *       correctly rounded operations only (frexp, atanh series, no fused multiply-add), so the skips
+ *       are reproducible bit for bit on any IEEE machine. Each pair is an edge with probability p.
+ *   WS  ring lattice of degree k; lattice edge e = (i, i + 1 + e mod (k/2)), i = e div (k/2), is
+ *       rewired iff w0 < floor(beta 2^32) (counter (e, 0, r, 2)) to the far end
+ *       (i + 1 + floor(w1 (n - 1) / 2^32)) mod n; coinciding edges are kept once.
+ *   BA  seed star on k + 1 nodes; each later node attaches k edges to endpoint slots drawn uniformly
+ *       (64-bit, counter (e, 0, r, 3)) from the endpoint list of all earlier edges
+ *       (degree-proportional); a node's repeated picks collapse to one edge.
+ * Realization r of the call is the spec's realization first + r (counter word 2). */
+enum ebtc_gen_family { EBTC_GEN_ER = 0, EBTC_GEN_WS = 1, EBTC_GEN_BA = 2 };
+
+typedef struct {
+  int32_t family;         /* enum ebtc_gen_family                                                */
+  int32_t n;              /* nodes: ER >= 1; WS >= k + 2; BA >= k + 2                            */
+  double p;               /* ER: edge probability in [0, 1]                                      */
+  int32_t k;              /* WS: even lattice degree >= 2; BA: edges per new node >= 1            */
+  int32_t count;          /* realizations drawn by this call, >= 1                               */
+  double beta;            /* WS: rewiring probability in [0, 1]                                  */
+  uint64_t seed;          /* Philox key (low word, high word)                                    */
+  int64_t first;          /* realization index of the call's first realization; first + count <= 2^32 */
+  int32_t t;              /* target nodes, 0 = no target                                         */
+  int32_t pattern_edges;  /* edges of the target pattern                                         */
+  const int32_t* targets; /* host [t]: distinct node ids in [0, n), in pattern order              */
+  const int32_t* pattern; /* host [pattern_edges][2]: local ends a != b in [0, t)                 */
+} ebtc_gen_spec;
+
+/* Workspace bytes for one ebtc_generate_count / ebtc_generate_fill pair (host call; the radix sort's
+ * temporary storage depends on the current device's architecture, so a device must be present,
+ * else EBTC_EHIP after the spec has been validated). Validates the spec: EBTC_EINVAL for out-of-range fields, repeated targets or bad pattern ends; EBTC_ENOTSUPPORTED
+ * when the keys (realization, a, b) would not fit 63 bits (count n^2 >= 2^63: draw fewer
+ * realizations per call). For G(n, p) the candidate buffer holds the mean edge count plus 8
+ * standard deviations per realization. */
+int ebtc_generate_plan(const ebtc_gen_spec* spec, size_t* ws_bytes);
+/* Draws the spec's realizations, asynchronously on `stream`, and writes their row pointers:
+ *   ws        device, >= ebtc_generate_plan bytes; it carries the drawn graphs to ebtc_generate_fill
+ *             and must not be reused in between
+ *   row_ptr   device int32 [count][n + 1]: realization r's local row pointers (first entry 0)
+ *   nnz       device int64 [count]: stored entries of realization r (twice its edges), or -1 if its
+ *             draw overflowed the candidate buffer or it would hold 2^31 entries or more
+ * The caller reads nnz to size col_idx. Errors: EINVAL, EWORKSPACE, EHIP. */
+int ebtc_generate_count(const ebtc_gen_spec* spec, void* ws, size_t ws_bytes, int32_t* row_ptr, int64_t* nnz,
+                        void* stream);
+/* Writes the columns of the realizations counted by the preceding ebtc_generate_count on the same
+ * ws and spec, asynchronously on `stream`:
+ *   dest_off  host [count]: offset of realization r's first entry in col_idx
+ *   col_idx   device int32: realization r's nnz[r] columns at col_idx[dest_off[r] ...], sorted
+ *             within each row, both (i, j) and (j, i) stored, no self-loops
+ * Errors: EINVAL, EWORKSPACE, EHIP. */
+int ebtc_generate_fill(const ebtc_gen_spec* spec, void* ws, size_t ws_bytes, const int64_t* dest_off,
+                       int32_t* col_idx, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,9 @@ EXPORTED = [
     "ebtc_batch_destroy", "ebtc_plan", "ebtc_scores", "ebtc_topk_ws_bytes", "ebtc_topk", "ebtc_spmv",
     "ebtc_tridiag_expv", "ebtc_validate_ws_bytes", "ebtc_validate", "ebtc_profile_phases", "ebtc_plan_backward",
     "ebtc_scores_backward", "ebtc_tune", "ebtc_subgraph_centrality_ws_bytes", "ebtc_subgraph_centrality",
+    "ebtc_generate_plan", "ebtc_generate_count", "ebtc_generate_fill",
 ]
+GEN_FAMILIES = {"er": 0, "ws": 1, "ba": 2}
 SPMV_FORMS = {"auto": 0, "stream": 1, "lanes": 2, "staged": 3, "segmented": 4}
 PHASES = ["start", "spmv", "dots", "update", "tridiag", "combine", "sum", "prepare"]
 
@@ -44,6 +46,14 @@ class Opts(ctypes.Structure):
         ("m", c_int32), ("m_max", c_int32), ("tol", c_double), ("reorth", c_int32), ("schedule", c_int32),
         ("use_hipgraph", c_int32), ("shift", c_int32), ("spmv", c_int32), ("lanes_per_row", c_int32),
         ("hub_threshold", c_int32), ("seg_len", c_int32),
+    ]
+
+
+class GenSpec(ctypes.Structure):
+    _fields_ = [
+        ("family", c_int32), ("n", c_int32), ("p", c_double), ("k", c_int32), ("count", c_int32),
+        ("beta", c_double), ("seed", ctypes.c_uint64), ("first", c_int64), ("t", c_int32),
+        ("pattern_edges", c_int32), ("targets", POINTER(c_int32)), ("pattern", POINTER(c_int32)),
     ]
 
 
@@ -90,6 +100,9 @@ def lib() -> ctypes.CDLL:
                               POINTER(c_double), vp]),
         "ebtc_subgraph_centrality_ws_bytes": (c_int, [c_int32, c_int32, c_int32, c_int32, POINTER(sz)]),
         "ebtc_subgraph_centrality": (c_int, [c_int32, c_int32, vp, vp, vp, c_int32, vp, c_int32, vp, vp, sz, vp]),
+        "ebtc_generate_plan": (c_int, [POINTER(GenSpec), POINTER(sz)]),
+        "ebtc_generate_count": (c_int, [POINTER(GenSpec), vp, sz, vp, vp, vp]),
+        "ebtc_generate_fill": (c_int, [POINTER(GenSpec), vp, sz, POINTER(c_int64), vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -132,10 +132,13 @@ class Batch:
         self.G = int(self.graph_n.size)
         self.R = int(self.rowptr_off.size)
         self.total_scores = int(self.graph_n.sum())
-        self.row_ptr = torch.as_tensor(np.ascontiguousarray(row_ptr, dtype=np.int32)).to(self.device)
-        self.col_idx = torch.as_tensor(np.ascontiguousarray(col_idx, dtype=np.int32)).to(self.device)
-        self.values = None if values is None else torch.as_tensor(
-            np.ascontiguousarray(values, dtype=self.ndtype)).to(self.device)
+        def dev(x, np_dtype, t_dtype):  # host arrays are copied; device tensors are used as they are
+            if isinstance(x, torch.Tensor):
+                return x.to(device=self.device, dtype=t_dtype).contiguous()
+            return torch.as_tensor(np.ascontiguousarray(x, dtype=np_dtype)).to(self.device)
+        self.row_ptr = dev(row_ptr, np.int32, torch.int32)
+        self.col_idx = dev(col_idx, np.int32, torch.int32)
+        self.values = None if values is None else dev(values, self.ndtype, self.tdtype)
         i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
         desc = A.BatchDesc(
             self.code, self.G, self.R,
@@ -222,6 +225,72 @@ class Batch:
         bad = ctypes.c_int64()
         A.check(A.lib().ebtc_validate(self.handle, _vp(wst), ws.value, ctypes.byref(bad), current_stream()))
         return int(bad.value)
+
+
+def _gen_spec(family: str, n: int, count: int, seed: int, first: int = 0, p: float = 0.0, k: int = 0,
+              beta: float = 0.0, targets=None, pattern=None):
+    tg = np.ascontiguousarray(np.asarray(targets if targets is not None else [], dtype=np.int32).ravel())
+    pt = np.ascontiguousarray(np.asarray(pattern if pattern is not None else np.zeros((0, 2)), dtype=np.int32)
+                              .reshape(-1, 2))
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    spec = A.GenSpec(A.GEN_FAMILIES[family], int(n), float(p), int(k), int(count), float(beta),
+                     int(seed) & 0xFFFFFFFFFFFFFFFF, int(first), int(tg.size), int(pt.shape[0]),
+                     tg.ctypes.data_as(i32p) if tg.size else None, pt.ctypes.data_as(i32p) if pt.size else None)
+    return spec, (tg, pt)
+
+
+def generate(family: str, n: int, count: int, seed: int, first: int = 0, p: float = 0.0, k: int = 0,
+             beta: float = 0.0, targets=None, pattern=None, device: str = "cuda"):
+    """Draws `count` realizations on the device (ebtc_generate_count / ebtc_generate_fill): family "er"
+    (edge probability p), "ws" (lattice degree k, rewiring beta) or "ba" (k edges per new node), with
+    the target pattern (local pairs) embedded on `targets`. Realization r of the call is the family's
+    realization first + r of `seed`. Returns (row_ptr int32 [count * (n + 1)], col_idx int32,
+    nnz int64 numpy [count])."""
+    spec, keep = _gen_spec(family, n, count, seed, first, p, k, beta, targets, pattern)
+    ws = ctypes.c_size_t()
+    A.check(A.lib().ebtc_generate_plan(ctypes.byref(spec), ctypes.byref(ws)))
+    dev = torch.device(device)
+    wst = torch.empty(max(1, ws.value), dtype=torch.uint8, device=dev)
+    row_ptr = torch.empty(count * (n + 1), dtype=torch.int32, device=dev)
+    nnz = torch.empty(count, dtype=torch.int64, device=dev)
+    st = current_stream()
+    A.check(A.lib().ebtc_generate_count(ctypes.byref(spec), _vp(wst), ws.value, _vp(row_ptr), _vp(nnz), st))
+    nnz_h = nnz.cpu().numpy()
+    if (nnz_h < 0).any():
+        raise A.EbtcError(A.EBTC_EWORKSPACE, "a realization overflowed the candidate buffer or 2^31 entries")
+    dest = np.ascontiguousarray(np.concatenate([[0], np.cumsum(nnz_h)[:-1]]).astype(np.int64))
+    col = torch.empty(max(1, int(nnz_h.sum())), dtype=torch.int32, device=dev)
+    A.check(A.lib().ebtc_generate_fill(ctypes.byref(spec), _vp(wst), ws.value,
+                                       dest.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _vp(col), st))
+    del keep
+    return row_ptr, col[:int(nnz_h.sum())], nnz_h
+
+
+def generated_batch(graphs: list, dtype: str = "f32", device: str = "cuda", chunk: int = 0,
+                    values: bool = False) -> "Batch":
+    """A Batch whose realizations are drawn on the device. graphs: dicts with the arguments of
+    `generate` (family, n, count = realizations of the graph, seed, first, p / k / beta, targets,
+    pattern). chunk > 0 draws at most that many realizations per call (bounds the workspace);
+    values: store explicit unit weights (else the pattern-only form, values NULL)."""
+    rps, cols, nnz_all, gn, gr = [], [], [], [], []
+    for g in graphs:
+        g = dict(g)
+        count = int(g.pop("count"))
+        first = int(g.pop("first", 0))
+        step = chunk if chunk > 0 else count
+        for c0 in range(0, count, step):
+            rp, ci, nz = generate(count=min(step, count - c0), first=first + c0, device=device, **g)
+            rps.append(rp)
+            cols.append(ci)
+            nnz_all.append(nz)
+        gn.append(int(g["n"]))
+        gr.append(count)
+    nnz = np.concatenate(nnz_all)
+    rowptr_off = np.concatenate([[0], np.cumsum(np.repeat(np.array(gn, np.int64) + 1, gr))[:-1]])
+    nnz_off = np.concatenate([[0], np.cumsum(nnz)]).astype(np.int64)
+    col = torch.cat(cols)
+    vals = torch.ones(col.numel(), dtype=_DT[dtype][1], device=col.device) if values else None
+    return Batch(gn, gr, rowptr_off, nnz_off, torch.cat(rps), col, vals, dtype, device)
 
 
 def spmv(row_ptr: torch.Tensor, col_idx: torch.Tensor, values: torch.Tensor | None, x: torch.Tensor,

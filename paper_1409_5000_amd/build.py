@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libebtc.so")
-SOURCES = ["k_lanczos.hip", "k_spmv.hip", "k_tridiag.hip", "k_topk.hip", "k_adjoint.hip", "api.cpp"]
+SOURCES = ["k_lanczos.hip", "k_spmv.hip", "k_tridiag.hip", "k_topk.hip", "k_adjoint.hip", "k_generate.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled for every device compile.

@@ -18,6 +18,13 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+}  // namespace
+
+// Error reporting for entry points defined in other translation units.
+int ebtc::report_error(int code, const std::string& msg) { return fail(code, msg); }
+
+namespace {
+
 #define EBTC_HIP(call)                                                                          \
   do {                                                                                          \
     hipError_t e_ = (call);                                                                     \

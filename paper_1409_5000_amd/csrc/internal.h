@@ -5,10 +5,14 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 #include "../../include/ebtc.h"
 
 namespace ebtc {
+
+// Records msg as ebtc_last_error() and returns code (shared by every entry point of the library).
+int report_error(int code, const std::string& msg);
 
 constexpr int kBlock = 256;          // threads of a streaming workgroup (4 waves of 64)
 constexpr int kRowsPerBlock = 2048;  // CSR rows owned by one workgroup in the Lanczos kernels

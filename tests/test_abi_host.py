@@ -263,3 +263,39 @@ def test_subgraph_centrality_validates_and_sizes():
                                       None) == A.EBTC_EINVAL
     assert L.ebtc_subgraph_centrality(0, 10, FAKE_DEV, FAKE_DEV, None, 1, FAKE_DEV, 5, FAKE_DEV, FAKE_DEV, 16,
                                       None) == A.EBTC_EWORKSPACE
+
+
+@pytest.mark.parametrize("kw,code,text", [
+    (dict(family="ws", n=1000, k=7), A.EBTC_EINVAL, "even k"),
+    (dict(family="ws", n=6, k=6), A.EBTC_EINVAL, "n >= k + 2"),
+    (dict(family="ws", n=100, k=4, beta=1.5), A.EBTC_EINVAL, "beta"),
+    (dict(family="er", n=100, p=1.5), A.EBTC_EINVAL, "p must be"),
+    (dict(family="er", n=0, p=0.1), A.EBTC_EINVAL, "n >= 1"),
+    (dict(family="ba", n=5, k=4), A.EBTC_EINVAL, "n >= k + 2"),
+    (dict(family="ba", n=50, k=0), A.EBTC_EINVAL, "k >= 1"),
+    (dict(family="er", n=100, p=0.1, targets=[1, 1]), A.EBTC_EINVAL, "repeated target"),
+    (dict(family="er", n=100, p=0.1, targets=[1, 100]), A.EBTC_EINVAL, "out of range"),
+    (dict(family="er", n=100, p=0.1, targets=[1, 2], pattern=[[0, 2]]), A.EBTC_EINVAL, "pattern edge"),
+    (dict(family="er", n=100, p=0.1, targets=[1, 2], pattern=[[1, 1]]), A.EBTC_EINVAL, "pattern edge"),
+    (dict(family="er", n=100, p=0.1, count=0), A.EBTC_EINVAL, "count"),
+    (dict(family="er", n=100, p=0.1, first=(1 << 32) - 1, count=2), A.EBTC_EINVAL, "2^32"),
+    (dict(family="er", n=2_000_000_000, p=1e-9, count=4), A.EBTC_ENOTSUPPORTED, "2^63"),
+])
+def test_generate_plan_validates(kw, code, text):
+    # the spec is checked before anything touches a device
+    from paper_1409_5000_amd.api import _gen_spec
+    kw = {"count": 1, "seed": 7, **kw}
+    spec, keep = _gen_spec(**kw)
+    ws = ctypes.c_size_t()
+    assert A.lib().ebtc_generate_plan(ctypes.byref(spec), ctypes.byref(ws)) == code
+    assert text in A.lib().ebtc_last_error().decode()
+    assert A.lib().ebtc_generate_plan(ctypes.byref(spec), None) == A.EBTC_EINVAL
+
+
+def test_generate_spec_layout():
+    # the C struct: int32 family, n; double p; int32 k, count; double beta; uint64 seed; int64 first;
+    # int32 t, pattern_edges; two pointers
+    f = {name: getattr(A.GenSpec, name).offset for name, _ in A.GenSpec._fields_}
+    assert (f["p"], f["k"], f["beta"], f["seed"], f["first"], f["t"], f["targets"], f["pattern"]) == \
+        (8, 16, 24, 32, 40, 48, 56, 64)
+    assert ctypes.sizeof(A.GenSpec) == 72
