@@ -37,7 +37,7 @@ def make_opts(m: int = 30, tol: float = 1e-6, m_max: int = 60, reorth: int = 1, 
               seg_len: int = 0) -> A.Opts:
     """Options of one call. spmv: "auto" (the tuned form, else "stream"), "stream", "lanes" (lanes per
     row, default 8), "staged" (segment length seg_len, default the largest that fits in LDS) or
-    "segmented" (seg_len columns per segment, default 16384 FP32 / 8192 FP64)."""
+    "segmented" (seg_len columns per segment, default 12288 FP32 / 6144 FP64)."""
     return A.default_opts(m=m, tol=tol, m_max=m_max, reorth=reorth, schedule=_SCHED[schedule],
                           use_hipgraph=int(hipgraph), shift=int(shift), spmv=A.SPMV_FORMS[spmv], lanes_per_row=lanes,
                           hub_threshold=hub, seg_len=seg_len)
@@ -195,7 +195,7 @@ class Batch:
         Plan Runs after tuning: the chosen form sets their workspace size."""
         opts = make_opts(**kw)
         ws = ctypes.c_size_t()
-        seg = make_opts(**{**kw, "spmv": "segmented", "seg_len": 4096 if self.dtype == "f64" else 8192})
+        seg = make_opts(**{**kw, "spmv": "segmented", "seg_len": 3072 if self.dtype == "f64" else 6144})
         if A.lib().ebtc_plan(self.handle, ctypes.byref(seg), ctypes.byref(ws), None) != A.EBTC_OK:
             A.check(A.lib().ebtc_plan(self.handle, ctypes.byref(opts), ctypes.byref(ws), None))
         wst = torch.empty(max(1, ws.value), dtype=torch.uint8, device=self.device)
@@ -204,7 +204,7 @@ class Batch:
         A.check(A.lib().ebtc_tune(self.handle, ctypes.byref(opts), _vp(wst), ws.value, ctypes.byref(form),
                                   ctypes.byref(lanes), ctypes.byref(segl), ms, current_stream()))
         names = {v: k for k, v in A.SPMV_FORMS.items()}
-        small = 4096 if self.dtype == "f64" else 8192
+        small = 3072 if self.dtype == "f64" else 6144
         labels = ["stream", "lanes4", "lanes8", "lanes16", "lanes32", "staged", f"segmented{small}",
                   f"segmented{2 * small}"]
         return {"form": names[form.value], "lanes": lanes.value, "seg_len": segl.value,

@@ -38,7 +38,7 @@ struct Layout {
   size_t off_tasks = 0, off_graphs = 0, off_blkmap = 0, off_state = 0, off_part = 0, off_npart = 0, off_V = 0,
          off_W = 0, off_U = 0;
   // column-segmented SpMV arenas (present when the plan uses that form)
-  size_t off_segflag = 0, off_segcnt = 0, off_segcol = 0, off_segval = 0;
+  size_t off_segflag = 0, off_segcnt = 0, off_segwoff = 0, off_segcol = 0, off_segval = 0;
   size_t total = 0;
   int64_t total_blocks = 0;
 };
@@ -168,6 +168,8 @@ Layout make_layout(const ebtc_batch* b, const ebtc_opts* o, const SpmvPlan& sp) 
     off = align_up(off + sizeof(int32_t) * blocks);
     L.off_segcnt = off;
     off = align_up(off + (size_t)sp.smax * kRowsPerBlock * blocks);
+    L.off_segwoff = off;
+    off = align_up(off + sizeof(uint16_t) * (size_t)sp.smax * 17 * blocks);
     L.off_segcol = off;
     off = align_up(off + sizeof(uint16_t) * z);
     L.off_segval = off;
@@ -221,8 +223,7 @@ SpmvPlan spmv_form(const ebtc_batch* b, int form, int lanes, int seg_len, int hu
     p.seglen = seg_len > 0 ? std::min(seg_len, maxseg) : maxseg;
   }
   if (form == EBTC_SPMV_SEGMENTED) {
-    const int dflt = b->dtype == EBTC_F64 ? 8192 : 16384;
-    p.segcols = std::min(seg_len > 0 ? seg_len : dflt, seg_max_cols(b->dtype));
+    p.segcols = std::min(seg_len > 0 ? seg_len : seg_max_cols(b->dtype), seg_max_cols(b->dtype));
     p.smax = (b->n_max + p.segcols - 1) / p.segcols;
   }
   p.hub = hub ? hub : 16 * (p.lanes ? p.lanes : 8);
@@ -262,10 +263,15 @@ LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout
     a.seg_stride = sp.smax * kRowsPerBlock;
     a.seg_flag = (int32_t*)(ws + L.off_segflag);
     a.seg_cnt = (uint8_t*)(ws + L.off_segcnt);
+    a.seg_woff = (uint16_t*)(ws + L.off_segwoff);
+    a.seg_wstride = sp.smax * 17;
     a.seg_col = (uint16_t*)(ws + L.off_segcol);
     a.seg_val = b->values ? (void*)(ws + L.off_segval) : nullptr;
+    // 16-byte slice stores need every slice length to be a whole number of vectors: n and the
+    // segment length multiples of the vector width (else a store would pass the slice's end, into
+    // the other LDS buffer)
     const int vw = 16 / elem_size(b->dtype);
-    a.seg_vec = 1;
+    a.seg_vec = sp.segcols % vw == 0 ? 1 : 0;
     for (int32_t g = 0; g < b->G; ++g)
       if (b->n[g] % vw != 0) a.seg_vec = 0;
   }
@@ -725,7 +731,7 @@ int ebtc_tune(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, int3
   for (int i = 0; i < 4; ++i) cands.push_back({spmv_form(b, EBTC_SPMV_LANE_GROUPS, 4 << i, 0, o->hub_threshold), 1 + i});
   const int maxseg = staged_max_seglen(b->dtype);
   if ((b->n_max + maxseg - 1) / maxseg <= 8) cands.push_back({spmv_form(b, EBTC_SPMV_LDS_STAGED, 0, 0, 0), 5});
-  const int small_seg = b->dtype == EBTC_F64 ? 4096 : 8192;
+  const int small_seg = seg_max_cols(b->dtype) / 2;
   for (int i = 0; i < 2; ++i) {
     const SpmvPlan p = spmv_form(b, EBTC_SPMV_SEGMENTED, 0, small_seg << i, 0);
     if (p.smax <= kSegMax && make_layout(b, o, p).total <= ws_bytes) cands.push_back({p, 6 + i});

@@ -95,7 +95,11 @@ struct LzArgs {
   uint8_t* seg_cnt;        // [row blocks][seg_stride] entries of row r in segment s at [s * rows + r]
   uint16_t* seg_col;       // [entries] column - s * seg_cols, a block's entries ordered by (segment, row)
   void* seg_val;           // [entries] values in the same order (nullptr for pattern-only graphs)
-  int32_t seg_vec;         // 1: every n is a multiple of 16 bytes / element size (16-byte slice loads)
+  int32_t seg_vec;         // 1: every n and seg_cols are multiples of 16 bytes / element size (16-byte
+                           // slice loads and stores)
+  uint16_t* seg_woff;      // [row blocks][seg_wstride] wave bands: entries of rows [128 w, 128 w + 128) in
+                           // segment s at [woff[s * 17 + w], woff[s * 17 + w + 1])
+  int32_t seg_wstride;     // max segments x 17
   // memory-bounded form (window > 0): Gram-Schmidt against the last `window` basis vectors only, the
   // raw basis kept in a ring of window + 1 slots (vector i in slot i % (window + 1))
   int32_t window;

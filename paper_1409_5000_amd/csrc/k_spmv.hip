@@ -406,19 +406,26 @@ __global__ __launch_bounds__(kStagedThreads) void k_spmv_staged(LzArgs a, int j)
 // (k_seg_prepare, once per call: stable, so a row keeps its order inside a segment); each step then
 // walks the segments in order: it stages v_j[segment] in LDS, streams the segment's entries (16-bit
 // in-segment column, value) with coalesced loads, serves every gather from LDS into a product
-// buffer, and adds each row's products to that row's FP64 sum in a register. The loads of segment
-// s + 1 (vector slice, per-row counts, entries) are issued into registers before the gathers of
-// segment s, so one segment's memory latency hides behind the previous segment's LDS work.
+// buffer, and adds each row's products to that row's FP64 sum in a register. Every wave owns a band
+// of 128 consecutive rows (two per lane) and a private region of the product buffer: the band's
+// entries of a segment are contiguous (offsets recorded by k_seg_prepare), so a wave forms and sums
+// its products with no workgroup barrier. The vector slices are double-buffered, which leaves one
+// workgroup barrier per segment. The loads of segment s + 1 (vector slice, per-row counts, entries)
+// are issued into registers before the gathers of segment s, so one segment's memory latency hides
+// behind the previous segment's LDS work.
 // A row's products are added segment by segment and in entry order within a segment, so for rows
 // stored with ascending columns the sums are those of the CSR-stream form, bit for bit.
 constexpr int kSegThreads = 1024;
+constexpr int kSegWaves = kSegThreads / 64;
+constexpr int kBandRows = kRowsPerBlock / kSegWaves;  // rows per wave: 128, two per lane
 template <typename T>
 struct SegShape {
-  static constexpr int CAP = sizeof(T) == 8 ? 4096 : 8192;  // product slots (32 KB)
-  static constexpr int UE = CAP / kSegThreads;              // prefetched entries per thread
-  static constexpr int XP = sizeof(T) == 8 ? 8 : 16;         // prefetched vector elements per thread
-  static constexpr int MAXCOLS = XP * kSegThreads;           // largest segment (64 KB of LDS)
+  static constexpr int WCAP = sizeof(T) == 8 ? 384 : 768;  // product slots per wave (3 KB)
+  static constexpr int UE = WCAP / 64;                      // prefetched entries per lane
+  static constexpr int XP = sizeof(T) == 8 ? 6 : 12;         // prefetched vector elements per thread
+  static constexpr int MAXCOLS = XP * kSegThreads;           // largest segment (48 KB per LDS buffer)
 };
+static_assert(kBandRows == 128, "two rows per lane");
 
 // Exclusive prefix sum of one int per thread over the workgroup; *total = the sum of all. wtot:
 // NT/64 ints. Ends with a barrier, so wtot may be reused by the next call.
@@ -562,6 +569,25 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
     run += c;
   }
   __syncthreads();
+  // wave bands: the entries of rows [128 w, 128 w + 128) in segment s are [wo[s][w], wo[s][w + 1]);
+  // wo[s][16] ends the segment. A band beyond the per-wave product capacity sends the block to the
+  // stream form.
+  uint16_t* wo = a.seg_woff + (size_t)blk * a.seg_wstride;
+  auto band_start = [&](int sg, int w) {
+    return (w < kSegWaves && w * kBandRows < rows) ? (int)cnt[sg * rows + w * kBandRows]
+                                                   : (sg + 1 < S ? (int)cnt[(sg + 1) * rows] : total);
+  };
+  for (int i = tid; i < S * (kSegWaves + 1); i += NT) {
+    const int sg = i / (kSegWaves + 1), w = i - sg * (kSegWaves + 1);
+    const int v = band_start(sg, w);
+    wo[i] = (uint16_t)v;
+    if (w < kSegWaves && band_start(sg, w + 1) - v > SegShape<T>::WCAP) bad = 1;
+  }
+  __syncthreads();
+  if (bad) {
+    if (tid == 0) a.seg_flag[blk] = 0;
+    return;
+  }
   uint16_t* pc = a.seg_col + tk.nnz_off + e0;
   T* pv = HAS_VAL ? (T*)a.seg_val + tk.nnz_off + e0 : nullptr;
   for_rows_staged<T, HAS_VAL, NT>(ci, va, rp_lds, rows, cap, lci, lva,
@@ -592,80 +618,76 @@ __device__ inline T load_elem(__amdgpu_buffer_rsrc_t r, int i) {
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, 0));
 }
 
-// Wave-level part of block_excl_scan: inclusive prefix of v within the wave; lane 63 stores the
-// wave total in wtot. The workgroup prefix follows after a barrier (scan_finish).
-__device__ inline int scan_start(int v, int* wtot) {
-  const int lane = threadIdx.x & 63;
-  int inc = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += t;
-  }
-  if (lane == 63) wtot[threadIdx.x >> 6] = inc;
-  return inc;
+// Wave-exclusive prefix sum of v (lanes below this one), in registers with DPP: inclusive scans of
+// the four rows of 16 lanes by row shifts 1, 2, 4, 8, then lane 15's total broadcast into rows 1
+// and 3 and lane 31's into rows 2 and 3. Disabled rows and lanes whose source is outside the row
+// read 0.
+__device__ inline int wave_excl_scan(int v) {
+  int x = v;
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+  return x - v;
 }
 
-template <int NT>
-__device__ inline int scan_finish(int inc, int v, const int* wtot, int* total) {
-  const int w = threadIdx.x >> 6;
-  int before = 0, all = 0;
-#pragma unroll
-  for (int i = 0; i < NT / 64; ++i) {
-    const int t = wtot[i];
-    before += i < w ? t : 0;
-    all += t;
-  }
-  *total = all;
-  return before + inc - v;
+// LDS writes of this wave visible to all of its lanes.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Per segment three barriers: (A) row offsets published, (B) products formed, (C) row sums done and
-// the next segment's vector slice and count scan staged. The loads of segment s + 1 are issued at
-// the top of segment s; the first segment's loads are issued before the step is opened.
+// One workgroup barrier per segment: after it, the slice of segment s + 1 is staged in the other
+// buffer. The loads of segment s + 1 are issued at the top of segment s; the first segment's loads
+// are issued before the step is opened.
 template <typename T, bool HAS_VAL, bool VEC>
 __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
   extern __shared__ __align__(16) unsigned char smem[];
   using SS = SegShape<T>;
-  constexpr int CAP = SS::CAP, NT = kSegThreads, UE = SS::UE, XP = SS::XP, U = kStreamU;
-  T* xs = (T*)smem;  // [seg_cols]
-  __shared__ T prod[CAP];
-  __shared__ int p_lds[kRowsPerBlock + 1];
-  __shared__ int wtot[2][NT / 64];
+  constexpr int NT = kSegThreads, UE = SS::UE, XP = SS::XP, WCAP = SS::WCAP;
+  __shared__ T prod[kSegWaves * WCAP];
+  __shared__ int p_lds[kRowsPerBlock + 1];  // stream fallback only
+  __shared__ uint16_t wo_lds[kSegMax * (kSegWaves + 1)];
   __shared__ double chunks[kMaxChunks];
   __shared__ double red[NT / 64];
   const Ref ref = resolve(a);
   const Task tk = a.tasks[ref.task];
   RState* st = a.state + ref.task;
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, rows = min(n - r0, kRowsPerBlock);
-  const int blk = tk.blk_begin + ref.blk, tid = threadIdx.x;
+  const int blk = tk.blk_begin + ref.blk, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int SEG = a.seg_cols, S = (n + SEG - 1) / SEG;
+  T* pw = prod + wv * WCAP;
   const T* x = (const T*)a.V + tk.vec_off + vslot(a, j) * n;
   T* w_out = (T*)a.W + tk.w_off + r0;
   const int32_t* rp = a.row_ptr + tk.rowptr_off;
   const int flag = a.seg_flag[blk];
   const int e0 = rp[r0], E = rp[r0 + rows] - e0;
-  const int SEG = a.seg_cols, S = (n + SEG - 1) / SEG;
   const uint8_t* cnt = a.seg_cnt + (size_t)blk * a.seg_stride;
+  const uint16_t* wo = a.seg_woff + (size_t)blk * a.seg_wstride;
   const uint16_t* pc = a.seg_col + tk.nnz_off + e0;
   const T* pv = HAS_VAL ? (const T*)a.seg_val + tk.nnz_off + e0 : nullptr;
-  const int rr = 2 * tid;  // the two rows whose counts this thread scans
+  const int rr = 2 * tid;  // this lane's two rows: 128 wv + 2 lane and the next
   // Buffer resources (scalar registers) over the block's entries, its counts and the vector: loads
   // take 32-bit byte offsets, and an offset past the end reads 0, which is what every guard wants.
   const __amdgpu_buffer_rsrc_t r_pc = make_rsrc(pc, 2 * E);
   const __amdgpu_buffer_rsrc_t r_pv = make_rsrc(pv, HAS_VAL ? (int)sizeof(T) * E : 0);
   const __amdgpu_buffer_rsrc_t r_cnt = make_rsrc(cnt, S * rows);
   const __amdgpu_buffer_rsrc_t r_x = make_rsrc(x, (int)sizeof(T) * n);
-  // registers holding the next segment: vector slice, two counts, the first CAP entries
-  // VEC: 16-byte slice loads and LDS stores (the host selects it when every realization's n is a
-  // multiple of the vector width, so that every segment start and length is one too)
+  // registers holding the next segment: vector slice, two counts, the band's entries
+  // VEC: 16-byte slice loads and LDS stores (the host selects it when every realization's n and the
+  // segment length are multiples of the vector width, so that every segment start and length is one
+  // too and no store passes the end of its slice)
   constexpr int VW = 16 / sizeof(T);
   using VT = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
   T xr[VEC ? 1 : XP];
   VT xq[VEC ? XP / VW : 1];
-  int cr0 = 0, cr1 = 0;
-  int ec[UE];
-  T ev[UE];
-  auto prefetch = [&](int s, int start) {
+  int cr0 = 0, cr1 = 0, nb0 = 0, nb1 = 0;
+  int ec[UE] = {};
+  T ev[UE] = {};
+  auto prefetch = [&](int s, int b0, int b1) {  // b0, b1: the band's entry range in segment s
     const int base = s * SEG, len = min(SEG, n - base);
     if constexpr (VEC) {
 #pragma unroll
@@ -688,43 +710,53 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
       cr0 = rr < rows ? __builtin_amdgcn_raw_buffer_load_b8(r_cnt, s * rows + rr, 0, 0) : 0;
       cr1 = rr + 1 < rows ? __builtin_amdgcn_raw_buffer_load_b8(r_cnt, s * rows + rr + 1, 0, 0) : 0;
     }
+    nb0 = b0;
+    nb1 = b1;
+    const int nbw = __builtin_amdgcn_readfirstlane(b1 - b0);  // the band's entries (wave-uniform)
 #pragma unroll
     for (int u = 0; u < UE; ++u) {
-      const int k = start + tid + u * NT;
-      ec[u] = __builtin_amdgcn_raw_buffer_load_b16(r_pc, 2 * k, 0, 0);
-      if constexpr (HAS_VAL) ev[u] = load_elem<T>(r_pv, k);
+      if (u * 64 < nbw) {  // slots wholly past the band issue no load
+        const int k = b0 + lane + u * 64;
+        const int kk = k < b1 ? k : E;  // past the band: read as zero (never used)
+        ec[u] = __builtin_amdgcn_raw_buffer_load_b16(r_pc, 2 * kk, 0, 0);
+        if constexpr (HAS_VAL) ev[u] = load_elem<T>(r_pv, kk);
+      }
     }
   };
-  if (flag) prefetch(0, 0);  // in bounds whatever the step's state; consumed only if the step runs
+  if (flag) prefetch(0, wo[wv], wo[wv + 1]);  // consumed only if the step runs
   double sj;
   if (!open_step(a, tk, st, ref.blk, j, chunks, &sj)) return;
   if (!flag) {
     const T* va = HAS_VAL ? (const T*)a.values + tk.nnz_off : nullptr;
-    spmv_stream_rows<T, HAS_VAL, NT, CAP>(rp, a.col_idx + tk.nnz_off, va, x, r0, rows, sj, p_lds, prod, w_out, red);
+    spmv_stream_rows<T, HAS_VAL, NT, kSegWaves * WCAP>(rp, a.col_idx + tk.nnz_off, va, x, r0, rows, sj, p_lds, prod,
+                                                      w_out, red);
     return;
   }
-  // stage segment 0: vector slice, wave part of the count scan, the entries in hand
+  for (int i = tid; i < S * (kSegWaves + 1); i += NT) wo_lds[i] = wo[i];
+  // the current segment: its entries, this lane's counts and offsets in the wave's product region
   int cc[UE];
   T cv[UE];
-  int inc, own, c0;
+  int c0 = 0, c1 = 0, ex = 0, bn = 0;
   auto stage = [&](int s, int buf) {
     const int len = min(SEG, n - s * SEG);
+    T* xb = (T*)smem + buf * SEG;
     if constexpr (VEC) {
 #pragma unroll
       for (int u = 0; u < XP / VW; ++u) {
         const int i = (tid + u * NT) * VW;
-        if (i < len) *(VT*)(xs + i) = xq[u];
+        if (i < len) *(VT*)(xb + i) = xq[u];
       }
     } else {
 #pragma unroll
       for (int u = 0; u < XP; ++u) {
         const int i = tid + u * NT;
-        if (i < len) xs[i] = xr[u];
+        if (i < len) xb[i] = xr[u];
       }
     }
     c0 = cr0;
-    own = cr0 + cr1;
-    inc = scan_start(own, wtot[buf]);
+    c1 = cr1;
+    ex = wave_excl_scan(cr0 + cr1);
+    bn = __builtin_amdgcn_readfirstlane(nb1 - nb0);
 #pragma unroll
     for (int u = 0; u < UE; ++u) {
       cc[u] = ec[u];
@@ -732,90 +764,40 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
     }
   };
   stage(0, 0);
-  __syncthreads();
-  double acc0 = 0.0, acc1 = 0.0;  // rows tid and tid + NT
-  int seg_start = 0;
+  __syncthreads();  // slice 0 and the band table published
+  double acc0 = 0.0, acc1 = 0.0;  // rows rr and rr + 1
+  constexpr int WO = kSegWaves + 1;
   for (int s = 0; s < S; ++s) {
-    // (C of the previous segment) published xs, wtot[s & 1]; p_lds and prod are free
-    int ce;
-    const int ex = scan_finish<NT>(inc, own, wtot[s & 1], &ce);
-    if (rr < rows) p_lds[rr] = ex;
-    if (rr + 1 < rows) p_lds[rr + 1] = ex + c0;
-    if (tid == 0) p_lds[rows] = ce;
-    if (s + 1 < S) prefetch(s + 1, seg_start + ce);
-    __syncthreads();  // (A)
-    if (ce <= CAP) {
+    const int buf = s & 1;
+    if (s + 1 < S) prefetch(s + 1, wo_lds[(s + 1) * WO + wv], wo_lds[(s + 1) * WO + wv + 1]);
+    const T* xb = (const T*)smem + buf * SEG;
 #pragma unroll
-      for (int u = 0; u < UE; ++u) {
-        const int k = tid + u * NT;
-        if (k < ce) {
-          const T xv = xs[cc[u]];
-          if constexpr (HAS_VAL) prod[k] = cv[u] * xv; else prod[k] = xv;
+    for (int u = 0; u < UE; ++u) {
+      if (u * 64 < bn) {  // wave-uniform
+        const int k = lane + u * 64;
+        if (k < bn) {
+          const T xv = xb[cc[u]];
+          if constexpr (HAS_VAL) pw[k] = cv[u] * xv; else pw[k] = xv;
         }
-      }
-      __syncthreads();  // (B)
-      if (tid < rows) {
-        const int e = p_lds[tid + 1];
-        for (int k = p_lds[tid]; k < e; ++k) acc0 += (double)prod[k];
-      }
-      if (tid + NT < rows) {
-        const int e = p_lds[tid + NT + 1];
-        for (int k = p_lds[tid + NT]; k < e; ++k) acc1 += (double)prod[k];
-      }
-    } else {
-      // more entries than product slots: row chunks, loads straight from memory
-      int ra = 0;
-      while (ra < rows) {
-        const int k0 = p_lds[ra];
-        int lo = ra + 1, hi = rows;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (p_lds[mid] - k0 <= CAP) lo = mid; else hi = mid - 1;
-        }
-        const int rb = lo, cn = p_lds[rb] - k0;
-        for (int q0 = tid; q0 < cn; q0 += NT * U) {
-          int c[U];
-          T v[U];
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int k = q0 + u * NT;
-            c[u] = k < cn ? (int)pc[seg_start + k0 + k] : 0;
-            if constexpr (HAS_VAL) v[u] = k < cn ? pv[seg_start + k0 + k] : (T)0;
-          }
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int k = q0 + u * NT;
-            if (k < cn) {
-              const T xv = xs[c[u]];
-              if constexpr (HAS_VAL) prod[k] = v[u] * xv; else prod[k] = xv;
-            }
-          }
-        }
-        __syncthreads();
-        if (tid >= ra && tid < rb) {
-          const int e = p_lds[tid + 1] - k0;
-          for (int k = p_lds[tid] - k0; k < e; ++k) acc0 += (double)prod[k];
-        }
-        if (tid + NT >= ra && tid + NT < rb) {
-          const int e = p_lds[tid + NT + 1] - k0;
-          for (int k = p_lds[tid + NT] - k0; k < e; ++k) acc1 += (double)prod[k];
-        }
-        ra = rb;
-        if (ra < rows) __syncthreads();  // the next chunk overwrites prod
       }
     }
-    seg_start += ce;
-    if (s + 1 < S) stage(s + 1, (s + 1) & 1);  // xs is no longer read: its last reads were before (B)
-    __syncthreads();  // (C)
+    wave_lds_sync();
+    for (int k = ex; k < ex + c0; ++k) acc0 += (double)pw[k];
+    for (int k = ex + c0; k < ex + c0 + c1; ++k) acc1 += (double)pw[k];
+    wave_lds_sync();  // the band's next products overwrite pw
+    if (s + 1 < S) {
+      stage(s + 1, buf ^ 1);  // the other buffer's last readers were segment s - 1's products
+      __syncthreads();
+    }
   }
-  if (tid < rows) w_out[tid] = (T)(acc0 * sj);
-  if (tid + NT < rows) w_out[tid + NT] = (T)(acc1 * sj);
+  if (rr < rows) w_out[rr] = (T)(acc0 * sj);
+  if (rr + 1 < rows) w_out[rr + 1] = (T)(acc1 * sj);
 }
 
 template <typename T>
 constexpr size_t seg_static_bytes() {
-  return (size_t)SegShape<T>::CAP * sizeof(T) + (size_t)(kRowsPerBlock + 1) * 4 + (kSegThreads / 64) * 12 +
-         kMaxChunks * 8 + 512;
+  return (size_t)kSegWaves * SegShape<T>::WCAP * sizeof(T) + (size_t)(kRowsPerBlock + 1) * 4 +
+         (size_t)kSegMax * (kSegWaves + 1) * 2 + kMaxChunks * 8 + (kSegThreads / 64) * 8 + 512;
 }
 
 // Staging capacity (entries) of k_seg_prepare next to smax x kRowsPerBlock 16-bit counters.
@@ -896,10 +878,10 @@ hipError_t step_any(int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s
   if (a.seg_cols > 0) {
     if (a.seg_vec)
       hipLaunchKernelGGL((k_spmv_seg<T, HAS_VAL, true>), dim3((unsigned)nb), dim3(kSegThreads),
-                         (size_t)a.seg_cols * sizeof(T), s, a, j);
+                         2 * (size_t)a.seg_cols * sizeof(T), s, a, j);
     else
       hipLaunchKernelGGL((k_spmv_seg<T, HAS_VAL, false>), dim3((unsigned)nb), dim3(kSegThreads),
-                         (size_t)a.seg_cols * sizeof(T), s, a, j);
+                         2 * (size_t)a.seg_cols * sizeof(T), s, a, j);
     return hipGetLastError();
   }
   if (a.seglen > 0) {

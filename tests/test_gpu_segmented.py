@@ -30,6 +30,30 @@ def symmetric_weights(hb, seed=0):
     return vals.astype(hb.dtype)
 
 
+def seg_eligible(hb, seg_len, dtype):
+    """Fraction of row blocks that take the sorted path, by the rules of the prepare kernel: at most
+    65535 entries, 255 entries of one row in one segment, and a wave band's (128 rows') entries in one
+    segment within its product slots (768 FP32 / 384 FP64)."""
+    seg = seg_len or (6144 if dtype == "f64" else 12288)
+    wcap = 384 if dtype == "f64" else 768
+    ok = tot = 0
+    for r in range(hb.R):
+        n, rp, ci, _ = hb.csr(r)
+        rows_of = np.repeat(np.arange(n), np.diff(rp))
+        for b0 in range(0, n, 2048):
+            b1 = min(n, b0 + 2048)
+            sl = slice(int(rp[b0]), int(rp[b1]))
+            tot += 1
+            if rp[b1] - rp[b0] > 65535:
+                continue
+            sg, rw = ci[sl] // seg, rows_of[sl] - b0
+            S = (n + seg - 1) // seg
+            per_row = np.bincount(sg * 2048 + rw, minlength=S * 2048)
+            per_band = np.bincount(sg * 16 + rw // 128, minlength=S * 16)
+            ok += int(per_row.max(initial=0) <= 255 and per_band.max(initial=0) <= wcap)
+    return ok / tot
+
+
 def run_pair(hb, m, **seg_kw):
     torch = torch_mod()
     b = api().Batch.from_host(hb)
@@ -51,13 +75,14 @@ def assert_bitwise(ref, seg):
 @pytest.mark.parametrize("weighted", [False, True])
 def test_segmented_equals_stream_bitwise(gpu_lib, dtype, seg_len, weighted):
     # n = 9000: four full row blocks and a ragged one of 808 rows; seg_len 500 / 1000 / 400 / 777
-    # give 18 / 9 / 23 / 12 segments with a ragged last one (500 and 400 keep a segment's entries
-    # within the prefetched product slots, the others take the row-chunk path); the defaults give
-    # one or two segments, row-chunked
+    # give 18 / 9 / 23 / 12 segments with a ragged last one, every block sorted; 4096 and the
+    # defaults put up to 2560 entries of a wave's rows into one segment, beyond its product slots:
+    # every block runs the stream arithmetic inside the segmented kernel
     w = dataclasses.replace(C.scaled(C.workload(1), n=9000, N=3), dtype=dtype)
     hb = C.build(w, with_values=weighted)
     if weighted:
         hb.values = symmetric_weights(hb)
+    assert seg_eligible(hb, seg_len, dtype) == (1.0 if seg_len in (500, 1000, 400, 777) else 0.0)
     b, ref, seg = run_pair(hb, w.m, seg_len=seg_len)
     assert_bitwise(ref, seg)
     if seg_len == 0:
@@ -66,11 +91,12 @@ def test_segmented_equals_stream_bitwise(gpu_lib, dtype, seg_len, weighted):
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_segmented_large_segments_prefetched_bitwise(gpu_lib, dtype):
-    # n = 40000, degree 8: the default segment (16384 FP32 / 8192 FP64 columns, 1024 threads) holds
-    # about 3.4k-6.7k entries of a row block, within the prefetched product slots
+    # n = 40000, degree 8: the default segment (12288 FP32 / 6144 FP64 columns, two LDS buffers)
+    # holds about 315 / 157 entries of a wave's 128 rows, within its product slots
     spec = C.er_spec(40000, 8.0, target="er", t=50, int_p=4 / 49, N=2, K=50)
     w = C.Workload(92, "segmented-large", (spec,), dtype, 20)
     hb = C.build(w)
+    assert seg_eligible(hb, 0, dtype) == 1.0
     b, ref, seg = run_pair(hb, w.m)
     assert_bitwise(ref, seg)
 
@@ -87,7 +113,8 @@ def test_segmented_fallback_blocks_bitwise(gpu_lib):
     assert deg.max() > 255
     rp1 = hb.csr(2)[1]
     assert rp1[2048] - rp1[0] > 65535 and rp1[6000] - rp1[4096] <= 65535
-    b, ref, seg = run_pair(hb, w.m, seg_len=8192)
+    assert 0.0 < seg_eligible(hb, 4096, "f32") < 1.0
+    b, ref, seg = run_pair(hb, w.m, seg_len=4096)
     assert_bitwise(ref, seg)
     check_against_oracle(hb, seg, b, w.m, "f32", K=20)
 

@@ -70,7 +70,7 @@ def test_schedules_and_forms_agree_bitwise(gpu_lib, schedule, hipgraph, spmv):
     hb = C.build(w)
     b = api().Batch.from_host(hb)
     ref = b.scores(m=w.m, reorth=0, schedule="batched", hipgraph=False, spmv="stream")
-    run = b.run(m=w.m, reorth=0, schedule=schedule, hipgraph=hipgraph, spmv=spmv, seg_len=3000)
+    run = b.run(m=w.m, reorth=0, schedule=schedule, hipgraph=hipgraph, spmv=spmv, seg_len=2000)
     for _ in range(2):
         out = run.launch()
         torch.cuda.synchronize()
