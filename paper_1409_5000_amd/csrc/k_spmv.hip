@@ -684,7 +684,8 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
   using VT = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
   T xr[VEC ? 1 : XP];
   VT xq[VEC ? XP / VW : 1];
-  int cr0 = 0, cr1 = 0, nb0 = 0, nb1 = 0;
+  int nb0 = 0, nb1 = 0;
+  uint32_t craw = 0;
   int ec[UE] = {};
   T ev[UE] = {};
   auto prefetch = [&](int s, int b0, int b1) {  // b0, b1: the band's entry range in segment s
@@ -702,13 +703,14 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
         xr[u] = i < len ? load_elem<T>(r_x, base + i) : (T)0;
       }
     }
-    if ((rows & 1) == 0) {  // an even row count keeps the pair 2-byte aligned
-      const uint32_t c2 = rr < rows ? __builtin_amdgcn_raw_buffer_load_b16(r_cnt, s * rows + rr, 0, 0) : 0u;
-      cr0 = c2 & 0xFF;
-      cr1 = c2 >> 8;
+    // the two counts as one 16-bit word, unpacked when staged (an unpack here would wait for this
+    // load and every load before it); an even row count keeps the pair 2-byte aligned
+    if ((rows & 1) == 0) {
+      craw = rr < rows ? __builtin_amdgcn_raw_buffer_load_b16(r_cnt, s * rows + rr, 0, 0) : 0u;
     } else {
-      cr0 = rr < rows ? __builtin_amdgcn_raw_buffer_load_b8(r_cnt, s * rows + rr, 0, 0) : 0;
-      cr1 = rr + 1 < rows ? __builtin_amdgcn_raw_buffer_load_b8(r_cnt, s * rows + rr + 1, 0, 0) : 0;
+      const uint32_t lo = rr < rows ? __builtin_amdgcn_raw_buffer_load_b8(r_cnt, s * rows + rr, 0, 0) : 0u;
+      const uint32_t hi = rr + 1 < rows ? __builtin_amdgcn_raw_buffer_load_b8(r_cnt, s * rows + rr + 1, 0, 0) : 0u;
+      craw = lo | (hi << 8);
     }
     nb0 = b0;
     nb1 = b1;
@@ -753,9 +755,9 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
         if (i < len) xb[i] = xr[u];
       }
     }
-    c0 = cr0;
-    c1 = cr1;
-    ex = wave_excl_scan(cr0 + cr1);
+    c0 = (int)(craw & 0xFF);
+    c1 = (int)(craw >> 8);
+    ex = wave_excl_scan(c0 + c1);
     bn = __builtin_amdgcn_readfirstlane(nb1 - nb0);
 #pragma unroll
     for (int u = 0; u < UE; ++u) {
