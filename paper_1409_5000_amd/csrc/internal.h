@@ -15,6 +15,7 @@ namespace ebtc {
 int report_error(int code, const std::string& msg);
 
 constexpr int kBlock = 256;          // threads of a streaming workgroup (4 waves of 64)
+constexpr int kDotsThreads = 1024;   // threads of a workgroup forming a row block's dot partials
 constexpr int kRowsPerBlock = 2048;  // CSR rows owned by one workgroup in the Lanczos kernels
 constexpr int kRowsPerThread = kRowsPerBlock / kBlock;
 constexpr int kStagedThreads = 1024; // threads of the LDS-staged SpMV workgroup (16 waves)
@@ -123,6 +124,7 @@ hipError_t launch_sc_out(const RState* state, const Task* tasks, const int32_t* 
 hipError_t launch_spmv_step(int dtype, bool has_val, int lanes, int j, const LzArgs& a, int64_t nblocks,
                             hipStream_t s);
 hipError_t launch_dots_step(int dtype, int j, const LzArgs& a, int64_t nblocks, hipStream_t s);
+
 hipError_t launch_dots_again(int dtype, int j, const LzArgs& a, int64_t nblocks, hipStream_t s);
 hipError_t launch_update(int dtype, int j, bool from_w, bool final_pass, bool second_pass, const LzArgs& a,
                          int64_t nblocks, hipStream_t s);

@@ -77,18 +77,26 @@ __device__ inline void block_dots(const T* __restrict__ Vr, int n, int lo, int j
 // First basis vector of the Gram-Schmidt window of step j (all of v_0..v_j without a window).
 __device__ inline int window_lo(const LzArgs& a, int j) { return a.window > 0 ? max(0, j - a.window + 1) : 0; }
 
+// Workgroup size of the step's dot partials for windows of P vectors of es-byte elements: the
+// two-vector ring and FP32 windows of up to 32 vectors take kDotsThreads (two rows per thread, 64
+// registers, eight waves per SIMD); the rest 256 threads (their accumulators need the registers).
+__host__ __device__ constexpr int dots_threads(int P, int es) {
+  return (P <= 2 || (es == 4 && P <= 32)) ? kDotsThreads : kBlock;
+}
+
 // k_dots_step: dot partials of w (written by the SpMV) against the window of Vraw_0..j.
 template <typename T, int P, int RING>
-__global__ __launch_bounds__(kBlock) void k_dots_step(LzArgs a, int j) {
-  __shared__ double red[kWaves * P];
+__global__ __launch_bounds__(dots_threads(P, sizeof(T))) void k_dots_step(LzArgs a, int j) {
+  constexpr int NT = dots_threads(P, sizeof(T));
+  __shared__ double red[(NT / 64) * P];
   const Ref ref = resolve(a);
   const Task tk = a.tasks[ref.task];
   const RState* st = a.state + ref.task;
   if (step_skipped(a, st, j)) return;
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
   const T* Vr = (const T*)a.V + tk.vec_off;
-  block_dots<T, P, kBlock, RING>(Vr, n, window_lo(a, j), j, r0, r1, nullptr, (const T*)a.W + tk.w_off,
-                           nullptr, a.part + tk.part_off + (size_t)ref.blk * kPartStride, red);
+  block_dots<T, P, NT, RING>(Vr, n, window_lo(a, j), j, r0, r1, nullptr, (const T*)a.W + tk.w_off, nullptr,
+                             a.part + tk.part_off + (size_t)ref.blk * kPartStride, red);
 }
 
 // Second Gram-Schmidt pass: dots of the once-orthogonalised vector (stored in the slot of j+1).
@@ -419,7 +427,9 @@ hipError_t launch_accum(int dtype, const LzArgs& a, int j, int64_t nb, hipStream
   } while (0)
 
 hipError_t launch_dots_step(int dtype, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
-  const dim3 g((unsigned)nb), b(kBlock);
+  if (a.window > 0 && a.window != 2) return hipErrorInvalidValue;
+  const int P = a.window > 0 ? 2 : (window_count(a, j) <= 32 ? 32 : 64);
+  const dim3 g((unsigned)nb), b(dots_threads(P, dtype == EBTC_F64 ? 8 : 4));
   if (dtype == EBTC_F64) EBTC_GS_LAUNCH(k_dots_step, double, a, j);
   else EBTC_GS_LAUNCH(k_dots_step, float, a, j);
   return hipGetLastError();
