@@ -195,8 +195,14 @@ class Batch:
         Plan Runs after tuning: the chosen form sets their workspace size."""
         opts = make_opts(**kw)
         ws = ctypes.c_size_t()
-        seg = make_opts(**{**kw, "spmv": "segmented", "seg_len": 3072 if self.dtype == "f64" else 6144})
-        if A.lib().ebtc_plan(self.handle, ctypes.byref(seg), ctypes.byref(ws), None) != A.EBTC_OK:
+        small = 3072 if self.dtype == "f64" else 6144
+        # workspace for the largest candidate: the segmented form with the shorter segment length that
+        # applies (more segments, more counts), else the plan of the other forms
+        for q in (small, 2 * small):
+            seg = make_opts(**{**kw, "spmv": "segmented", "seg_len": q})
+            if A.lib().ebtc_plan(self.handle, ctypes.byref(seg), ctypes.byref(ws), None) == A.EBTC_OK:
+                break
+        else:
             A.check(A.lib().ebtc_plan(self.handle, ctypes.byref(opts), ctypes.byref(ws), None))
         wst = torch.empty(max(1, ws.value), dtype=torch.uint8, device=self.device)
         form, lanes, segl = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
@@ -204,7 +210,6 @@ class Batch:
         A.check(A.lib().ebtc_tune(self.handle, ctypes.byref(opts), _vp(wst), ws.value, ctypes.byref(form),
                                   ctypes.byref(lanes), ctypes.byref(segl), ms, current_stream()))
         names = {v: k for k, v in A.SPMV_FORMS.items()}
-        small = 3072 if self.dtype == "f64" else 6144
         labels = ["stream", "lanes4", "lanes8", "lanes16", "lanes32", "staged", f"segmented{small}",
                   f"segmented{2 * small}"]
         return {"form": names[form.value], "lanes": lanes.value, "seg_len": segl.value,

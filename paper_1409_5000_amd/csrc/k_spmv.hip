@@ -533,8 +533,9 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
   __syncthreads();  // every thread has read rp_lds[0] and rp_lds[rows]
   for (int i = tid; i <= rows; i += NT) rp_lds[i] -= e0;
   __syncthreads();
-  // counts per (segment, row): a row is visited by one thread, so no counter has two writers
-  for_rows_staged<T, HAS_VAL, NT>(ci, va, rp_lds, rows, cap, lci, lva,
+  // counts per (segment, row): a row is visited by one thread, so no counter has two writers (the
+  // columns alone are staged: the values are not needed to count)
+  for_rows_staged<T, false, NT>(ci, nullptr, rp_lds, rows, cap, lci, lva,
                                   [&](int r, const int* cs, const T*, int k, int e) {
                                     for (; k < e; ++k) {
                                       const int c = cs[k];
