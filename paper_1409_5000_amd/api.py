@@ -151,6 +151,35 @@ class Batch:
         self.score_off = np.concatenate([[0], np.cumsum(self.graph_n.astype(np.int64))])
 
     @classmethod
+    def from_csr(cls, graphs: list, dtype: str = "f32", device: str = "cuda") -> "Batch":
+        """From per-realization CSR arrays: graphs[g] is a list of (row_ptr, col_idx) or
+        (row_ptr, col_idx, values) tuples, one per realization of graph g, all with n_g rows (local
+        row pointers starting at 0, symmetric pattern, sorted columns, no self-loops). Values are
+        taken from every realization or from none (pattern-only: all ones)."""
+        gn, gr, rps, cis, vals, ro, no = [], [], [], [], [], [], [0]
+        roff = 0
+        for reals in graphs:
+            if not reals:
+                raise ValueError("every graph needs at least one realization")
+            n = int(np.asarray(reals[0][0]).size) - 1
+            gn.append(n)
+            gr.append(len(reals))
+            for real in reals:
+                rp, ci = np.asarray(real[0], np.int64), np.asarray(real[1], np.int32)
+                if rp.size != n + 1:
+                    raise ValueError("the realizations of a graph must have the same number of rows")
+                ro.append(roff)
+                roff += n + 1
+                rps.append(rp.astype(np.int32))
+                cis.append(ci)
+                no.append(no[-1] + ci.size)
+                vals.append(None if len(real) < 3 or real[2] is None else np.asarray(real[2]))
+        if any(v is None for v in vals) and not all(v is None for v in vals):
+            raise ValueError("give values for every realization or for none")
+        values = None if vals[0] is None else np.concatenate(vals)
+        return cls(gn, gr, ro, no, np.concatenate(rps), np.concatenate(cis), values, dtype, device)
+
+    @classmethod
     def from_host(cls, hb, device: str = "cuda", with_values: bool | None = None) -> "Batch":
         """From a host batch object (fields n, nreal, rowptr_off, nnz_off, row_ptr, col_idx, values, dtype)."""
         dtype = "f64" if np.dtype(hb.dtype) == np.float64 else "f32"

@@ -445,3 +445,18 @@ def test_tuner_choice_used_and_equivalent(gpu_lib):
     r = before.scores.cpu().numpy()
     assert np.max(np.abs(auto.scores.cpu().numpy() - r)) <= 1e-6 * np.max(np.abs(r))
     check_against_oracle(hb, auto, b, w.m, "f32", K=50)
+
+
+def test_batch_from_csr_matches_host_batch(gpu_lib):
+    # the same realizations through Batch.from_csr and Batch.from_host give the same bits
+    torch = torch_mod()
+    w = C.scaled(C.workload(1), n=3000, N=3)
+    hb = C.build(w)
+    reals = [hb.csr(r) for r in range(hb.R)]
+    b1 = api().Batch.from_csr([[(rp, ci, v) for (_, rp, ci, v) in reals]], dtype="f32")
+    b2 = api().Batch.from_host(hb)
+    s1, s2 = b1.scores(m=w.m), b2.scores(m=w.m)
+    torch.cuda.synchronize()
+    assert np.array_equal(s1.scores.cpu().numpy(), s2.scores.cpu().numpy())
+    with pytest.raises(ValueError):
+        api().Batch.from_csr([[(reals[0][1], reals[0][2], None), (reals[1][1], reals[1][2], reals[1][3])]])
