@@ -263,7 +263,8 @@ enum ebtc_phase {
   EBTC_PHASE_COMBINE = 5,    /* u = beta0 V y                                                    */
   EBTC_PHASE_SUM = 6,        /* realization sum with per-graph log-scale                        */
   EBTC_PHASE_PREPARE = 7,    /* column-segment sort of the entries (column-segmented SpMV only) */
-  EBTC_PHASE_COUNT = 8
+  EBTC_PHASE_FIRST = 8,      /* step 0's product A 1 of the all-ones start: row sums, no gathers */
+  EBTC_PHASE_COUNT = 9
 };
 /* Measurement only: runs ebtc_scores' batched launch sequence once, eagerly (no hipGraph), with a
  * HIP event recorded on `stream` before and after every kernel launch, then synchronises the

@@ -29,7 +29,7 @@ EXPORTED = [
 ]
 GEN_FAMILIES = {"er": 0, "ws": 1, "ba": 2}
 SPMV_FORMS = {"auto": 0, "stream": 1, "lanes": 2, "staged": 3, "segmented": 4}
-PHASES = ["start", "spmv", "dots", "update", "tridiag", "combine", "sum", "prepare"]
+PHASES = ["start", "spmv", "dots", "update", "tridiag", "combine", "sum", "prepare", "first"]
 
 
 class BatchDesc(ctypes.Structure):

@@ -328,7 +328,8 @@ int run_steps(const ebtc_batch* b, const ebtc_opts* o, const LzArgs& a, int64_t 
   const int steps = o->m > 0 ? o->m : o->m_max;
   if (with_start) EBTC_PHASE(prof, EBTC_PHASE_START, launch_start(b->dtype, a, nblocks, s));
   for (int j = 0; j < steps; ++j) {
-    EBTC_PHASE(prof, EBTC_PHASE_SPMV, launch_spmv_step(b->dtype, has_val, lanes, j, a, nblocks, s));
+    EBTC_PHASE(prof, j == 0 && a.unit_start ? EBTC_PHASE_FIRST : EBTC_PHASE_SPMV,
+               launch_spmv_step(b->dtype, has_val, lanes, j, a, nblocks, s));
     EBTC_PHASE(prof, EBTC_PHASE_DOTS, launch_dots_step(b->dtype, j, a, nblocks, s));
     if (o->reorth == 2) {
       EBTC_PHASE(prof, EBTC_PHASE_UPDATE, launch_update(b->dtype, j, true, false, false, a, nblocks, s));
@@ -365,7 +366,8 @@ int run_pass2(const ebtc_batch* b, const ebtc_opts* o, const LzArgs& a1, int64_t
   for (int j = 0; j < steps; ++j) {
     EBTC_PHASE(prof, EBTC_PHASE_COMBINE, launch_accum(b->dtype, a, j, nblocks, s));
     if (j + 1 == steps) break;  // the last vector needed is v_{steps-1}
-    EBTC_PHASE(prof, EBTC_PHASE_SPMV, launch_spmv_step(b->dtype, has_val, lanes, j, a, nblocks, s));
+    EBTC_PHASE(prof, j == 0 && a.unit_start ? EBTC_PHASE_FIRST : EBTC_PHASE_SPMV,
+               launch_spmv_step(b->dtype, has_val, lanes, j, a, nblocks, s));
     EBTC_PHASE(prof, EBTC_PHASE_DOTS, launch_dots_step(b->dtype, j, a, nblocks, s));
     EBTC_PHASE(prof, EBTC_PHASE_UPDATE, launch_update(b->dtype, j, true, true, false, a, nblocks, s));
   }
@@ -375,6 +377,7 @@ int run_pass2(const ebtc_batch* b, const ebtc_opts* o, const LzArgs& a1, int64_t
 int enqueue_batched(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, void* scores, double* log_scale,
                     void* ckpt, ebtc_diag* diag, const SpmvPlan& sp, hipStream_t s, Prof* prof = nullptr) {
   LzArgs a = make_args(b, o, ws, L, sp);
+  a.unit_start = 1;  // k_start (and k_restart) set v_0 = 1
   a.diag = diag;
   EBTC_LAUNCH(launch_blkmap(a.tasks, b->R, (int32_t*)(ws + L.off_blkmap), s));
   int rc = enqueue_prepare(b, sp, a, L.total_blocks, s, prof);
@@ -399,6 +402,7 @@ int enqueue_batched(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L
 int enqueue_plain(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, void* scores, double* log_scale,
                   void* ckpt, ebtc_diag* diag, const SpmvPlan& sp, hipStream_t s) {
   LzArgs a = make_args(b, o, ws, L, sp);
+  a.unit_start = 1;
   a.blkmap = nullptr;
   a.diag = diag;
   for (int64_t r = 0; r < b->R; ++r) {
@@ -834,6 +838,7 @@ int ebtc_scores_backward(ebtc_batch* b, const ebtc_opts* o, const double* log_sc
   if (rc) return rc;
   // 1. forward recomputation (same kernels and order as ebtc_scores: bitwise the same basis)
   LzArgs fa = make_args(b, o, w, B.fwd, sp);
+  fa.unit_start = 1;
   EBTC_LAUNCH(launch_blkmap(fa.tasks, b->R, (int32_t*)(w + B.fwd.off_blkmap), s));
   rc = enqueue_prepare(b, sp, fa, B.fwd.total_blocks, s, nullptr);  // the sorted entries serve both solves
   if (rc) return rc;
@@ -843,6 +848,7 @@ int ebtc_scores_backward(ebtc_batch* b, const ebtc_opts* o, const double* log_sc
   EBTC_LAUNCH(launch_tridiag_state(fa, 0, b->R, 0, 0, steps, o->shift, o->tol, nullptr, nullptr, s));
   // 2. adjoint Lanczos started at the cotangent (shares W and the partial-sum arenas)
   LzArgs aa = fa;
+  aa.unit_start = 0;  // started at the cotangent
   aa.state = (RState*)(w + B.off_astate);
   aa.V = w + B.off_aV;
   EBTC_LAUNCH(launch_start_vec(b->dtype, aa, (const GraphInfo*)(w + B.fwd.off_graphs), grad_scores,

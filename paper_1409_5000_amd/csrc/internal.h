@@ -105,6 +105,7 @@ struct LzArgs {
   // raw basis kept in a ring of window + 1 slots (vector i in slot i % (window + 1))
   int32_t window;
   int32_t stop_mused;      // second pass of the memory-bounded form: steps j >= m_used - 1 are skipped
+  int32_t unit_start;      // 1: v_0 is the raw all-ones vector, so step 0's product is A's row sums
 };
 
 // Slot of basis vector i in a realization's V block.

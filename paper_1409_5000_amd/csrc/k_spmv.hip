@@ -400,6 +400,69 @@ __global__ __launch_bounds__(kStagedThreads) void k_spmv_staged(LzArgs a, int j)
   for (int i = threadIdx.x; i < rows; i += kStagedThreads) W[i] = w_lds[i];
 }
 
+// Step 0 of a process started at the all-ones vector: A v_0 = s_0 A 1, each row's sum of its values
+// (its entry count for a pattern-only graph), summed in FP64 in entry order like every SpMV form, so
+// the result is theirs bit for bit without reading a column index or gathering the vector. The row
+// block's values are staged through LDS in chunks with coalesced loads; a row longer than a chunk is
+// summed straight from memory.
+template <typename T, bool HAS_VAL>
+__global__ __launch_bounds__(kBlock) void k_spmv_first(LzArgs a) {
+  constexpr int CAP = StreamShape<T>::CAP, U = kStreamU;
+  __shared__ double chunks[kMaxChunks];
+  __shared__ int rp_lds[kRowsPerBlock + 1];
+  __shared__ T lv[HAS_VAL ? CAP : 1];
+  const Ref ref = resolve(a);
+  const Task tk = a.tasks[ref.task];
+  RState* st = a.state + ref.task;
+  double sj;
+  if (!open_step(a, tk, st, ref.blk, 0, chunks, &sj)) return;
+  const int n = tk.n, r0 = ref.blk * kRowsPerBlock, rows = min(n - r0, kRowsPerBlock), tid = threadIdx.x;
+  const int32_t* rp = a.row_ptr + tk.rowptr_off + r0;
+  T* w = (T*)a.W + tk.w_off + r0;
+  if constexpr (!HAS_VAL) {
+    for (int r = tid; r < rows; r += kBlock) w[r] = (T)((double)(rp[r + 1] - rp[r]) * sj);
+  } else {
+    const T* va = (const T*)a.values + tk.nnz_off;
+    for (int i = tid; i <= rows; i += kBlock) rp_lds[i] = rp[i];
+    __syncthreads();
+    int ra = 0;
+    while (ra < rows) {
+      const int k0 = rp_lds[ra];
+      if (rp_lds[ra + 1] - k0 > CAP) {  // one long row: thread 0 sums it in order
+        if (tid == 0) {
+          double acc = 0.0;
+          for (int k = k0; k < rp_lds[ra + 1]; ++k) acc += (double)va[k];
+          w[ra] = (T)(acc * sj);
+        }
+        ++ra;
+        continue;
+      }
+      int lo = ra + 1, hi = rows;  // largest rb with rp[rb] - rp[ra] <= CAP (same for every thread)
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rp_lds[mid] - k0 <= CAP) lo = mid; else hi = mid - 1;
+      }
+      const int rb = lo, ce = rp_lds[rb] - k0;
+      for (int q0 = tid; q0 < ce; q0 += kBlock * U) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = q0 + u * kBlock < ce ? va[k0 + q0 + u * kBlock] : (T)0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (q0 + u * kBlock < ce) lv[q0 + u * kBlock] = v[u];
+      }
+      __syncthreads();
+      for (int r = ra + tid; r < rb; r += kBlock) {
+        double acc = 0.0;
+        for (int k = rp_lds[r] - k0; k < rp_lds[r + 1] - k0; ++k) acc += (double)lv[k];
+        w[r] = (T)(acc * sj);
+      }
+      __syncthreads();
+      ra = rb;
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------- column-segmented
 // The random gathers of the CSR-stream form each cost an L1 miss: a row block's entries touch the
 // whole vector. Here every call first sorts each row block's entries by column segment
@@ -989,6 +1052,17 @@ int staged_max_seglen(int dtype) {
 }
 
 hipError_t launch_spmv_step(int dtype, bool has_val, int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
+  if (j == 0 && a.unit_start) {
+    const dim3 g((unsigned)nb), b(kBlock);
+    if (dtype == EBTC_F64) {
+      if (has_val) hipLaunchKernelGGL((k_spmv_first<double, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_spmv_first<double, false>), g, b, 0, s, a);
+    } else {
+      if (has_val) hipLaunchKernelGGL((k_spmv_first<float, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_spmv_first<float, false>), g, b, 0, s, a);
+    }
+    return hipGetLastError();
+  }
   if (dtype == EBTC_F64)
     return has_val ? step_any<double, true>(lanes, j, a, nb, s) : step_any<double, false>(lanes, j, a, nb, s);
   return has_val ? step_any<float, true>(lanes, j, a, nb, s) : step_any<float, false>(lanes, j, a, nb, s);
