@@ -289,19 +289,23 @@ def main() -> int:
                    "backward_over_forward": round(bwd_ms / fwd_ms, 3), "budget": 3.0}
         log(f"adjoint: forward {fwd_ms:.3f} ms, backward {bwd_ms:.3f} ms, ratio {bwd_ms / fwd_ms:.2f}")
 
-    # plain per-realization loop on the same batch
-    runp = b.run(m=m, tol=tol, m_max=m_max, schedule="plain", hipgraph=False, diag=False, **form)
-    step(runp)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.plain_steps):
+    # plain per-realization loop on the same batch (--plain-steps 0 skips it)
+    plain = None
+    if args.plain_steps > 0:
+        runp = b.run(m=m, tol=tol, m_max=m_max, schedule="plain", hipgraph=False, diag=False, **form)
         step(runp)
-    torch.cuda.synchronize()
-    plain_wall = time.perf_counter() - t0
-    plain_value = hb.R * args.plain_steps / plain_wall
-    log(f"plain: {1000 * plain_wall / args.plain_steps:.3f} ms/step, {plain_value:.1f} realizations/s")
-    del runp
-    torch.cuda.empty_cache()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            step(runp)
+        torch.cuda.synchronize()
+        plain_wall = time.perf_counter() - t0
+        plain_value = hb.R * args.plain_steps / plain_wall
+        log(f"plain: {1000 * plain_wall / args.plain_steps:.3f} ms/step, {plain_value:.1f} realizations/s")
+        plain = {"value": round(plain_value, 2), "ms_per_step": round(1000 * plain_wall / args.plain_steps, 3),
+                 "batched_over_plain": round(value / plain_value, 2)}
+        del runp
+        torch.cuda.empty_cache()
 
     # per-kernel durations with HIP events around each launch: one eager pass of the same launch
     # sequence on the timed run's workspace
@@ -379,8 +383,7 @@ def main() -> int:
                    "adaptive_tol": w.tol if m == 0 else None, "reorth": args.reorth, "K": [int(x) for x in K[:4]],
                    "schedule": "batched, hipGraph replay", "parallelism": "1 GPU",
                    "spmv_form": tuned if tuned is not None else form},
-        "plain": {"value": round(plain_value, 2), "ms_per_step": round(1000 * plain_wall / args.plain_steps, 3),
-                  "batched_over_plain": round(value / plain_value, 2)},
+        "plain": plain,
         "effective_GBps_whole_path": round(total_alg * args.steps / wall / 1e9, 1),
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
