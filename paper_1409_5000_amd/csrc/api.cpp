@@ -38,7 +38,7 @@ struct Layout {
   size_t off_tasks = 0, off_graphs = 0, off_blkmap = 0, off_state = 0, off_part = 0, off_npart = 0, off_V = 0,
          off_W = 0, off_U = 0;
   // column-segmented SpMV arenas (present when the plan uses that form)
-  size_t off_segflag = 0, off_segcnt = 0, off_segwoff = 0, off_segcol = 0, off_segval = 0;
+  size_t off_segflag = 0, off_segcnt = 0, off_segwoff = 0, off_segblk = 0, off_segcol = 0, off_segval = 0;
   size_t total = 0;
   int64_t total_blocks = 0;
 };
@@ -170,6 +170,8 @@ Layout make_layout(const ebtc_batch* b, const ebtc_opts* o, const SpmvPlan& sp) 
     off = align_up(off + (size_t)sp.smax * kRowsPerBlock * blocks);
     L.off_segwoff = off;
     off = align_up(off + sizeof(uint16_t) * (size_t)sp.smax * 17 * blocks);
+    L.off_segblk = off;
+    off = align_up(off + sizeof(SegBlock) * blocks);
     L.off_segcol = off;
     off = align_up(off + sizeof(uint16_t) * z);
     L.off_segval = off;
@@ -265,6 +267,7 @@ LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout
     a.seg_cnt = (uint8_t*)(ws + L.off_segcnt);
     a.seg_woff = (uint16_t*)(ws + L.off_segwoff);
     a.seg_wstride = sp.smax * 17;
+    a.seg_blk = (SegBlock*)(ws + L.off_segblk);
     a.seg_col = (uint16_t*)(ws + L.off_segcol);
     a.seg_val = b->values ? (void*)(ws + L.off_segval) : nullptr;
     // 16-byte slice stores need every slice length to be a whole number of vectors: n and the

@@ -40,6 +40,21 @@ struct Task {
 };
 static_assert(sizeof(Task) == 64, "Task layout");
 
+// Per row block of the column-segmented form, written by the sort: what the first loads of a product
+// need, so that they wait on one load instead of the chain workgroup map -> realization -> row
+// pointers -> band table.
+struct SegBlock {
+  int64_t entries;   // index of the block's first entry in seg_col / seg_val
+  int64_t vec_off;   // Task::vec_off of its realization
+  int32_t n;         // order of its realization
+  int32_t nnz;       // entries of the block
+  int16_t rows;      // rows of the block
+  int16_t flag;      // the block's seg_flag
+  uint16_t wo0[17];  // band starts of segment 0 (the first 17 entries of its seg_woff table)
+  uint16_t pad;
+};
+static_assert(sizeof(SegBlock) == 64, "SegBlock layout");
+
 struct GraphInfo {
   int64_t score_off;   // offset of the graph's block in the score output
   int32_t n;
@@ -101,6 +116,7 @@ struct LzArgs {
   uint16_t* seg_woff;      // [row blocks][seg_wstride] wave bands: entries of rows [128 w, 128 w + 128) in
                            // segment s at [woff[s * 17 + w], woff[s * 17 + w + 1])
   int32_t seg_wstride;     // max segments x 17
+  SegBlock* seg_blk;       // [row blocks] descriptors for the first loads of a product
   // memory-bounded form (window > 0): Gram-Schmidt against the last `window` basis vectors only, the
   // raw basis kept in a ring of window + 1 slots (vector i in slot i % (window + 1))
   int32_t window;

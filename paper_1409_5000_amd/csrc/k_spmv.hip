@@ -589,8 +589,21 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
   if (tid == 0) bad = 0;
   __syncthreads();
   const int e0 = rp_lds[0];
-  if (rp_lds[rows] - e0 > 65535 || S > kSegMax) {  // offsets must fit 16 bits
-    if (tid == 0) a.seg_flag[blk] = 0;
+  const int nz = rp_lds[rows] - e0;
+  SegBlock* desc = a.seg_blk + blk;
+  auto finish = [&](int f) {  // the block's flag and descriptor (band starts written by the caller)
+    if (tid == 0) {
+      a.seg_flag[blk] = f;
+      desc->entries = tk.nnz_off + e0;
+      desc->vec_off = tk.vec_off;
+      desc->n = n;
+      desc->nnz = nz;
+      desc->rows = (int16_t)rows;
+      desc->flag = (int16_t)f;
+    }
+  };
+  if (nz > 65535 || S > kSegMax) {  // offsets must fit 16 bits
+    finish(0);
     return;
   }
   const int32_t* ci = a.col_idx + tk.nnz_off + e0;
@@ -617,7 +630,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
                                     }
                                   });
   if (bad) {
-    if (tid == 0) a.seg_flag[blk] = 0;
+    finish(0);
     return;
   }
   uint8_t* cnt_out = a.seg_cnt + (size_t)blk * a.seg_stride;
@@ -647,11 +660,12 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
     const int sg = i / (kSegWaves + 1), w = i - sg * (kSegWaves + 1);
     const int v = band_start(sg, w);
     wo[i] = (uint16_t)v;
+    if (i <= kSegWaves) desc->wo0[i] = (uint16_t)v;  // segment 0 (i = w)
     if (w < kSegWaves && band_start(sg, w + 1) - v > SegShape<T>::WCAP) bad = 1;
   }
   __syncthreads();
   if (bad) {
-    if (tid == 0) a.seg_flag[blk] = 0;
+    finish(0);
     return;
   }
   uint16_t* pc = a.seg_col + tk.nnz_off + e0;
@@ -667,7 +681,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
                                       if constexpr (HAS_VAL) pv[pos] = vs[k];
                                     }
                                   });
-  if (tid == 0) a.seg_flag[blk] = 1;
+  finish(1);
 }
 
 // Raw buffer resource over [p, p + bytes): loads through it take 32-bit byte offsets and return 0
@@ -724,22 +738,20 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
   __shared__ uint16_t wo_lds[kSegMax * (kSegWaves + 1)];
   __shared__ double chunks[kMaxChunks];
   __shared__ double red[NT / 64];
-  const Ref ref = resolve(a);
-  const Task tk = a.tasks[ref.task];
-  RState* st = a.state + ref.task;
-  const int n = tk.n, r0 = ref.blk * kRowsPerBlock, rows = min(n - r0, kRowsPerBlock);
-  const int blk = tk.blk_begin + ref.blk, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // The first segment's loads wait on the block's descriptor alone: in a batched launch the logical
+  // workgroup is the block's flattened index.
+  const int lb = logical_block();
+  const int blk = a.blkmap != nullptr ? lb : a.tasks[a.single_task].blk_begin + lb;
+  const SegBlock* d = a.seg_blk + blk;
+  const int n = d->n, rows = d->rows, flag = d->flag, E = d->nnz;
   const int SEG = a.seg_cols, S = (n + SEG - 1) / SEG;
   T* pw = prod + wv * WCAP;
-  const T* x = (const T*)a.V + tk.vec_off + vslot(a, j) * n;
-  T* w_out = (T*)a.W + tk.w_off + r0;
-  const int32_t* rp = a.row_ptr + tk.rowptr_off;
-  const int flag = a.seg_flag[blk];
-  const int e0 = rp[r0], E = rp[r0 + rows] - e0;
+  const T* x = (const T*)a.V + d->vec_off + vslot(a, j) * n;
   const uint8_t* cnt = a.seg_cnt + (size_t)blk * a.seg_stride;
   const uint16_t* wo = a.seg_woff + (size_t)blk * a.seg_wstride;
-  const uint16_t* pc = a.seg_col + tk.nnz_off + e0;
-  const T* pv = HAS_VAL ? (const T*)a.seg_val + tk.nnz_off + e0 : nullptr;
+  const uint16_t* pc = a.seg_col + d->entries;
+  const T* pv = HAS_VAL ? (const T*)a.seg_val + d->entries : nullptr;
   const int rr = 2 * tid;  // this lane's two rows: 128 wv + 2 lane and the next
   // Buffer resources (scalar registers) over the block's entries, its counts and the vector: loads
   // take 32-bit byte offsets, and an offset past the end reads 0, which is what every guard wants.
@@ -796,7 +808,13 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
       }
     }
   };
-  if (flag) prefetch(0, wo[wv], wo[wv + 1]);  // consumed only if the step runs
+  if (flag) prefetch(0, d->wo0[wv], d->wo0[wv + 1]);  // consumed only if the step runs
+  const Ref ref = resolve(a);
+  const Task tk = a.tasks[ref.task];
+  RState* st = a.state + ref.task;
+  const int r0 = ref.blk * kRowsPerBlock;
+  T* w_out = (T*)a.W + tk.w_off + r0;
+  const int32_t* rp = a.row_ptr + tk.rowptr_off;
   double sj;
   if (!open_step(a, tk, st, ref.blk, j, chunks, &sj)) return;
   if (!flag) {

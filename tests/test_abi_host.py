@@ -156,7 +156,8 @@ def test_plan_workspace_arithmetic(dtype, es):
 def test_plan_segmented_workspace_arithmetic():
     # the column-segmented form appends: block flags (int32), per-(segment, row) counts (8 bits,
     # max segments x 2048 per block), wave-band offsets (16 bits, max segments x 17 per block),
-    # in-segment columns (16 bits per entry); no value copy for a pattern-only batch
+    # 64-byte block descriptors, in-segment columns (16 bits per entry); no value copy for a
+    # pattern-only batch
     d, keep = make_desc(G=2, nreal=(2, 3), n=(3000, 70), nnz=(10, 10, 10, 10, 10))
     rc, h = create(d)
     rc, ws, _ = plan(h, m=30, spmv=4, seg_len=1000)
@@ -166,6 +167,7 @@ def test_plan_segmented_workspace_arithmetic():
     off = align(off + 4 * blocks)
     off = align(off + 3 * 2048 * blocks)      # per-(segment, row) counts
     off = align(off + 2 * 3 * 17 * blocks)    # per-(segment, wave band) entry offsets (16 bits)
+    off = align(off + 64 * blocks)            # block descriptors
     off = align(off + 2 * 50)
     assert ws == off
     rc, _, _ = plan(h, m=30, spmv=4, seg_len=50)  # 60 segments
