@@ -311,6 +311,11 @@ __global__ __launch_bounds__(kBlock) void k_combine(LzArgs a) {
 
 // eq. (5) in scaled form: S~_g = sum_k e^{theta_k - Sigma_g} u_k, k ascending, FP64 weights and
 // accumulation; Sigma_g = max_k theta_k.
+// One workgroup per kSumRows rows of a graph (one row per thread, so that a small batch of graphs
+// still spreads over the CUs); each thread adds its row over the graph's realizations in order k,
+// kSumU loads in flight at a time.
+constexpr int kSumRows = kBlock;
+constexpr int kSumU = 8;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_sum(const GraphInfo* graphs, const Task* tasks, const RState* state,
                                                  const T* U, T* scores, double* log_scale) {
@@ -318,9 +323,9 @@ __global__ __launch_bounds__(kBlock) void k_sum(const GraphInfo* graphs, const T
   __shared__ int64_t uo[kBlock];
   __shared__ double sig;
   const GraphInfo gi = graphs[blockIdx.y];
-  const int r0 = blockIdx.x * kRowsPerBlock;
+  const int r0 = blockIdx.x * kSumRows;
   if (r0 >= gi.n) return;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, r = r0 + tid;
   if (tid < 64) {
     double m = -INFINITY;
     for (int k = tid; k < gi.count; k += 64) m = fmax(m, state[gi.first + k].theta);
@@ -329,9 +334,7 @@ __global__ __launch_bounds__(kBlock) void k_sum(const GraphInfo* graphs, const T
     if (tid == 0) sig = m;
   }
   __syncthreads();
-  double acc[kRowsPerThread];
-#pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) acc[q] = 0.0;
+  double acc = 0.0;
   for (int kb = 0; kb < gi.count; kb += kBlock) {
     const int cnt = min(kBlock, gi.count - kb);
     if (tid < cnt) {
@@ -339,22 +342,19 @@ __global__ __launch_bounds__(kBlock) void k_sum(const GraphInfo* graphs, const T
       uo[tid] = tasks[gi.first + kb + tid].u_off;
     }
     __syncthreads();
-    for (int kk = 0; kk < cnt; ++kk) {
-      const double wgt = wk[kk];
-      const T* u = U + uo[kk];
+    if (r < gi.n) {
+      for (int k0 = 0; k0 < cnt; k0 += kSumU) {
+        T v[kSumU];
 #pragma unroll
-      for (int q = 0; q < kRowsPerThread; ++q) {
-        const int r = r0 + q * kBlock + tid;
-        if (r < gi.n) acc[q] += wgt * (double)u[r];
+        for (int u = 0; u < kSumU; ++u) v[u] = k0 + u < cnt ? U[uo[k0 + u] + r] : (T)0;
+#pragma unroll
+        for (int u = 0; u < kSumU; ++u)
+          if (k0 + u < cnt) acc += wk[k0 + u] * (double)v[u];
       }
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
-    const int r = r0 + q * kBlock + tid;
-    if (r < gi.n) scores[gi.score_off + r] = (T)acc[q];
-  }
+  if (r < gi.n) scores[gi.score_off + r] = (T)acc;
   if (blockIdx.x == 0 && tid == 0) log_scale[blockIdx.y] = sig;
 }
 
@@ -463,7 +463,7 @@ hipError_t launch_combine(int dtype, const LzArgs& a, int64_t nb, hipStream_t s)
 
 hipError_t launch_sum(int dtype, const GraphInfo* graphs, int32_t G, int32_t max_blocks, const Task* tasks,
                       const RState* state, const void* U, void* scores, double* log_scale, hipStream_t s) {
-  const dim3 g((unsigned)max_blocks, (unsigned)G), b(kBlock);
+  const dim3 g((unsigned)(max_blocks * (kRowsPerBlock / kSumRows)), (unsigned)G), b(kBlock);
   if (dtype == EBTC_F64)
     hipLaunchKernelGGL(k_sum<double>, g, b, 0, s, graphs, tasks, state, (const double*)U, (double*)scores, log_scale);
   else

@@ -28,7 +28,9 @@ template <typename T, typename K>
 __global__ __launch_bounds__(kTopkThreads) void k_topk(const GraphInfo* graphs, const int32_t* kvec,
                                                        const int64_t* koff, const T* scores, int32_t* idx_out,
                                                        T* val_out) {
+  constexpr int NH = 4;  // count rows: wave w adds to row w % NH, so that waves rarely contend
   __shared__ uint32_t hist[256];
+  __shared__ uint32_t whist[NH][256];
   __shared__ K s_prefix, s_mask;
   __shared__ int s_remaining, s_eq_total, s_ngt, s_eq_seen;
   __shared__ int wave_cnt[kTopkThreads / 64];
@@ -47,13 +49,33 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk(const GraphInfo* graphs, 
     s_remaining = K_;
   }
   __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6;
   for (int shift = BITS - 8; shift >= 0; shift -= 8) {
-    if (tid < 256) hist[tid] = 0;
+    for (int i = tid; i < NH * 256; i += kTopkThreads) (&whist[0][0])[i] = 0;
     __syncthreads();
     const K prefix = s_prefix, mask = s_mask;
-    for (int i = tid; i < n; i += kTopkThreads) {
-      const K k = key_of(s[i]);
-      if ((k & mask) == prefix) atomicAdd(&hist[(int)((k >> shift) & 255)], 1u);
+    for (int i0 = 0; i0 < n; i0 += kTopkThreads) {  // uniform trip count: the ballots below need all lanes
+      const int i = i0 + tid;
+      const K k = i < n ? key_of(s[i]) : (K)0;
+      const bool in = i < n && (k & mask) == prefix;
+      const int bin = (int)((k >> shift) & 255);
+      // the lanes sharing the first counted lane's bin (most of them in the leading passes, where
+      // scores of one magnitude share their top key bits) add their count with one atomic
+      const unsigned long long act = __ballot(in);
+      if (act) {
+        const int lead = __ffsll((long long)act) - 1;
+        const int lbin = __shfl(bin, lead, 64);
+        const unsigned long long same = __ballot(in && bin == lbin);
+        if (lane == lead) atomicAdd(&whist[wave % NH][lbin], (uint32_t)__popcll(same));
+        if (in && bin != lbin) atomicAdd(&whist[wave % NH][bin], 1u);
+      }
+    }
+    __syncthreads();
+    if (tid < 256) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int w = 0; w < NH; ++w) c += whist[w][tid];
+      hist[tid] = c;
     }
     __syncthreads();
     if (tid == 0) {
@@ -75,7 +97,6 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk(const GraphInfo* graphs, 
   const int need = s_remaining;         // entries equal to t to take
   const int gt_total = K_ - need;       // entries strictly above t
   const bool all_ties = (s_eq_total == need);
-  const int lane = tid & 63, wave = tid >> 6;
   for (int base = 0; base < n; base += kTopkThreads) {
     const int i = base + tid;
     const K k = (i < n) ? key_of(s[i]) : (K)0;
