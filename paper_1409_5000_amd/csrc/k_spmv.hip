@@ -407,9 +407,12 @@ __global__ __launch_bounds__(kStagedThreads) void k_spmv_staged(LzArgs a, int j)
 // the result is theirs bit for bit without reading a column index or gathering the vector. The row
 // block's values are staged through LDS in chunks with coalesced loads; a row longer than a chunk is
 // summed straight from memory.
+// 1024 threads and 32 KB chunks of values: a chunk is at most one round of eight coalesced loads
+// per thread.
+constexpr int kFirstThreads = 1024;
 template <typename T, bool HAS_VAL>
-__global__ __launch_bounds__(kBlock) void k_spmv_first(LzArgs a) {
-  constexpr int CAP = StreamShape<T>::CAP, U = kStreamU;
+__global__ __launch_bounds__(kFirstThreads) void k_spmv_first(LzArgs a) {
+  constexpr int NT = kFirstThreads, CAP = 32768 / (int)sizeof(T), U = kStreamU;
   __shared__ double chunks[kMaxChunks];
   __shared__ int rp_lds[kRowsPerBlock + 1];
   __shared__ T lv[HAS_VAL ? CAP : 1];
@@ -422,10 +425,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_first(LzArgs a) {
   const int32_t* rp = a.row_ptr + tk.rowptr_off + r0;
   T* w = (T*)a.W + tk.w_off + r0;
   if constexpr (!HAS_VAL) {
-    for (int r = tid; r < rows; r += kBlock) w[r] = (T)((double)(rp[r + 1] - rp[r]) * sj);
+    for (int r = tid; r < rows; r += NT) w[r] = (T)((double)(rp[r + 1] - rp[r]) * sj);
   } else {
     const T* va = (const T*)a.values + tk.nnz_off;
-    for (int i = tid; i <= rows; i += kBlock) rp_lds[i] = rp[i];
+    for (int i = tid; i <= rows; i += NT) rp_lds[i] = rp[i];
     __syncthreads();
     int ra = 0;
     while (ra < rows) {
@@ -445,16 +448,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv_first(LzArgs a) {
         if (rp_lds[mid] - k0 <= CAP) lo = mid; else hi = mid - 1;
       }
       const int rb = lo, ce = rp_lds[rb] - k0;
-      for (int q0 = tid; q0 < ce; q0 += kBlock * U) {
+      for (int q0 = tid; q0 < ce; q0 += NT * U) {
         T v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = q0 + u * kBlock < ce ? va[k0 + q0 + u * kBlock] : (T)0;
+        for (int u = 0; u < U; ++u) v[u] = q0 + u * NT < ce ? va[k0 + q0 + u * NT] : (T)0;
 #pragma unroll
         for (int u = 0; u < U; ++u)
-          if (q0 + u * kBlock < ce) lv[q0 + u * kBlock] = v[u];
+          if (q0 + u * NT < ce) lv[q0 + u * NT] = v[u];
       }
       __syncthreads();
-      for (int r = ra + tid; r < rb; r += kBlock) {
+      for (int r = ra + tid; r < rb; r += NT) {
         double acc = 0.0;
         for (int k = rp_lds[r] - k0; k < rp_lds[r + 1] - k0; ++k) acc += (double)lv[k];
         w[r] = (T)(acc * sj);
@@ -1078,7 +1081,7 @@ int staged_max_seglen(int dtype) {
 
 hipError_t launch_spmv_step(int dtype, bool has_val, int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
   if (j == 0 && a.unit_start) {
-    const dim3 g((unsigned)nb), b(kBlock);
+    const dim3 g((unsigned)nb), b(kFirstThreads);
     if (dtype == EBTC_F64) {
       if (has_val) hipLaunchKernelGGL((k_spmv_first<double, true>), g, b, 0, s, a);
       else hipLaunchKernelGGL((k_spmv_first<double, false>), g, b, 0, s, a);

@@ -412,6 +412,43 @@ def test_topk_ties_and_sizes(gpu_lib):
         o += k
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_topk_mixed_signs_and_dominant_bins(gpu_lib, dtype):
+    # mixed signs, zeros and one magnitude class shared by most scores (the counting passes
+    # then put most of a wave's lanes in one bin), at sizes that are not multiples of the workgroup
+    torch = torch_mod()
+    rng = np.random.default_rng(11)
+    sizes = [70001, 3000]
+
+    class B:
+        pass
+    hb = B()
+    hb.dtype = dtype
+    hb.n = np.array(sizes, np.int32)
+    hb.nreal = np.ones(len(sizes), np.int32)
+    hb.rowptr_off = np.concatenate([[0], np.cumsum(np.array(sizes) + 1)[:-1]]).astype(np.int64)
+    hb.nnz_off = np.zeros(len(sizes) + 1, np.int64)
+    hb.row_ptr = np.zeros(int(np.sum(np.array(sizes) + 1)), np.int32)
+    hb.col_idx = np.zeros(1, np.int32)
+    hb.values = None
+    b = api().Batch.from_host(hb)
+    a0 = (1.0 + rng.random(sizes[0]) * 1e-3).astype(dtype)  # one binade: shared leading key bits
+    a0[rng.integers(0, sizes[0], 500)] = -rng.random(500).astype(dtype)
+    a0[:7] = 0.0
+    a1 = rng.standard_normal(sizes[1]).astype(dtype)
+    a1[::5] = a1[0]  # ties
+    blocks = [a0, a1]
+    s = torch.as_tensor(np.concatenate(blocks)).to("cuda")
+    ks = [777, 3000]
+    idx, _ = b.topk(s, ks)
+    idx = idx.cpu().numpy()
+    o = 0
+    for blk, k in zip(blocks, ks):
+        brute = [i for _, i in sorted((-float(v), i) for i, v in enumerate(blk))][:k]
+        assert idx[o:o + k].tolist() == brute
+        o += k
+
+
 def test_validate_detects_bad_realization(gpu_lib):
     good = gs.random_graph(300, 0.05, 1)
     bad = gs.random_graph(300, 0.05, 2)
