@@ -407,12 +407,12 @@ __global__ __launch_bounds__(kStagedThreads) void k_spmv_staged(LzArgs a, int j)
 // the result is theirs bit for bit without reading a column index or gathering the vector. The row
 // block's values are staged through LDS in chunks with coalesced loads; a row longer than a chunk is
 // summed straight from memory.
-// 1024 threads and 32 KB chunks of values: a chunk is at most one round of eight coalesced loads
-// per thread.
-constexpr int kFirstThreads = 1024;
+// With values: 1024 threads and 32 KB chunks of values, a chunk at most one round of eight
+// coalesced loads per thread. Pattern-only: 256 threads (row pointers only; fewer waves to launch).
+__host__ __device__ constexpr int first_threads(bool has_val) { return has_val ? 1024 : kBlock; }
 template <typename T, bool HAS_VAL>
-__global__ __launch_bounds__(kFirstThreads) void k_spmv_first(LzArgs a) {
-  constexpr int NT = kFirstThreads, CAP = 32768 / (int)sizeof(T), U = kStreamU;
+__global__ __launch_bounds__(first_threads(HAS_VAL)) void k_spmv_first(LzArgs a) {
+  constexpr int NT = first_threads(HAS_VAL), CAP = 32768 / (int)sizeof(T), U = kStreamU;
   __shared__ double chunks[kMaxChunks];
   __shared__ int rp_lds[kRowsPerBlock + 1];
   __shared__ T lv[HAS_VAL ? CAP : 1];
@@ -1081,7 +1081,7 @@ int staged_max_seglen(int dtype) {
 
 hipError_t launch_spmv_step(int dtype, bool has_val, int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
   if (j == 0 && a.unit_start) {
-    const dim3 g((unsigned)nb), b(kFirstThreads);
+    const dim3 g((unsigned)nb), b(first_threads(has_val));
     if (dtype == EBTC_F64) {
       if (has_val) hipLaunchKernelGGL((k_spmv_first<double, true>), g, b, 0, s, a);
       else hipLaunchKernelGGL((k_spmv_first<double, false>), g, b, 0, s, a);
