@@ -104,7 +104,7 @@ typedef struct {
   int32_t hub_threshold; /* rows with more entries are reduced by a whole workgroup; 0 = auto     */
   int32_t seg_len;       /* LDS-staged and column-segmented forms: vector segment length in
                             elements (0 = the form's default: the largest that fits for LDS-staged,
-                            16384 FP32 / 8192 FP64 for column-segmented)                          */
+                            12288 FP32 / 6144 FP64 for column-segmented)                          */
 } ebtc_opts;
 
 enum ebtc_spmv_form {
@@ -113,13 +113,19 @@ enum ebtc_spmv_form {
                                 every row in FP64 from LDS                                         */
   EBTC_SPMV_LANE_GROUPS = 2, /* L lanes per row, two rows and four entries per lane in flight      */
   EBTC_SPMV_LDS_STAGED = 3,  /* the gathered vector streams through LDS in column segments         */
-  EBTC_SPMV_SEGMENTED = 4    /* each call first sorts every row block's entries by column segment
+  EBTC_SPMV_SEGMENTED = 4,   /* each call first sorts every row block's entries by column segment
                                 (stable; 16-bit in-segment columns, 8-bit per-row counts); each step
                                 then stages one vector segment at a time in LDS and serves every
                                 gather of that segment from it. Needs ceil(n / seg_len) <= 32;
                                 row blocks with more than 65535 entries, or a row with more than 255
                                 entries in one segment, use the CSR-stream form                     */
+  EBTC_SPMV_BALANCED = 5     /* the CSR-stream arithmetic with workgroups over equal shares of a
+                                realization's entries (8192 each) instead of equal row counts: rows
+                                stay whole, so the sums are the stream form's; for graphs whose
+                                first rows hold most entries (preferential attachment). Each call
+                                first finds every share's rows                                     */
 };
+#define EBTC_TUNE_SLOTS 9 /* entries of ebtc_tune's ms_out */
 
 /* Per-realization diagnostics (device array [R], written by ebtc_scores). */
 typedef struct {
@@ -235,8 +241,9 @@ int ebtc_subgraph_centrality(int32_t dtype, int32_t n, const int32_t* row_ptr, c
 
 /* ---------------------------------------------------------------- autotuning                     */
 /* Times the SpMV forms on this batch with HIP events -- the CSR stream, lane groups of 4, 8, 16 and
- * 32 lanes per row, and the LDS-staged form when the largest vector passes through LDS in at most
- * eight segments -- each as one warm-up and three timed launches of the first Lanczos product over
+ * 32 lanes per row, the LDS-staged form when the largest vector passes through LDS in at most
+ * eight segments, and the entry-balanced form when ws_bytes covers its plan -- each as one warm-up
+ * and three timed launches of the first Lanczos product over
  * every realization, and records the fastest in the batch (the column-segmented form is tried when
  * ws_bytes covers ebtc_plan's size for opts with spmv = EBTC_SPMV_SEGMENTED; plan the later calls
  * after tuning, since the chosen form sets their workspace size): later calls with opts->spmv ==
@@ -244,10 +251,10 @@ int ebtc_subgraph_centrality(int32_t dtype, int32_t n, const int32_t* row_ptr, c
  * the workspace (size from ebtc_plan for opts, 256-byte aligned); not thread-safe with other calls
  * on the same batch.
  *   form_out, lanes_out, seglen_out  host (nullable): the chosen form and its parameters
- *   ms_out  host [8] (nullable): ms per launch of stream, lanes 4, 8, 16, 32, LDS-staged,
- *           column-segmented with 8192 and 16384 FP32 (4096 and 8192 FP64) columns per segment, the
- *           latter two including their one sort per call spread over the call's m steps (-1 where
- *           the form was not tried)
+ *   ms_out  host [EBTC_TUNE_SLOTS] (nullable): ms per launch of stream, lanes 4, 8, 16, 32,
+ *           LDS-staged, column-segmented with 6144 and 12288 FP32 (3072 and 6144 FP64) columns per
+ *           segment, and entry-balanced; the segmented and balanced figures include their once-per-
+ *           call preparation spread over the call's m steps (-1 where the form was not tried)
  * Errors: EINVAL (NULL batch or workspace, bad opts), EWORKSPACE, EHIP. On error the batch keeps its
  * previous choice. */
 int ebtc_tune(ebtc_batch* batch, const ebtc_opts* opts, void* ws, size_t ws_bytes, int32_t* form_out,

@@ -226,21 +226,25 @@ class Batch:
         ws = ctypes.c_size_t()
         small = 3072 if self.dtype == "f64" else 6144
         # workspace for the largest candidate: the segmented form with the shorter segment length that
-        # applies (more segments, more counts), else the plan of the other forms
+        # applies (more segments, more counts), the entry-balanced form, else the plan of the others
+        A.check(A.lib().ebtc_plan(self.handle, ctypes.byref(opts), ctypes.byref(ws), None))
+        need = ws.value
         for q in (small, 2 * small):
             seg = make_opts(**{**kw, "spmv": "segmented", "seg_len": q})
             if A.lib().ebtc_plan(self.handle, ctypes.byref(seg), ctypes.byref(ws), None) == A.EBTC_OK:
+                need = max(need, ws.value)
                 break
-        else:
-            A.check(A.lib().ebtc_plan(self.handle, ctypes.byref(opts), ctypes.byref(ws), None))
-        wst = torch.empty(max(1, ws.value), dtype=torch.uint8, device=self.device)
+        bal = make_opts(**{**kw, "spmv": "balanced"})
+        if A.lib().ebtc_plan(self.handle, ctypes.byref(bal), ctypes.byref(ws), None) == A.EBTC_OK:
+            need = max(need, ws.value)
+        wst = torch.empty(max(1, need), dtype=torch.uint8, device=self.device)
         form, lanes, segl = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        ms = (ctypes.c_double * 8)()
-        A.check(A.lib().ebtc_tune(self.handle, ctypes.byref(opts), _vp(wst), ws.value, ctypes.byref(form),
+        ms = (ctypes.c_double * A.TUNE_SLOTS)()
+        A.check(A.lib().ebtc_tune(self.handle, ctypes.byref(opts), _vp(wst), need, ctypes.byref(form),
                                   ctypes.byref(lanes), ctypes.byref(segl), ms, current_stream()))
         names = {v: k for k, v in A.SPMV_FORMS.items()}
         labels = ["stream", "lanes4", "lanes8", "lanes16", "lanes32", "staged", f"segmented{small}",
-                  f"segmented{2 * small}"]
+                  f"segmented{2 * small}", "balanced"]
         return {"form": names[form.value], "lanes": lanes.value, "seg_len": segl.value,
                 "ms_per_launch": {l: ms[i] for i, l in enumerate(labels) if ms[i] >= 0}}
 

@@ -39,6 +39,9 @@ struct Layout {
          off_W = 0, off_U = 0;
   // column-segmented SpMV arenas (present when the plan uses that form)
   size_t off_segflag = 0, off_segcnt = 0, off_segwoff = 0, off_segblk = 0, off_segcol = 0, off_segval = 0;
+  // entry-balanced SpMV arenas (present when the plan uses that form)
+  size_t off_bal = 0, off_balbeg = 0;
+  int64_t nbal = 0;  // shares of kBalEntries entries over all realizations
   size_t total = 0;
   int64_t total_blocks = 0;
 };
@@ -84,6 +87,7 @@ struct ebtc_batch {
   std::vector<Task> tasks;          // host staging of the device task table (kept alive for async copies)
   std::vector<GraphInfo> graphs;
   std::vector<int64_t> nnz_r;       // per-realization entry counts (validation upload)
+  std::vector<int64_t> bal_begin;   // [R + 1] first entry-balanced share of each realization
   std::vector<int32_t> topk_k;
   std::vector<int64_t> topk_off;
   std::vector<ExecEntry> execs;
@@ -102,7 +106,7 @@ int check_opts(const ebtc_opts* o) {
   if (o->reorth < 0 || o->reorth > 2)
     return fail(EBTC_EINVAL, "reorth must be 0 (memory-bounded two-pass), 1 or 2");
   if (o->schedule < EBTC_SCHED_AUTO || o->schedule > EBTC_SCHED_BATCHED) return fail(EBTC_EINVAL, "unknown schedule");
-  if (o->spmv < EBTC_SPMV_AUTO || o->spmv > EBTC_SPMV_SEGMENTED) return fail(EBTC_EINVAL, "unknown spmv form");
+  if (o->spmv < EBTC_SPMV_AUTO || o->spmv > EBTC_SPMV_BALANCED) return fail(EBTC_EINVAL, "unknown spmv form");
   if (o->lanes_per_row != 0 && o->lanes_per_row != 4 && o->lanes_per_row != 8 && o->lanes_per_row != 16 &&
       o->lanes_per_row != 32)
     return fail(EBTC_EINVAL, "lanes_per_row must be 0, 4, 8, 16 or 32");
@@ -128,6 +132,17 @@ int check_plan(const ebtc_batch* b, const SpmvPlan& p) {
                                  " segments: n_max " + std::to_string(b->n_max) + " > " +
                                  std::to_string(kSegMax) + " x " + std::to_string(p.segcols));
   return EBTC_OK;
+}
+
+// First entry-balanced share of each realization ([R + 1]): one share per kBalEntries entries, at
+// least one per realization.
+std::vector<int64_t> bal_shares(const ebtc_batch* b) {
+  std::vector<int64_t> v((size_t)b->R + 1, 0);
+  for (int64_t r = 0; r < b->R; ++r) {
+    const int64_t z = b->nnz_off[r + 1] - b->nnz_off[r];
+    v[r + 1] = v[r] + std::max<int64_t>(1, (z + kBalEntries - 1) / kBalEntries);
+  }
+  return v;
 }
 
 Layout make_layout(const ebtc_batch* b, const ebtc_opts* o, const SpmvPlan& sp) {
@@ -177,6 +192,13 @@ Layout make_layout(const ebtc_batch* b, const ebtc_opts* o, const SpmvPlan& sp) 
     L.off_segval = off;
     if (b->values) off = align_up(off + es * z);
   }
+  if (sp.form == EBTC_SPMV_BALANCED) {
+    L.nbal = bal_shares(b).back();
+    L.off_bal = off;
+    off = align_up(off + sizeof(BalPart) * (size_t)L.nbal);
+    L.off_balbeg = off;
+    off = align_up(off + sizeof(int64_t) * (size_t)(b->R + 1));
+  }
   L.total = off;
   return L;
 }
@@ -213,6 +235,11 @@ int upload_tables(ebtc_batch* b, char* ws, const Layout& L, hipStream_t s) {
   fill_tables(b, L);
   EBTC_HIP(hipMemcpyAsync(ws + L.off_tasks, b->tasks.data(), sizeof(Task) * b->R, hipMemcpyHostToDevice, s));
   EBTC_HIP(hipMemcpyAsync(ws + L.off_graphs, b->graphs.data(), sizeof(GraphInfo) * b->G, hipMemcpyHostToDevice, s));
+  if (L.nbal > 0) {
+    if (b->bal_begin.size() != (size_t)b->R + 1) b->bal_begin = bal_shares(b);  // fixed per batch; kept alive
+    EBTC_HIP(hipMemcpyAsync(ws + L.off_balbeg, b->bal_begin.data(), sizeof(int64_t) * (b->R + 1),
+                            hipMemcpyHostToDevice, s));
+  }
   return EBTC_OK;
 }
 
@@ -277,6 +304,11 @@ LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout
     a.seg_vec = sp.segcols % vw == 0 ? 1 : 0;
     for (int32_t g = 0; g < b->G; ++g)
       if (b->n[g] % vw != 0) a.seg_vec = 0;
+  }
+  if (sp.form == EBTC_SPMV_BALANCED) {
+    a.bal = (BalPart*)(ws + L.off_bal);
+    a.bal_begin = (const int64_t*)(ws + L.off_balbeg);
+    a.nbal = (int32_t)L.nbal;
   }
   return a;
 }
@@ -351,6 +383,11 @@ int run_steps(const ebtc_batch* b, const ebtc_opts* o, const LzArgs& a, int64_t 
 // The column-segmented form's once-per-call sort of the entries (no-op for the other forms).
 int enqueue_prepare(const ebtc_batch* b, const SpmvPlan& sp, const LzArgs& a, int64_t nblocks, hipStream_t s,
                     Prof* prof) {
+  if (sp.form == EBTC_SPMV_BALANCED) {
+    const bool one = a.blkmap == nullptr;  // the plain schedule: one realization
+    EBTC_PHASE(prof, EBTC_PHASE_PREPARE, launch_bal_rows(a, one ? a.single_task : 0, one ? 1 : (int)b->R, s));
+    return EBTC_OK;
+  }
   if (sp.form != EBTC_SPMV_SEGMENTED) return EBTC_OK;
   EBTC_PHASE(prof, EBTC_PHASE_PREPARE, launch_seg_prepare(b->dtype, b->values != nullptr, a, nblocks, sp.smax, s));
   return EBTC_OK;
@@ -410,6 +447,7 @@ int enqueue_plain(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, 
   a.diag = diag;
   for (int64_t r = 0; r < b->R; ++r) {
     a.single_task = (int32_t)r;
+    if (a.bal != nullptr) a.nbal = (int32_t)(b->bal_begin[r + 1] - b->bal_begin[r]);
     const int64_t nb = b->tasks[r].nblk;
     int rc = enqueue_prepare(b, sp, a, nb, s, nullptr);
     if (rc) return rc;
@@ -743,6 +781,10 @@ int ebtc_tune(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, int3
     const SpmvPlan p = spmv_form(b, EBTC_SPMV_SEGMENTED, 0, small_seg << i, 0);
     if (p.smax <= kSegMax && make_layout(b, o, p).total <= ws_bytes) cands.push_back({p, 6 + i});
   }
+  {
+    const SpmvPlan p = spmv_form(b, EBTC_SPMV_BALANCED, 0, 0, 0);
+    if (make_layout(b, o, p).total <= ws_bytes) cands.push_back({p, 8});
+  }
   for (const Cand& c : cands) {
     rc = prepare_kernels(c.p);
     if (rc) return rc;
@@ -754,7 +796,8 @@ int ebtc_tune(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, int3
   LzArgs a0 = make_args(b, o, w, L, base);
   EBTC_LAUNCH(launch_blkmap(a0.tasks, b->R, (int32_t*)(w + L.off_blkmap), s));
   EBTC_LAUNCH(launch_start(b->dtype, a0, L.total_blocks, s));
-  double ms[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+  double ms[EBTC_TUNE_SLOTS];
+  for (double& v : ms) v = -1.0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   for (auto& e : ev) {
     if (hipEventCreate(&e) != hipSuccess) {
@@ -774,9 +817,15 @@ int ebtc_tune(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, int3
     // [ev0, ev1): the once-per-call sort (segmented form only); [ev2, ev3): kReps products after a
     // warm-up. Step 0 reads only the start vector and the state k_start wrote, so every launch
     // does the same work.
-    hipError_t e = hipEventRecord(ev[0], s);
+    hipError_t e = hipSuccess;
+    if (p.form == EBTC_SPMV_BALANCED) {
+      if (b->bal_begin.size() != (size_t)b->R + 1) b->bal_begin = bal_shares(b);
+      e = hipMemcpyAsync(w + Lc.off_balbeg, b->bal_begin.data(), sizeof(int64_t) * (b->R + 1), hipMemcpyHostToDevice, s);
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[0], s);
     if (e == hipSuccess && p.form == EBTC_SPMV_SEGMENTED)
       e = launch_seg_prepare(b->dtype, has_val, a, L.total_blocks, p.smax, s);
+    if (e == hipSuccess && p.form == EBTC_SPMV_BALANCED) e = launch_bal_rows(a, 0, (int)b->R, s);
     if (e == hipSuccess) e = hipEventRecord(ev[1], s);
     if (e == hipSuccess) e = launch_spmv_step(b->dtype, has_val, p.lanes, 0, a, L.total_blocks, s);
     if (e == hipSuccess) e = hipEventRecord(ev[2], s);
@@ -790,7 +839,7 @@ int ebtc_tune(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, int3
       rc = fail(EBTC_EHIP, std::string("tuning launch: ") + hipGetErrorString(e));
       break;
     }
-    ms[cands[c].slot] = t_spmv / kReps + (p.form == EBTC_SPMV_SEGMENTED ? t_prep / steps : 0.0);
+    ms[cands[c].slot] = t_spmv / kReps + (p.form == EBTC_SPMV_SEGMENTED || p.form == EBTC_SPMV_BALANCED ? t_prep / steps : 0.0);
     if (best < 0 || ms[cands[c].slot] < ms[cands[best].slot]) best = (int)c;
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
@@ -803,7 +852,7 @@ int ebtc_tune(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, int3
   if (lanes_out) *lanes_out = b->tuned_lanes;
   if (seglen_out) *seglen_out = b->tuned_seglen;
   if (ms_out)
-    for (int i = 0; i < 8; ++i) ms_out[i] = ms[i];
+    for (int i = 0; i < EBTC_TUNE_SLOTS; ++i) ms_out[i] = ms[i];
   return EBTC_OK;
 }
 

@@ -55,6 +55,18 @@ struct SegBlock {
 };
 static_assert(sizeof(SegBlock) == 64, "SegBlock layout");
 
+// One workgroup's share of the entry-balanced SpMV form: the rows of realization `task` whose first
+// entry falls in its entries [q * kBalEntries, (q + 1) * kBalEntries) (the last share of a
+// realization also takes its trailing empty rows). Row bounds written once per call.
+struct BalPart {
+  int32_t task;
+  int32_t q;
+  int32_t r_begin;
+  int32_t r_end;
+};
+static_assert(sizeof(BalPart) == 16, "BalPart layout");
+constexpr int kBalEntries = 8192;
+
 struct GraphInfo {
   int64_t score_off;   // offset of the graph's block in the score output
   int32_t n;
@@ -117,6 +129,10 @@ struct LzArgs {
                            // segment s at [woff[s * 17 + w], woff[s * 17 + w + 1])
   int32_t seg_wstride;     // max segments x 17
   SegBlock* seg_blk;       // [row blocks] descriptors for the first loads of a product
+  // entry-balanced SpMV (bal != nullptr): one workgroup per share of kBalEntries entries
+  BalPart* bal;            // [nbal] shares, realization by realization
+  const int64_t* bal_begin;  // [R + 1] first share of each realization (host-computed)
+  int32_t nbal;
   // memory-bounded form (window > 0): Gram-Schmidt against the last `window` basis vectors only, the
   // raw basis kept in a ring of window + 1 slots (vector i in slot i % (window + 1))
   int32_t window;
@@ -164,6 +180,8 @@ int seg_max_cols(int dtype);
 hipError_t prepare_seg_kernels();
 // Sorts every row block's entries by column segment (a.seg_* arrays); smax = max segments in the launch.
 hipError_t launch_seg_prepare(int dtype, bool has_val, const LzArgs& a, int64_t nblocks, int smax, hipStream_t s);
+// Row bounds of the entry-balanced form's shares of realizations [t0, t0 + count).
+hipError_t launch_bal_rows(const LzArgs& a, int t0, int count, hipStream_t s);
 
 // ---- launchers (k_tridiag.hip)
 // mode 0: final (closes step m_steps-1 when still open; writes y/theta/est, diag, checkpoint);

@@ -168,7 +168,9 @@ struct StreamShape {
   static constexpr int CAP = sizeof(T) == 8 ? 3072 : 6144;  // product slots (24 KB)
 };
 
-template <typename T, bool HAS_VAL, int NT = kBlock, int CAP = StreamShape<T>::CAP>
+// SEQ_HUB: a row beyond the capacity is summed by one thread in entry order instead (the first
+// product's arithmetic, for a caller that must reproduce it).
+template <typename T, bool HAS_VAL, int NT = kBlock, int CAP = StreamShape<T>::CAP, bool SEQ_HUB = false>
 __device__ inline void spmv_stream_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                         const T* __restrict__ va, const T* __restrict__ x, int r0, int rows,
                                         double scale, int* rp_lds, T* prod, T* w_out, double* red) {
@@ -179,6 +181,18 @@ __device__ inline void spmv_stream_rows(const int32_t* __restrict__ rp, const in
   int ra = 0;
   while (ra < rows) {
     const int nz0 = rp_lds[ra];
+    if (SEQ_HUB && rp_lds[ra + 1] - nz0 > CAP) {
+      if (tid == 0) {
+        double acc = 0.0;
+        for (int k = nz0; k < rp_lds[ra + 1]; ++k) {
+          const T xv = x[ci[k]];
+          if constexpr (HAS_VAL) acc += (double)(va[k] * xv); else acc += (double)xv;
+        }
+        w_out[ra] = (T)(acc * scale);
+      }
+      ++ra;
+      continue;
+    }
     if (rp_lds[ra + 1] - nz0 > CAP) {  // hub row: whole workgroup, direct gathers
       const int e = rp_lds[ra + 1];
       T acc = 0;
@@ -274,6 +288,65 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream_1(int32_t n, const int32
   const int r0 = logical_block() * kStreamRows;
   if (r0 >= n) return;
   spmv_stream_rows<T, HAS_VAL>(rp, ci, va, x, r0, min(n - r0, kStreamRows), 1.0, rp_lds, prod, y + r0, red);
+}
+
+// ------------------------------------------------------------------------------- entry-balanced
+// Power-law graphs keep most of their entries in a few rows, numbered first (a Barabasi-Albert
+// graph of 1e6 nodes holds 22 times the mean in its first 2048 rows), so one row block's workgroup
+// sets the time of a launch. Here each workgroup takes an equal share of a realization's entries:
+// the rows whose first entry falls in its kBalEntries entries, whole (a row is never split, so its
+// sum is the CSR-stream form's, bit for bit), walked 256 rows at a time by the stream arithmetic.
+
+// Row bounds of every share, once per call: one workgroup per realization, one thread per share.
+__global__ __launch_bounds__(kBlock) void k_bal_rows(LzArgs a, int t0) {
+  const int t = t0 + blockIdx.x;
+  const Task tk = a.tasks[t];
+  const int32_t* rp = a.row_ptr + tk.rowptr_off;
+  const int n = tk.n, base = rp[0];
+  const int64_t p0 = a.bal_begin[t], np = a.bal_begin[t + 1] - p0;
+  auto first_at_or_after = [&](int64_t e) {  // first row r with rp[r] >= base + e, in [0, n]
+    int lo = 0, hi = n;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((int64_t)rp[mid] - base < e) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  };
+  for (int64_t q = threadIdx.x; q < np; q += kBlock) {
+    BalPart bp;
+    bp.task = t;
+    bp.q = (int32_t)q;
+    bp.r_begin = first_at_or_after(q * kBalEntries);
+    bp.r_end = q + 1 == np ? n : first_at_or_after((q + 1) * kBalEntries);
+    a.bal[p0 + q] = bp;
+  }
+}
+
+// FIRST: the first product from the all-ones start, whose rows beyond the LDS capacity are summed in
+// entry order as the row-sum kernel does (the other forms' first product), so that every step
+// matches the CSR-stream form bit for bit.
+template <typename T, bool HAS_VAL, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_spmv_bal(LzArgs a, int j) {
+  __shared__ int rp_lds[kStreamRows + 1];
+  __shared__ T prod[StreamShape<T>::CAP];
+  __shared__ double chunks[kMaxChunks];
+  const int lb = logical_block();
+  const BalPart bp = a.bal[a.blkmap != nullptr ? (int64_t)lb : a.bal_begin[a.single_task] + lb];
+  const Task tk = a.tasks[bp.task];
+  RState* st = a.state + bp.task;
+  double sj;
+  // only the first share of a realization records the closed step (all compute it)
+  if (!open_step(a, tk, st, bp.q == 0 ? 0 : 1, j, chunks, &sj)) return;
+  const int n = tk.n;
+  const T* va = HAS_VAL ? (const T*)a.values + tk.nnz_off : nullptr;
+  const T* x = (const T*)a.V + tk.vec_off + vslot(a, j) * n;
+  T* W = (T*)a.W + tk.w_off;
+  for (int r0 = bp.r_begin; r0 < bp.r_end; r0 += kStreamRows) {
+    if (r0 > bp.r_begin) __syncthreads();  // the previous rows' LDS readers are done
+    spmv_stream_rows<T, HAS_VAL, kBlock, StreamShape<T>::CAP, FIRST>(a.row_ptr + tk.rowptr_off, a.col_idx + tk.nnz_off,
+                                                                    va, x, r0, min(bp.r_end - r0, kStreamRows), sj,
+                                                                    rp_lds, prod, W + r0, chunks);
+  }
 }
 
 // ------------------------------------------------------------------------------- LDS-staged gathers
@@ -969,6 +1042,13 @@ hipError_t step_direct(int lanes, int j, const LzArgs& a, int64_t nb, hipStream_
 
 template <typename T, bool HAS_VAL>
 hipError_t step_any(int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
+  if (a.bal != nullptr) {
+    if (j == 0 && a.unit_start)
+      hipLaunchKernelGGL((k_spmv_bal<T, HAS_VAL, true>), dim3((unsigned)a.nbal), dim3(kBlock), 0, s, a, j);
+    else
+      hipLaunchKernelGGL((k_spmv_bal<T, HAS_VAL, false>), dim3((unsigned)a.nbal), dim3(kBlock), 0, s, a, j);
+    return hipGetLastError();
+  }
   if (a.seg_cols > 0) {
     if (a.seg_vec)
       hipLaunchKernelGGL((k_spmv_seg<T, HAS_VAL, true>), dim3((unsigned)nb), dim3(kSegThreads),
@@ -1067,6 +1147,12 @@ int seg_max_cols(int dtype) {
   return dtype == EBTC_F64 ? SegShape<double>::MAXCOLS : SegShape<float>::MAXCOLS;
 }
 
+hipError_t launch_bal_rows(const LzArgs& a, int t0, int count, hipStream_t s) {
+  if (a.bal == nullptr || count < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_bal_rows, dim3((unsigned)count), dim3(kBlock), 0, s, a, t0);
+  return hipGetLastError();
+}
+
 hipError_t launch_seg_prepare(int dtype, bool has_val, const LzArgs& a, int64_t nb, int smax, hipStream_t s) {
   if (smax < 1 || smax > kSegMax || a.seg_cols <= 0) return hipErrorInvalidValue;
   if (dtype == EBTC_F64)
@@ -1080,7 +1166,7 @@ int staged_max_seglen(int dtype) {
 }
 
 hipError_t launch_spmv_step(int dtype, bool has_val, int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
-  if (j == 0 && a.unit_start) {
+  if (j == 0 && a.unit_start && a.bal == nullptr) {  // the balanced form gathers the ones instead
     const dim3 g((unsigned)nb), b(first_threads(has_val));
     if (dtype == EBTC_F64) {
       if (has_val) hipLaunchKernelGGL((k_spmv_first<double, true>), g, b, 0, s, a);

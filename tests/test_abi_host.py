@@ -153,6 +153,24 @@ def test_plan_workspace_arithmetic(dtype, es):
     A.lib().ebtc_batch_destroy(h)
 
 
+def test_plan_balanced_workspace_arithmetic():
+    # the entry-balanced form appends its shares (16 bytes each: one per 8192 entries of a
+    # realization, at least one) and the first share of each realization (int64, R + 1)
+    nnz = (10, 9000, 8192, 8193, 0)
+    d, keep = make_desc(G=2, nreal=(2, 3), n=(3000, 70), nnz=nnz)
+    rc, h = create(d)
+    assert rc == 0
+    rc, ws, _ = plan(h, m=30, spmv=5)
+    assert rc == 0
+    shares = sum(max(1, -(-z // 8192)) for z in nnz)
+    assert shares == 1 + 2 + 1 + 2 + 1
+    off = expected_ws(2, (2, 3), (3000, 70), 31, 4, RSTATE_BYTES)
+    off = align(off + 16 * shares)
+    off = align(off + 8 * (5 + 1))
+    assert ws == off
+    A.lib().ebtc_batch_destroy(h)
+
+
 def test_plan_segmented_workspace_arithmetic():
     # the column-segmented form appends: block flags (int32), per-(segment, row) counts (8 bits,
     # max segments x 2048 per block), wave-band offsets (16 bits, max segments x 17 per block),
@@ -179,7 +197,7 @@ def test_plan_segmented_workspace_arithmetic():
     (dict(m=65), "m must be"), (dict(m=-1), "m must be"), (dict(m=0, m_max=0), "m_max"),
     (dict(m=0, tol=0.0), "tol"), (dict(reorth=3), "reorth"), (dict(schedule=9), "schedule"),
     (dict(lanes_per_row=5), "lanes_per_row"), (dict(hub_threshold=-1), "hub_threshold"),
-    (dict(seg_len=-1), "seg_len"), (dict(spmv=5), "spmv form"), (dict(spmv=-1), "spmv form"),
+    (dict(seg_len=-1), "seg_len"), (dict(spmv=6), "spmv form"), (dict(spmv=-1), "spmv form"),
 ])
 def test_plan_rejects_bad_opts(kw, text):
     d, keep = make_desc()

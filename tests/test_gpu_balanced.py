@@ -1,0 +1,140 @@
+"""GPU parity of the entry-balanced SpMV form against the CSR-stream form and the FP64 oracle.
+
+The balanced form runs the stream form's row arithmetic over workgroups that take equal shares of a
+realization's entries instead of equal row counts; rows stay whole, and its first product sums rows
+beyond the LDS capacity in entry order like the row-sum kernel the other forms use, so the whole
+Lanczos path must agree with the stream form bit for bit -- scores, log-scales, m_used, flags and
+gradients -- on power-law graphs (a few rows holding most entries), rows longer than one share or
+than the LDS capacity, empty rows and graphs, and ragged sizes.
+"""
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+from fixtures import configs as C, graphs as G
+from tests.test_gpu_parity import api, check_against_oracle, torch_mod
+from tests.test_gpu_segmented import assert_bitwise, symmetric_weights
+
+pytestmark = pytest.mark.gpu
+
+
+def hub_batch(dtype, weighted):
+    """Three realizations: ER n=20000 with hubs of 9000, 7000, 7000 and 2500 neighbours (longer than
+    a share, than the stream form's LDS capacity, or neither), a graph with isolated nodes between
+    two dense clusters (long runs of empty rows), and a 5-node path."""
+    rng = np.random.default_rng(21)
+    reals = []
+    n0 = 20000
+    keys = G.er_keys(n0, 6.0 / (n0 - 1), G.rng_for(31, 0, 1))
+    hubs, deg = np.array([0, 1, 700, 19999]), np.array([9000, 7000, 7000, 2500])
+    extra = [G.canon(np.full(d, h), rng.choice(n0, d, replace=False), n0) for h, d in zip(hubs, deg)]
+    keys = np.unique(np.concatenate([keys] + extra))
+    keys = keys[(keys // n0) != (keys % n0)]
+    reals.append((n0, *G.csr_from_keys(keys, n0)))
+    n1 = 30000
+    a = G.er_keys(400, 0.2, G.rng_for(31, 1, 1))
+    i, j = a // 400, a % 400
+    b = G.canon(i + 29000, j + 29000, n1)
+    keys1 = np.unique(np.concatenate([G.canon(i, j, n1), b]))
+    reals.append((n1, *G.csr_from_keys(keys1, n1)))
+    n2 = 5
+    keys2 = G.canon(np.arange(4), np.arange(1, 5), n2)
+    reals.append((n2, *G.csr_from_keys(keys2, n2)))
+    parts = [(SimpleNamespace(n=n, K=min(n, 10)), np.arange(min(n, 10)), [(rp, ci)]) for n, rp, ci in reals]
+    hb = C.assemble(parts, dtype, with_values=weighted)
+    if weighted:
+        hb.values = symmetric_weights(hb, seed=3)
+    return hb
+
+
+def run_pair(hb, m, **kw):
+    torch = torch_mod()
+    b = api().Batch.from_host(hb)
+    ref = b.scores(m=m, spmv="stream", **kw)
+    bal = b.scores(m=m, spmv="balanced", **kw)
+    torch.cuda.synchronize()
+    return b, ref, bal
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_balanced_equals_stream_on_hubs_and_empty_rows(gpu_lib, dtype, weighted):
+    hb = hub_batch(dtype, weighted)
+    rp0 = hb.csr(0)[1]
+    assert np.diff(rp0).max() > 8192  # a row longer than one share and than the LDS capacity
+    b, ref, bal = run_pair(hb, 20)
+    assert_bitwise(ref, bal)
+    # rows of 9000 entries put the norm near 100: FP64 rounding in another summation order then
+    # moves the scores by ~8e-12 relative, in one or two Gram-Schmidt passes alike, so this graph is
+    # held to the FP32 bar; the FP64 bar is checked on the power-law batch below
+    check_against_oracle(hb, bal, b, 20, "f32", K=10)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_balanced_equals_stream_on_power_law_batch(gpu_lib, dtype):
+    # Barabasi-Albert (its first row block holds several times the mean entries) beside a ragged ER
+    specs = (C.GraphSpec("ba", 20000, 10, "clique", 20, N=2, K=20),
+             C.er_spec(9000, 12.0, target="er", t=20, int_p=0.2, N=3, K=20))
+    w = C.Workload(93, "balanced-power-law", specs, dtype, 25)
+    hb = C.build(w)
+    rp = hb.csr(0)[1]
+    blocks = np.diff(rp[np.minimum(np.arange(0, 20000 + 2048, 2048), 20000)])
+    assert blocks[0] > 3 * blocks.mean()
+    b, ref, bal = run_pair(hb, w.m)
+    assert_bitwise(ref, bal)
+    check_against_oracle(hb, bal, b, w.m, dtype, K=20)
+
+
+@pytest.mark.parametrize("schedule,hipgraph", [("plain", False), ("batched", True)])
+def test_balanced_schedules_and_replays(gpu_lib, schedule, hipgraph):
+    torch = torch_mod()
+    specs = (C.GraphSpec("ba", 12000, 6, "clique", 20, N=2, K=20),)
+    w = C.Workload(94, "balanced-schedules", specs, "f32", 20)
+    hb = C.build(w)
+    b = api().Batch.from_host(hb)
+    ref = b.scores(m=w.m, spmv="stream", schedule="batched", hipgraph=False)
+    run = b.run(m=w.m, spmv="balanced", schedule=schedule, hipgraph=hipgraph)
+    r = ref.scores.cpu().numpy()
+    for _ in range(3):  # replays with eager work between them
+        o = run.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(o.scores.cpu().numpy(), r)
+        torch.zeros(1 << 20, device="cuda").sum().item()
+
+
+def test_balanced_adaptive_and_two_pass(gpu_lib):
+    hb = hub_batch("f32", True)
+    _, ref, bal = run_pair(hb, 0, tol=1e-6, m_max=40)
+    assert_bitwise(ref, bal)
+    _, ref, bal = run_pair(hb, 25, reorth=0)
+    assert_bitwise(ref, bal)
+
+
+def test_balanced_backward_equals_stream(gpu_lib):
+    torch = torch_mod()
+    specs = (C.GraphSpec("ba", 6000, 5, "clique", 20, N=2, K=20),)
+    w = C.Workload(95, "balanced-backward", specs, "f32", 20)
+    hb = C.build(w)
+    hb.values = symmetric_weights(hb, seed=7)
+    b = api().Batch.from_host(hb)
+    fwd = b.scores(m=w.m)
+    g = torch.linspace(-1.0, 1.0, fwd.scores.numel(), device="cuda", dtype=fwd.scores.dtype)
+    g_ref = b.scores_backward(fwd.log_scale, g, m=w.m, spmv="stream").cpu().numpy()
+    g_bal = b.scores_backward(fwd.log_scale, g, m=w.m, spmv="balanced").cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(g_ref, g_bal)
+
+
+def test_tuner_times_the_balanced_form(gpu_lib):
+    hb = hub_batch("f32", False)
+    b = api().Batch.from_host(hb)
+    t = b.tune(m=20)
+    assert t["ms_per_launch"]["balanced"] > 0.0
+    out = b.scores(m=20)  # the tuned form
+    ref = b.scores(m=20, spmv="stream")
+    if t["form"] in ("stream", "balanced"):
+        assert_bitwise(ref, out)
+    else:  # other forms add a row's products in another order
+        r, o = ref.scores.cpu().numpy(), out.scores.cpu().numpy()
+        assert np.max(np.abs(r - o)) <= 1e-5 * np.max(np.abs(r))
