@@ -1166,7 +1166,9 @@ int staged_max_seglen(int dtype) {
 }
 
 hipError_t launch_spmv_step(int dtype, bool has_val, int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
-  if (j == 0 && a.unit_start && a.bal == nullptr) {  // the balanced form gathers the ones instead
+  // the first product: row sums (degrees for a pattern-only graph, from the row pointers alone); the
+  // balanced form sums weighted rows itself, in equal shares of entries
+  if (j == 0 && a.unit_start && (a.bal == nullptr || !has_val)) {
     const dim3 g((unsigned)nb), b(first_threads(has_val));
     if (dtype == EBTC_F64) {
       if (has_val) hipLaunchKernelGGL((k_spmv_first<double, true>), g, b, 0, s, a);
