@@ -104,7 +104,9 @@ typedef struct {
   int32_t hub_threshold; /* rows with more entries are reduced by a whole workgroup; 0 = auto     */
   int32_t seg_len;       /* LDS-staged and column-segmented forms: vector segment length in
                             elements (0 = the form's default: the largest that fits for LDS-staged,
-                            12288 FP32 / 6144 FP64 for column-segmented)                          */
+                            12288 FP32 / 6144 FP64 for column-segmented); for the entry-balanced
+                            form, entries per share, 256..2^24 (0 = the largest power of two in
+                            4096..16384 that leaves the batch 8192 shares)                        */
 } ebtc_opts;
 
 enum ebtc_spmv_form {
@@ -120,7 +122,7 @@ enum ebtc_spmv_form {
                                 row blocks with more than 65535 entries, or a row with more than 255
                                 entries in one segment, use the CSR-stream form                     */
   EBTC_SPMV_BALANCED = 5     /* the CSR-stream arithmetic with workgroups over equal shares of a
-                                realization's entries (8192 each) instead of equal row counts: rows
+                                realization's entries (seg_len each) instead of equal row counts: rows
                                 stay whole, so the sums are the stream form's; for graphs whose
                                 first rows hold most entries (preferential attachment). Each call
                                 first finds every share's rows                                     */

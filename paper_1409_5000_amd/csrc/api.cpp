@@ -41,7 +41,8 @@ struct Layout {
   size_t off_segflag = 0, off_segcnt = 0, off_segwoff = 0, off_segblk = 0, off_segcol = 0, off_segval = 0;
   // entry-balanced SpMV arenas (present when the plan uses that form)
   size_t off_bal = 0, off_balbeg = 0;
-  int64_t nbal = 0;  // shares of kBalEntries entries over all realizations
+  int balent = 0;
+  int64_t nbal = 0;  // shares of SpmvPlan::balent entries over all realizations
   size_t total = 0;
   int64_t total_blocks = 0;
 };
@@ -88,6 +89,7 @@ struct ebtc_batch {
   std::vector<GraphInfo> graphs;
   std::vector<int64_t> nnz_r;       // per-realization entry counts (validation upload)
   std::vector<int64_t> bal_begin;   // [R + 1] first entry-balanced share of each realization
+  int32_t bal_entries = 0;          // the share size bal_begin was computed for
   std::vector<int32_t> topk_k;
   std::vector<int64_t> topk_off;
   std::vector<ExecEntry> execs;
@@ -122,11 +124,19 @@ struct SpmvPlan {
   int seglen = 0;   // LDS-staged: segment length
   int segcols = 0;  // column-segmented: columns per segment
   int smax = 0;     // column-segmented: segments of the largest realization
+  int balent = 0;   // entry-balanced: entries per share
 };
 
 SpmvPlan spmv_plan(const ebtc_batch* b, const ebtc_opts* o);
 
+std::vector<int64_t> bal_shares(const ebtc_batch* b, int e);
+
 int check_plan(const ebtc_batch* b, const SpmvPlan& p) {
+  if (p.form == EBTC_SPMV_BALANCED) {
+    if (p.balent < 256 || p.balent > (1 << 24))
+      return fail(EBTC_EINVAL, "the entry-balanced SpMV takes shares of 256 to 2^24 entries (seg_len)");
+    if (bal_shares(b, p.balent).back() > INT32_MAX) return fail(EBTC_EINVAL, "too many entry-balanced shares");
+  }
   if (p.form == EBTC_SPMV_SEGMENTED && p.smax > kSegMax)
     return fail(EBTC_EINVAL, "the column-segmented SpMV needs at most " + std::to_string(kSegMax) +
                                  " segments: n_max " + std::to_string(b->n_max) + " > " +
@@ -134,15 +144,33 @@ int check_plan(const ebtc_batch* b, const SpmvPlan& p) {
   return EBTC_OK;
 }
 
-// First entry-balanced share of each realization ([R + 1]): one share per kBalEntries entries, at
-// least one per realization.
-std::vector<int64_t> bal_shares(const ebtc_batch* b) {
+// First entry-balanced share of each realization ([R + 1]): one share per e entries, at least one
+// per realization.
+std::vector<int64_t> bal_shares(const ebtc_batch* b, int e) {
   std::vector<int64_t> v((size_t)b->R + 1, 0);
   for (int64_t r = 0; r < b->R; ++r) {
     const int64_t z = b->nnz_off[r + 1] - b->nnz_off[r];
-    v[r + 1] = v[r] + std::max<int64_t>(1, (z + kBalEntries - 1) / kBalEntries);
+    v[r + 1] = v[r] + std::max<int64_t>(1, (z + e - 1) / e);
   }
   return v;
+}
+
+// The shares of the batch's plan, computed once per share size and kept alive for async uploads.
+const std::vector<int64_t>& bal_table(ebtc_batch* b, int e) {
+  if (b->bal_entries != e || b->bal_begin.size() != (size_t)b->R + 1) {
+    b->bal_begin = bal_shares(b, e);
+    b->bal_entries = e;
+  }
+  return b->bal_begin;
+}
+
+// Default share size: the largest power of two in [kBalEntriesMin, kBalEntriesMax] that leaves the
+// batch at least kBalTargetShares shares.
+int bal_default(const ebtc_batch* b) {
+  const int64_t z = b->nnz_off[b->R];
+  int e = kBalEntriesMax;
+  while (e > kBalEntriesMin && z / e < kBalTargetShares) e >>= 1;
+  return e;
 }
 
 Layout make_layout(const ebtc_batch* b, const ebtc_opts* o, const SpmvPlan& sp) {
@@ -193,7 +221,8 @@ Layout make_layout(const ebtc_batch* b, const ebtc_opts* o, const SpmvPlan& sp) 
     if (b->values) off = align_up(off + es * z);
   }
   if (sp.form == EBTC_SPMV_BALANCED) {
-    L.nbal = bal_shares(b).back();
+    L.nbal = bal_shares(b, sp.balent).back();
+    L.balent = sp.balent;
     L.off_bal = off;
     off = align_up(off + sizeof(BalPart) * (size_t)L.nbal);
     L.off_balbeg = off;
@@ -236,9 +265,8 @@ int upload_tables(ebtc_batch* b, char* ws, const Layout& L, hipStream_t s) {
   EBTC_HIP(hipMemcpyAsync(ws + L.off_tasks, b->tasks.data(), sizeof(Task) * b->R, hipMemcpyHostToDevice, s));
   EBTC_HIP(hipMemcpyAsync(ws + L.off_graphs, b->graphs.data(), sizeof(GraphInfo) * b->G, hipMemcpyHostToDevice, s));
   if (L.nbal > 0) {
-    if (b->bal_begin.size() != (size_t)b->R + 1) b->bal_begin = bal_shares(b);  // fixed per batch; kept alive
-    EBTC_HIP(hipMemcpyAsync(ws + L.off_balbeg, b->bal_begin.data(), sizeof(int64_t) * (b->R + 1),
-                            hipMemcpyHostToDevice, s));
+    const std::vector<int64_t>& t = bal_table(b, L.balent);
+    EBTC_HIP(hipMemcpyAsync(ws + L.off_balbeg, t.data(), sizeof(int64_t) * (b->R + 1), hipMemcpyHostToDevice, s));
   }
   return EBTC_OK;
 }
@@ -255,6 +283,7 @@ SpmvPlan spmv_form(const ebtc_batch* b, int form, int lanes, int seg_len, int hu
     p.segcols = std::min(seg_len > 0 ? seg_len : seg_max_cols(b->dtype), seg_max_cols(b->dtype));
     p.smax = (b->n_max + p.segcols - 1) / p.segcols;
   }
+  if (form == EBTC_SPMV_BALANCED) p.balent = seg_len > 0 ? seg_len : bal_default(b);
   p.hub = hub ? hub : 16 * (p.lanes ? p.lanes : 8);
   return p;
 }
@@ -309,6 +338,7 @@ LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout
     a.bal = (BalPart*)(ws + L.off_bal);
     a.bal_begin = (const int64_t*)(ws + L.off_balbeg);
     a.nbal = (int32_t)L.nbal;
+    a.bal_entries = sp.balent;
   }
   return a;
 }
@@ -685,7 +715,7 @@ int ebtc_scores(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, vo
     return enqueue_batched(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, sp, s);
   const ExecKey key{ws,        scores_out, log_scale_out, ckpt_out, diag_out, o->m,
                     o->m_max,  o->reorth,  o->shift,      sp.form,  sp.lanes, sp.hub,
-                    sp.seglen + sp.segcols, o->tol};
+                    sp.seglen + sp.segcols + sp.balent, o->tol};
   for (auto& e : b->execs) {
     if (e.key == key) {
       EBTC_HIP(hipGraphLaunch(e.exec, s));
@@ -819,8 +849,8 @@ int ebtc_tune(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, int3
     // does the same work.
     hipError_t e = hipSuccess;
     if (p.form == EBTC_SPMV_BALANCED) {
-      if (b->bal_begin.size() != (size_t)b->R + 1) b->bal_begin = bal_shares(b);
-      e = hipMemcpyAsync(w + Lc.off_balbeg, b->bal_begin.data(), sizeof(int64_t) * (b->R + 1), hipMemcpyHostToDevice, s);
+      const std::vector<int64_t>& t = bal_table(b, p.balent);
+      e = hipMemcpyAsync(w + Lc.off_balbeg, t.data(), sizeof(int64_t) * (b->R + 1), hipMemcpyHostToDevice, s);
     }
     if (e == hipSuccess) e = hipEventRecord(ev[0], s);
     if (e == hipSuccess && p.form == EBTC_SPMV_SEGMENTED)
@@ -847,7 +877,7 @@ int ebtc_tune(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, int3
   const SpmvPlan& p = cands[best].p;
   b->tuned_form = p.form;
   b->tuned_lanes = p.lanes;
-  b->tuned_seglen = p.form == EBTC_SPMV_SEGMENTED ? p.segcols : p.seglen;
+  b->tuned_seglen = p.form == EBTC_SPMV_SEGMENTED ? p.segcols : p.form == EBTC_SPMV_BALANCED ? p.balent : p.seglen;
   if (form_out) *form_out = b->tuned_form;
   if (lanes_out) *lanes_out = b->tuned_lanes;
   if (seglen_out) *seglen_out = b->tuned_seglen;

@@ -56,7 +56,7 @@ struct SegBlock {
 static_assert(sizeof(SegBlock) == 64, "SegBlock layout");
 
 // One workgroup's share of the entry-balanced SpMV form: the rows of realization `task` whose first
-// entry falls in its entries [q * kBalEntries, (q + 1) * kBalEntries) (the last share of a
+// entry falls in its entries [q * E, (q + 1) * E), E = LzArgs::bal_entries (the last share of a
 // realization also takes its trailing empty rows). Row bounds written once per call.
 struct BalPart {
   int32_t task;
@@ -65,7 +65,10 @@ struct BalPart {
   int32_t r_end;
 };
 static_assert(sizeof(BalPart) == 16, "BalPart layout");
-constexpr int kBalEntries = 8192;
+// Share sizes of the entry-balanced form: the default is the largest power of two in this range that
+// still gives a batch about 8192 shares (two or more workgroups per CU in flight, few launches' worth
+// of row walks per workgroup).
+constexpr int kBalEntriesMin = 4096, kBalEntriesMax = 16384, kBalTargetShares = 8192;
 
 struct GraphInfo {
   int64_t score_off;   // offset of the graph's block in the score output
@@ -129,10 +132,11 @@ struct LzArgs {
                            // segment s at [woff[s * 17 + w], woff[s * 17 + w + 1])
   int32_t seg_wstride;     // max segments x 17
   SegBlock* seg_blk;       // [row blocks] descriptors for the first loads of a product
-  // entry-balanced SpMV (bal != nullptr): one workgroup per share of kBalEntries entries
+  // entry-balanced SpMV (bal != nullptr): one workgroup per share of bal_entries entries
   BalPart* bal;            // [nbal] shares, realization by realization
   const int64_t* bal_begin;  // [R + 1] first share of each realization (host-computed)
   int32_t nbal;
+  int32_t bal_entries;     // entries per share
   // memory-bounded form (window > 0): Gram-Schmidt against the last `window` basis vectors only, the
   // raw basis kept in a ring of window + 1 slots (vector i in slot i % (window + 1))
   int32_t window;

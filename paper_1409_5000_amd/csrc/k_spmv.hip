@@ -294,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream_1(int32_t n, const int32
 // Power-law graphs keep most of their entries in a few rows, numbered first (a Barabasi-Albert
 // graph of 1e6 nodes holds 22 times the mean in its first 2048 rows), so one row block's workgroup
 // sets the time of a launch. Here each workgroup takes an equal share of a realization's entries:
-// the rows whose first entry falls in its kBalEntries entries, whole (a row is never split, so its
+// the rows whose first entry falls in its share of entries, whole (a row is never split, so its
 // sum is the CSR-stream form's, bit for bit), walked 256 rows at a time by the stream arithmetic.
 
 // Row bounds of every share, once per call: one workgroup per realization, one thread per share.
@@ -316,8 +316,8 @@ __global__ __launch_bounds__(kBlock) void k_bal_rows(LzArgs a, int t0) {
     BalPart bp;
     bp.task = t;
     bp.q = (int32_t)q;
-    bp.r_begin = first_at_or_after(q * kBalEntries);
-    bp.r_end = q + 1 == np ? n : first_at_or_after((q + 1) * kBalEntries);
+    bp.r_begin = first_at_or_after(q * a.bal_entries);
+    bp.r_end = q + 1 == np ? n : first_at_or_after((q + 1) * a.bal_entries);
     a.bal[p0 + q] = bp;
   }
 }

@@ -153,21 +153,24 @@ def test_plan_workspace_arithmetic(dtype, es):
     A.lib().ebtc_batch_destroy(h)
 
 
-def test_plan_balanced_workspace_arithmetic():
-    # the entry-balanced form appends its shares (16 bytes each: one per 8192 entries of a
-    # realization, at least one) and the first share of each realization (int64, R + 1)
+@pytest.mark.parametrize("seg_len,per", [(0, 4096), (8192, 8192), (300, 300)])
+def test_plan_balanced_workspace_arithmetic(seg_len, per):
+    # the entry-balanced form appends its shares (16 bytes each: one per `per` entries of a
+    # realization, at least one) and the first share of each realization (int64, R + 1); a small
+    # batch takes the smallest default share size (4096)
     nnz = (10, 9000, 8192, 8193, 0)
     d, keep = make_desc(G=2, nreal=(2, 3), n=(3000, 70), nnz=nnz)
     rc, h = create(d)
     assert rc == 0
-    rc, ws, _ = plan(h, m=30, spmv=5)
+    rc, ws, _ = plan(h, m=30, spmv=5, seg_len=seg_len)
     assert rc == 0
-    shares = sum(max(1, -(-z // 8192)) for z in nnz)
-    assert shares == 1 + 2 + 1 + 2 + 1
+    shares = sum(max(1, -(-z // per)) for z in nnz)
     off = expected_ws(2, (2, 3), (3000, 70), 31, 4, RSTATE_BYTES)
     off = align(off + 16 * shares)
     off = align(off + 8 * (5 + 1))
     assert ws == off
+    rc, _, _ = plan(h, m=30, spmv=5, seg_len=100)
+    assert rc == A.EBTC_EINVAL and "shares of 256" in A.lib().ebtc_last_error().decode()
     A.lib().ebtc_batch_destroy(h)
 
 
