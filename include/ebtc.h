@@ -271,8 +271,11 @@ enum ebtc_phase {
   EBTC_PHASE_TRIDIAG = 4,    /* FP64 tridiagonal exponential (final and adaptive checks)        */
   EBTC_PHASE_COMBINE = 5,    /* u = beta0 V y                                                    */
   EBTC_PHASE_SUM = 6,        /* realization sum with per-graph log-scale                        */
-  EBTC_PHASE_PREPARE = 7,    /* column-segment sort of the entries (column-segmented SpMV only) */
-  EBTC_PHASE_FIRST = 8,      /* step 0's product A 1 of the all-ones start: row sums, no gathers */
+  EBTC_PHASE_PREPARE = 7,    /* once per call: the column-segment sort of the entries
+                                (column-segmented SpMV) or the rows of every share (entry-balanced) */
+  EBTC_PHASE_FIRST = 8,      /* step 0's product A 1 of the all-ones start: row sums, no gathers
+                                (the entry-balanced form computes a weighted graph's row sums with
+                                its own SpMV kernel over the ones, in equal shares of entries)     */
   EBTC_PHASE_COUNT = 9
 };
 /* Measurement only: runs ebtc_scores' batched launch sequence once, eagerly (no hipGraph), with a
