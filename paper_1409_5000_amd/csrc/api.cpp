@@ -386,6 +386,12 @@ struct Prof {
     if (prof && prof->after()) return fail(EBTC_EHIP, "event record failed");          \
   } while (0)
 
+// Whether the column-segmented sort of this call also computes step 0's product (weighted graphs:
+// the values pass through the sort anyway).
+int first_in_sort(const ebtc_batch* b, const SpmvPlan& sp) {
+  return sp.form == EBTC_SPMV_SEGMENTED && b->values != nullptr ? 1 : 0;
+}
+
 // Lanczos steps for the launches described by (a, nblocks); a.blkmap / a.single_task select the scope.
 int run_steps(const ebtc_batch* b, const ebtc_opts* o, const LzArgs& a, int64_t nblocks, int64_t first,
               int64_t count, int lanes, hipStream_t s, Prof* prof, bool with_start = true) {
@@ -393,8 +399,9 @@ int run_steps(const ebtc_batch* b, const ebtc_opts* o, const LzArgs& a, int64_t 
   const int steps = o->m > 0 ? o->m : o->m_max;
   if (with_start) EBTC_PHASE(prof, EBTC_PHASE_START, launch_start(b->dtype, a, nblocks, s));
   for (int j = 0; j < steps; ++j) {
-    EBTC_PHASE(prof, j == 0 && a.unit_start ? EBTC_PHASE_FIRST : EBTC_PHASE_SPMV,
-               launch_spmv_step(b->dtype, has_val, lanes, j, a, nblocks, s));
+    if (!(j == 0 && a.unit_start && a.first_in_prepare))
+      EBTC_PHASE(prof, j == 0 && a.unit_start ? EBTC_PHASE_FIRST : EBTC_PHASE_SPMV,
+                 launch_spmv_step(b->dtype, has_val, lanes, j, a, nblocks, s));
     EBTC_PHASE(prof, EBTC_PHASE_DOTS, launch_dots_step(b->dtype, j, a, nblocks, s));
     if (o->reorth == 2) {
       EBTC_PHASE(prof, EBTC_PHASE_UPDATE, launch_update(b->dtype, j, true, false, false, a, nblocks, s));
@@ -448,6 +455,7 @@ int enqueue_batched(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L
                     void* ckpt, ebtc_diag* diag, const SpmvPlan& sp, hipStream_t s, Prof* prof = nullptr) {
   LzArgs a = make_args(b, o, ws, L, sp);
   a.unit_start = 1;  // k_start (and k_restart) set v_0 = 1
+  a.first_in_prepare = first_in_sort(b, sp);
   a.diag = diag;
   EBTC_LAUNCH(launch_blkmap(a.tasks, b->R, (int32_t*)(ws + L.off_blkmap), s));
   int rc = enqueue_prepare(b, sp, a, L.total_blocks, s, prof);
@@ -473,6 +481,7 @@ int enqueue_plain(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, 
                   void* ckpt, ebtc_diag* diag, const SpmvPlan& sp, hipStream_t s) {
   LzArgs a = make_args(b, o, ws, L, sp);
   a.unit_start = 1;
+  a.first_in_prepare = first_in_sort(b, sp);
   a.blkmap = nullptr;
   a.diag = diag;
   for (int64_t r = 0; r < b->R; ++r) {
@@ -921,6 +930,7 @@ int ebtc_scores_backward(ebtc_batch* b, const ebtc_opts* o, const double* log_sc
   // 1. forward recomputation (same kernels and order as ebtc_scores: bitwise the same basis)
   LzArgs fa = make_args(b, o, w, B.fwd, sp);
   fa.unit_start = 1;
+  fa.first_in_prepare = first_in_sort(b, sp);
   EBTC_LAUNCH(launch_blkmap(fa.tasks, b->R, (int32_t*)(w + B.fwd.off_blkmap), s));
   rc = enqueue_prepare(b, sp, fa, B.fwd.total_blocks, s, nullptr);  // the sorted entries serve both solves
   if (rc) return rc;
@@ -931,6 +941,7 @@ int ebtc_scores_backward(ebtc_batch* b, const ebtc_opts* o, const double* log_sc
   // 2. adjoint Lanczos started at the cotangent (shares W and the partial-sum arenas)
   LzArgs aa = fa;
   aa.unit_start = 0;  // started at the cotangent
+  aa.first_in_prepare = 0;
   aa.state = (RState*)(w + B.off_astate);
   aa.V = w + B.off_aV;
   EBTC_LAUNCH(launch_start_vec(b->dtype, aa, (const GraphInfo*)(w + B.fwd.off_graphs), grad_scores,

@@ -142,6 +142,8 @@ struct LzArgs {
   int32_t window;
   int32_t stop_mused;      // second pass of the memory-bounded form: steps j >= m_used - 1 are skipped
   int32_t unit_start;      // 1: v_0 is the raw all-ones vector, so step 0's product is A's row sums
+  int32_t first_in_prepare;  // 1: the column-segmented sort also writes step 0's product (weighted
+                             // graphs), so the step sequence launches none for it
 };
 
 // Slot of basis vector i in a realization's V block.

@@ -667,6 +667,20 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
   const int e0 = rp_lds[0];
   const int nz = rp_lds[rows] - e0;
   SegBlock* desc = a.seg_blk + blk;
+  // Step 0's product from the all-ones start, when the caller has it computed here rather than in a
+  // launch of its own (the values pass through this kernel anyway): each row's values added in entry
+  // order in FP64 and scaled by s_0 = 1/sqrt(n), as the row-sum kernel does.
+  const bool first = HAS_VAL && a.first_in_prepare;
+  T* w0 = (T*)a.W + tk.w_off + r0;
+  const double s0 = 1.0 / sqrt((double)n);
+  auto direct_sums = [&](const T* v) {  // a block the sort does not take: rows from memory (v[rp_lds[r]])
+    if (!first) return;
+    for (int r = tid; r < rows; r += NT) {
+      double acc = 0.0;
+      for (int k = rp_lds[r]; k < rp_lds[r + 1]; ++k) acc += (double)v[k];
+      w0[r] = (T)(acc * s0);
+    }
+  };
   auto finish = [&](int f) {  // the block's flag and descriptor (band starts written by the caller)
     if (tid == 0) {
       a.seg_flag[blk] = f;
@@ -679,6 +693,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
     }
   };
   if (nz > 65535 || S > kSegMax) {  // offsets must fit 16 bits
+    direct_sums(HAS_VAL ? (const T*)a.values + tk.nnz_off : nullptr);
     finish(0);
     return;
   }
@@ -706,6 +721,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
                                     }
                                   });
   if (bad) {
+    direct_sums(va);
     finish(0);
     return;
   }
@@ -741,6 +757,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
   }
   __syncthreads();
   if (bad) {
+    direct_sums(va);
     finish(0);
     return;
   }
@@ -748,14 +765,19 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
   T* pv = HAS_VAL ? (T*)a.seg_val + tk.nnz_off + e0 : nullptr;
   for_rows_staged<T, HAS_VAL, NT>(ci, va, rp_lds, rows, cap, lci, lva,
                                   [&](int r, const int* cs, const T* vs, int k, int e) {
+                                    double acc = 0.0;
                                     for (; k < e; ++k) {
                                       const int c = cs[k];
                                       const int sg = c / SEG;
                                       const int pos = cnt[sg * rows + r];
                                       cnt[sg * rows + r] = (uint16_t)(pos + 1);
                                       pc[pos] = (uint16_t)(c - sg * SEG);
-                                      if constexpr (HAS_VAL) pv[pos] = vs[k];
+                                      if constexpr (HAS_VAL) {
+                                        pv[pos] = vs[k];
+                                        acc += (double)vs[k];
+                                      }
                                     }
+                                    if (first) w0[r] = (T)(acc * s0);
                                   });
   finish(1);
 }
