@@ -30,7 +30,7 @@ namespace {
 template <typename T, int P, int NT, int RING>
 __device__ inline void block_dots(const T* __restrict__ Vr, int n, int lo, int j, int r0, int r1,
                                   const T* wsrc_lds, const T* wsrc_glob, T* wstore, double* part_blk, double* red) {
-  static_assert(P == 2 || P == 32 || P == 64, "lane layout of ReduceScatter");
+  static_assert(P == 2 || P == 8 || P == 32 || P == 64, "lane layout of ReduceScatter");
   constexpr int RPT = kRowsPerBlock / NT;
   constexpr int CH = P < 8 ? P : 8;
   const int tid = threadIdx.x, cnt = j - lo + 1;
@@ -78,10 +78,12 @@ __device__ inline void block_dots(const T* __restrict__ Vr, int n, int lo, int j
 __device__ inline int window_lo(const LzArgs& a, int j) { return a.window > 0 ? max(0, j - a.window + 1) : 0; }
 
 // Workgroup size of the step's dot partials for windows of P vectors of es-byte elements: the
-// two-vector ring and FP32 windows of up to 32 vectors take kDotsThreads (two rows per thread, 64
-// registers, eight waves per SIMD); the rest 256 threads (their accumulators need the registers).
+// two-vector ring, windows of up to 8 vectors and FP32 windows of up to 32 take kDotsThreads (two
+// rows per thread, 64 registers, eight waves per SIMD); the rest 256 threads (their accumulators need
+// the registers). The first eight steps use the 8-vector window: a 32-vector one would reduce and
+// store 32 partials per workgroup for one to eight dots.
 __host__ __device__ constexpr int dots_threads(int P, int es) {
-  return (P <= 2 || (es == 4 && P <= 32)) ? kDotsThreads : kBlock;
+  return (P <= 8 || (es == 4 && P <= 32)) ? kDotsThreads : kBlock;
 }
 
 // k_dots_step: dot partials of w (written by the SpMV) against the window of Vraw_0..j.
@@ -419,6 +421,8 @@ hipError_t launch_accum(int dtype, const LzArgs& a, int j, int64_t nb, hipStream
     if (a.window > 0) {                                                                  \
       if (a.window != 2) return hipErrorInvalidValue;                                    \
       hipLaunchKernelGGL((KERNEL<T, 2, 3>), g, b, 0, s, __VA_ARGS__);                    \
+    } else if (window_count(a, j) <= 8) {                                                \
+      hipLaunchKernelGGL((KERNEL<T, 8, 0>), g, b, 0, s, __VA_ARGS__);                    \
     } else if (window_count(a, j) <= 32) {                                               \
       hipLaunchKernelGGL((KERNEL<T, 32, 0>), g, b, 0, s, __VA_ARGS__);                   \
     } else {                                                                             \
@@ -428,7 +432,7 @@ hipError_t launch_accum(int dtype, const LzArgs& a, int j, int64_t nb, hipStream
 
 hipError_t launch_dots_step(int dtype, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
   if (a.window > 0 && a.window != 2) return hipErrorInvalidValue;
-  const int P = a.window > 0 ? 2 : (window_count(a, j) <= 32 ? 32 : 64);
+  const int P = a.window > 0 ? 2 : window_count(a, j) <= 8 ? 8 : (window_count(a, j) <= 32 ? 32 : 64);
   const dim3 g((unsigned)nb), b(dots_threads(P, dtype == EBTC_F64 ? 8 : 4));
   if (dtype == EBTC_F64) EBTC_GS_LAUNCH(k_dots_step, double, a, j);
   else EBTC_GS_LAUNCH(k_dots_step, float, a, j);
