@@ -30,7 +30,7 @@ namespace {
 template <typename T, int P, int NT, int RING>
 __device__ inline void block_dots(const T* __restrict__ Vr, int n, int lo, int j, int r0, int r1,
                                   const T* wsrc_lds, const T* wsrc_glob, T* wstore, double* part_blk, double* red) {
-  static_assert(P == 2 || P == 8 || P == 32 || P == 64, "lane layout of ReduceScatter");
+  static_assert(P == 2 || P == 8 || P == 16 || P == 32 || P == 64, "lane layout of ReduceScatter");
   constexpr int RPT = kRowsPerBlock / NT;
   constexpr int CH = P < 8 ? P : 8;
   const int tid = threadIdx.x, cnt = j - lo + 1;
@@ -80,8 +80,8 @@ __device__ inline int window_lo(const LzArgs& a, int j) { return a.window > 0 ? 
 // Workgroup size of the step's dot partials for windows of P vectors of es-byte elements: the
 // two-vector ring, windows of up to 8 vectors and FP32 windows of up to 32 take kDotsThreads (two
 // rows per thread, 64 registers, eight waves per SIMD); the rest 256 threads (their accumulators need
-// the registers). The first eight steps use the 8-vector window: a 32-vector one would reduce and
-// store 32 partials per workgroup for one to eight dots.
+// the registers). The first steps use windows of 8 and 16 vectors: a 32-vector one would reduce and
+// store 32 partials per workgroup for one to sixteen dots.
 __host__ __device__ constexpr int dots_threads(int P, int es) {
   return (P <= 8 || (es == 4 && P <= 32)) ? kDotsThreads : kBlock;
 }
@@ -423,6 +423,8 @@ hipError_t launch_accum(int dtype, const LzArgs& a, int j, int64_t nb, hipStream
       hipLaunchKernelGGL((KERNEL<T, 2, 3>), g, b, 0, s, __VA_ARGS__);                    \
     } else if (window_count(a, j) <= 8) {                                                \
       hipLaunchKernelGGL((KERNEL<T, 8, 0>), g, b, 0, s, __VA_ARGS__);                    \
+    } else if (window_count(a, j) <= 16) {                                               \
+      hipLaunchKernelGGL((KERNEL<T, 16, 0>), g, b, 0, s, __VA_ARGS__);                   \
     } else if (window_count(a, j) <= 32) {                                               \
       hipLaunchKernelGGL((KERNEL<T, 32, 0>), g, b, 0, s, __VA_ARGS__);                   \
     } else {                                                                             \
@@ -432,7 +434,8 @@ hipError_t launch_accum(int dtype, const LzArgs& a, int j, int64_t nb, hipStream
 
 hipError_t launch_dots_step(int dtype, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
   if (a.window > 0 && a.window != 2) return hipErrorInvalidValue;
-  const int P = a.window > 0 ? 2 : window_count(a, j) <= 8 ? 8 : (window_count(a, j) <= 32 ? 32 : 64);
+  const int wc = window_count(a, j);
+  const int P = a.window > 0 ? 2 : wc <= 8 ? 8 : wc <= 16 ? 16 : (wc <= 32 ? 32 : 64);
   const dim3 g((unsigned)nb), b(dots_threads(P, dtype == EBTC_F64 ? 8 : 4));
   if (dtype == EBTC_F64) EBTC_GS_LAUNCH(k_dots_step, double, a, j);
   else EBTC_GS_LAUNCH(k_dots_step, float, a, j);
