@@ -149,6 +149,18 @@ def load_traffic(kernel_phase: str, alg_bytes_per_launch: float):
     return t.get("hbm_bytes_per_launch", {}).get(kernel_phase)
 
 
+def gpu_clocks():
+    """Clock levels of GPU 0 as rocm-smi reports them when called (before the run: the idle levels; the
+    clocks are not pinned and rise under load), or None."""
+    import subprocess
+    try:
+        out = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
+        card = next(iter(json.loads(out.stdout).values()))
+        return {k.rstrip(":"): v for k, v in card.items() if "clock" in k.lower()}
+    except Exception:  # no rocm-smi, no card, or output not JSON: the report just omits the clocks
+        return None
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +190,8 @@ def main() -> int:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (realizations and graphs "
               "are independent, so several GPUs would shard them; this benchmark runs on one GPU).", file=sys.stderr)
         return 2
+
+    clocks = gpu_clocks()  # read before this process touches the GPU
 
     import numpy as np
     import torch
@@ -245,19 +259,22 @@ def main() -> int:
         step(run)
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} done")
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
+    evs[0].record()
+    for i in range(args.steps):
         step(run)
-    ev1.record()
+        evs[i + 1].record()  # per-step spread from the events between steps
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
+    gpu_ms = evs[0].elapsed_time(evs[-1])
+    per_step = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+    q1, med, q3 = (float(x) for x in np.percentile(per_step, [25, 50, 75]))
     ms_per_step = 1000.0 * wall / args.steps
     value = hb.R * args.steps / wall
-    log(f"batched: {ms_per_step:.3f} ms/step, {value:.1f} realizations/s (events {gpu_ms / args.steps:.3f} ms/step)")
+    log(f"batched: {ms_per_step:.3f} ms/step, {value:.1f} realizations/s (events {gpu_ms / args.steps:.3f} ms/step; "
+        f"per step median {med:.3f}, IQR {q1:.3f}-{q3:.3f})")
     gpu_scores = run.scores.double().cpu().numpy()
     gpu_ls = run.log_scale.cpu().numpy()
 
@@ -371,6 +388,8 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
+        "step_ms_events": {"median": round(med, 4), "q1": round(q1, 4), "q3": round(q3, 4), "n": args.steps},
+        "gpu_clocks_before_run": clocks,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
