@@ -192,45 +192,53 @@ __global__ __launch_bounds__(kBlock) void k_block_exp(const RState* fwd, const R
   }
 }
 
-// Node-major Z[i][b] = sum_a Wraw_a[i] X'[a][b] and Vn[i][b] = s_b Vraw_b[i] (b < k1), stride ld.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_build_zv(LzArgs fwd, LzArgs adj, const double* xall, T* Z, T* Vn,
-                                                     int ld) {
-  __shared__ double X[kMLimit * kMLimit];
-  __shared__ double sb[kMLimit];
+// Node-major Z[i][b] = sum_a Wraw_a[i] X'[a][b] and Vn[i][b] = s_b Vraw_b[i] (b < k1), stride LD.
+// One thread per row and all LD columns at once, so the adjoint basis is read once (eight of its
+// elements in flight per thread); each sum still runs over a = 0..k2-1 in order from 0. Outputs leave
+// as 16-byte stores (LD is a multiple of 8 and every realization's part starts at a multiple of LD
+// elements).
+template <typename T, int LD>
+__global__ __launch_bounds__(kBlock) void k_build_zv(LzArgs fwd, LzArgs adj, const double* xall, T* Z, T* Vn) {
+  static_assert(LD % 8 == 0 && LD <= kMX, "column chunks of eight");
+  __shared__ double X[LD * LD];
+  __shared__ double sb[LD];
   const Ref ref = resolve(fwd);
   const Task tk = fwd.tasks[ref.task];
   const RState* f = fwd.state + ref.task;
   const RState* q = adj.state + ref.task;
-  const int k1 = f->m_used, k2 = q->m_used;
+  const int k1 = f->m_used, k2 = min(q->m_used, LD);
   const double* xr = xall + (size_t)ref.task * kMLimit * kMLimit;
-  for (int e = threadIdx.x; e < kMLimit * kMLimit; e += kBlock) X[e] = xr[e];
-  if ((int)threadIdx.x < kMLimit) sb[threadIdx.x] = (int)threadIdx.x < k1 ? f->s[threadIdx.x] : 0.0;
+  for (int e = threadIdx.x; e < LD * LD; e += kBlock) X[e] = xr[(e / LD) * kMLimit + e % LD];
+  if ((int)threadIdx.x < LD) sb[threadIdx.x] = (int)threadIdx.x < k1 ? f->s[threadIdx.x] : 0.0;
   __syncthreads();
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
   const T* Vr = (const T*)fwd.V + tk.vec_off;
   const T* Wr = (const T*)adj.V + tk.vec_off;
-  T* Zr = Z + tk.w_off * (int64_t)ld;
-  T* Vnr = Vn + tk.w_off * (int64_t)ld;
-  constexpr int CH = 8;  // output columns per pass (bounds the accumulator registers)
+  T* Zr = Z + tk.w_off * (int64_t)LD;
+  T* Vnr = Vn + tk.w_off * (int64_t)LD;
+  using V4 = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+  constexpr int PER = 16 / sizeof(T);  // elements per 16-byte store
   for (int i = r0 + (int)threadIdx.x; i < r1; i += kBlock) {
-    for (int b0 = 0; b0 < ld; b0 += CH) {
-      double acc[CH];
+    double acc[LD];
 #pragma unroll
-      for (int c = 0; c < CH; ++c) acc[c] = 0.0;
-      for (int aa = 0; aa < k2; ++aa) {
-        const double w = (double)Wr[(size_t)aa * n + i];
+    for (int c = 0; c < LD; ++c) acc[c] = 0.0;
+#pragma unroll 8
+    for (int a = 0; a < k2; ++a) {
+      const double wa = (double)Wr[(size_t)a * n + i];
 #pragma unroll
-        for (int c = 0; c < CH; ++c) acc[c] += w * X[aa * kMLimit + b0 + c];
-      }
+      for (int c = 0; c < LD; ++c) acc[c] += wa * X[a * LD + c];
+    }
 #pragma unroll
-      for (int c = 0; c < CH; ++c) {
+    for (int b0 = 0; b0 < LD; b0 += PER) {
+      T zo[PER], vo[PER];
+#pragma unroll
+      for (int c = 0; c < PER; ++c) {
         const int b = b0 + c;
-        if (b < ld) {
-          Zr[(size_t)i * ld + b] = (T)acc[c];
-          Vnr[(size_t)i * ld + b] = b < k1 ? (T)(sb[b] * (double)Vr[(size_t)b * n + i]) : (T)0;
-        }
+        zo[c] = (T)acc[b];
+        vo[c] = b < k1 ? (T)(sb[b] * (double)Vr[(size_t)b * n + i]) : (T)0;
       }
+      *(V4*)(Zr + (size_t)i * LD + b0) = *(const V4*)zo;
+      *(V4*)(Vnr + (size_t)i * LD + b0) = *(const V4*)vo;
     }
   }
 }
@@ -262,6 +270,21 @@ __global__ __launch_bounds__(kBlock) void k_sddmm(LzArgs fwd, const T* Z, const 
       gr[k] = (T)s;
     }
   }
+}
+
+template <typename T>
+hipError_t build_zv_ld(int ld, const LzArgs& fwd, const LzArgs& adj, const double* x, void* Z, void* Vn, int64_t nb,
+                       hipStream_t s) {
+  const dim3 g((unsigned)nb), b(kBlock);
+  switch (ld) {
+    case 8: hipLaunchKernelGGL((k_build_zv<T, 8>), g, b, 0, s, fwd, adj, x, (T*)Z, (T*)Vn); break;
+    case 16: hipLaunchKernelGGL((k_build_zv<T, 16>), g, b, 0, s, fwd, adj, x, (T*)Z, (T*)Vn); break;
+    case 24: hipLaunchKernelGGL((k_build_zv<T, 24>), g, b, 0, s, fwd, adj, x, (T*)Z, (T*)Vn); break;
+    case 32: hipLaunchKernelGGL((k_build_zv<T, 32>), g, b, 0, s, fwd, adj, x, (T*)Z, (T*)Vn); break;
+    case 40: hipLaunchKernelGGL((k_build_zv<T, 40>), g, b, 0, s, fwd, adj, x, (T*)Z, (T*)Vn); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -306,13 +329,8 @@ hipError_t launch_block_exp(const RState* fwd, const RState* adj, const Task* ta
 
 hipError_t launch_build_zv(int dtype, const LzArgs& fwd, const LzArgs& adj, const double* x, void* Z, void* Vn,
                            int ld, int64_t nb, hipStream_t s) {
-  if (dtype == EBTC_F64)
-    hipLaunchKernelGGL(k_build_zv<double>, dim3((unsigned)nb), dim3(kBlock), 0, s, fwd, adj, x, (double*)Z,
-                       (double*)Vn, ld);
-  else
-    hipLaunchKernelGGL(k_build_zv<float>, dim3((unsigned)nb), dim3(kBlock), 0, s, fwd, adj, x, (float*)Z, (float*)Vn,
-                       ld);
-  return hipGetLastError();
+  return dtype == EBTC_F64 ? build_zv_ld<double>(ld, fwd, adj, x, Z, Vn, nb, s)
+                           : build_zv_ld<float>(ld, fwd, adj, x, Z, Vn, nb, s);
 }
 
 hipError_t launch_sddmm(int dtype, int ld, const LzArgs& fwd, const void* Z, const void* Vn, void* grad, int64_t nb,
