@@ -222,20 +222,29 @@ __global__ __launch_bounds__(kBlock) void k_build_zv(LzArgs fwd, LzArgs adj, con
     double acc[LD];
 #pragma unroll
     for (int c = 0; c < LD; ++c) acc[c] = 0.0;
-#pragma unroll 8
-    for (int a = 0; a < k2; ++a) {
-      const double wa = (double)Wr[(size_t)a * n + i];
+    for (int a0 = 0; a0 < k2; a0 += 8) {
+      T wv[8];  // eight loads issued before the first use (a guarded load would be waited on at once)
 #pragma unroll
-      for (int c = 0; c < LD; ++c) acc[c] += wa * X[a * LD + c];
+      for (int u = 0; u < 8; ++u) wv[u] = Wr[(size_t)min(a0 + u, k2 - 1) * n + i];  // past k2: unused
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (a0 + u < k2) {
+          const double wa = (double)wv[u];
+#pragma unroll
+          for (int c = 0; c < LD; ++c) acc[c] += wa * X[(a0 + u) * LD + c];
+        }
+      }
     }
 #pragma unroll
     for (int b0 = 0; b0 < LD; b0 += PER) {
       T zo[PER], vo[PER];
 #pragma unroll
+      for (int c = 0; c < PER; ++c) vo[c] = Vr[(size_t)max(min(b0 + c, k1 - 1), 0) * n + i];  // past k1: unused
+#pragma unroll
       for (int c = 0; c < PER; ++c) {
         const int b = b0 + c;
         zo[c] = (T)acc[b];
-        vo[c] = b < k1 ? (T)(sb[b] * (double)Vr[(size_t)b * n + i]) : (T)0;
+        vo[c] = b < k1 ? (T)(sb[b] * (double)vo[c]) : (T)0;
       }
       *(V4*)(Zr + (size_t)i * LD + b0) = *(const V4*)zo;
       *(V4*)(Vnr + (size_t)i * LD + b0) = *(const V4*)vo;
@@ -244,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_build_zv(LzArgs fwd, LzArgs adj, con
 }
 
 // grad[k] = <Z[i, :], Vn[col_k, :]> for every stored entry (i, col_k) of the realization; lane groups
-// of 4 per row, the row's Z kept in registers, one contiguous ld-element gather per entry.
+// of 4 per row, the row's Z kept in registers, one contiguous LD-element gather per entry.
 template <typename T, int LD>
 __global__ __launch_bounds__(kBlock) void k_sddmm(LzArgs fwd, const T* Z, const T* Vn, T* grad) {
   constexpr int L = 4;
@@ -262,12 +271,25 @@ __global__ __launch_bounds__(kBlock) void k_sddmm(LzArgs fwd, const T* Z, const 
 #pragma unroll
     for (int b = 0; b < LD; ++b) z[b] = Zr[(size_t)i * LD + b];
     const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += L) {
-      const T* v = Vnr + (size_t)ci[k] * LD;
-      double s = 0.0;
+    // two of the lane's entries per round (k and k + L), both gathers in flight together
+    for (int k = rp[i] + lane; k < e; k += 2 * L) {
+      const int k1 = k + L < e ? k + L : k;  // the round's second entry (or k again)
+      const T* v0 = Vnr + (size_t)ci[k] * LD;
+      const T* v1 = Vnr + (size_t)ci[k1] * LD;
+      T x0[LD], x1[LD];
 #pragma unroll
-      for (int b = 0; b < LD; ++b) s += (double)z[b] * (double)v[b];
-      gr[k] = (T)s;
+      for (int b = 0; b < LD; ++b) {
+        x0[b] = v0[b];
+        x1[b] = v1[b];
+      }
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int b = 0; b < LD; ++b) {
+        s0 += (double)z[b] * (double)x0[b];
+        s1 += (double)z[b] * (double)x1[b];
+      }
+      gr[k] = (T)s0;
+      if (k1 != k) gr[k1] = (T)s1;
     }
   }
 }
