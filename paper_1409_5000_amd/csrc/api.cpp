@@ -397,17 +397,22 @@ int run_steps(const ebtc_batch* b, const ebtc_opts* o, const LzArgs& a, int64_t 
               int64_t count, int lanes, hipStream_t s, Prof* prof, bool with_start = true) {
   const bool has_val = b->values != nullptr;
   const int steps = o->m > 0 ? o->m : o->m_max;
+  // every realization in one row block: dots and update of a step in one launch (one workgroup each)
+  const bool one_block = b->n_max <= kRowsPerBlock && o->reorth == 1 && a.window == 0;
   if (with_start) EBTC_PHASE(prof, EBTC_PHASE_START, launch_start(b->dtype, a, nblocks, s));
   for (int j = 0; j < steps; ++j) {
     if (!(j == 0 && a.unit_start && a.first_in_prepare))
       EBTC_PHASE(prof, j == 0 && a.unit_start ? EBTC_PHASE_FIRST : EBTC_PHASE_SPMV,
                  launch_spmv_step(b->dtype, has_val, lanes, j, a, nblocks, s));
-    EBTC_PHASE(prof, EBTC_PHASE_DOTS, launch_dots_step(b->dtype, j, a, nblocks, s));
-    if (o->reorth == 2) {
+    if (one_block) {
+      EBTC_PHASE(prof, EBTC_PHASE_DOTS, launch_dots_update_1(b->dtype, j, a, nblocks, s));
+    } else if (o->reorth == 2) {
+      EBTC_PHASE(prof, EBTC_PHASE_DOTS, launch_dots_step(b->dtype, j, a, nblocks, s));
       EBTC_PHASE(prof, EBTC_PHASE_UPDATE, launch_update(b->dtype, j, true, false, false, a, nblocks, s));
       EBTC_PHASE(prof, EBTC_PHASE_DOTS, launch_dots_again(b->dtype, j, a, nblocks, s));
       EBTC_PHASE(prof, EBTC_PHASE_UPDATE, launch_update(b->dtype, j, false, true, true, a, nblocks, s));
     } else {
+      EBTC_PHASE(prof, EBTC_PHASE_DOTS, launch_dots_step(b->dtype, j, a, nblocks, s));
       EBTC_PHASE(prof, EBTC_PHASE_UPDATE, launch_update(b->dtype, j, true, true, false, a, nblocks, s));
     }
     if (o->m == 0)

@@ -167,6 +167,9 @@ hipError_t launch_dots_step(int dtype, int j, const LzArgs& a, int64_t nblocks, 
 hipError_t launch_dots_again(int dtype, int j, const LzArgs& a, int64_t nblocks, hipStream_t s);
 hipError_t launch_update(int dtype, int j, bool from_w, bool final_pass, bool second_pass, const LzArgs& a,
                          int64_t nblocks, hipStream_t s);
+// Dots and update of step j in one launch; every realization must fit one row block (n <= kRowsPerBlock)
+// and the basis window must be the whole basis (one Gram-Schmidt pass).
+hipError_t launch_dots_update_1(int dtype, int j, const LzArgs& a, int64_t nblocks, hipStream_t s);
 hipError_t launch_combine(int dtype, const LzArgs& a, int64_t nblocks, hipStream_t s);
 // Memory-bounded form, second pass: restart from the start vector keeping theta, y, m_used, flags;
 // before step j, u (+)= beta0 y_j s_j Vraw_j (j = 0 assigns) and the realization stops after m_used.

@@ -120,14 +120,10 @@ __global__ __launch_bounds__(kBlock) void k_dots_again(LzArgs a, int j) {
 // then v~_{j+1} = src - sum_i c_i Vraw_i over the window (FP64 accumulation, rounded once), plus
 // the partial squared norm on the final pass.
 template <typename T, int P, int RING>
-__global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, int final_pass, int second) {
-  __shared__ double cs[P];
-  __shared__ double csum[P][kMaxChunks];
-  __shared__ double red[kWaves];
-  const Ref ref = resolve(a);
+__device__ inline void update_body(const LzArgs& a, const Ref& ref, int j, int from_w, int final_pass, int second,
+                                   double* cs, double (*csum)[kMaxChunks], double* red) {
   const Task tk = a.tasks[ref.task];
   RState* st = a.state + ref.task;
-  if (step_skipped(a, st, j)) return;
   constexpr int CH = P < 8 ? P : 8;
   const int tid = threadIdx.x, lo = window_lo(a, j), cnt = j - lo + 1;
   const double* part = a.part + tk.part_off;
@@ -192,6 +188,36 @@ __global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, 
   if (!final_pass) return;
   nrm = block_sum<kBlock>(nrm, red);
   if (tid == 0) a.npart[tk.part_off / kPartStride + ref.blk] = nrm;
+}
+
+template <typename T, int P, int RING>
+__global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, int final_pass, int second) {
+  __shared__ double cs[P];
+  __shared__ double csum[P][kMaxChunks];
+  __shared__ double red[kWaves];
+  const Ref ref = resolve(a);
+  if (step_skipped(a, a.state + ref.task, j)) return;
+  update_body<T, P, RING>(a, ref, j, from_w, final_pass, second, cs, csum, red);
+}
+
+// Dots and update of step j in one launch, for batches whose realizations each fit one row block
+// (n <= kRowsPerBlock, one workgroup per realization): the workgroup's dot partials are then the
+// realization's totals, so the update reads them back after a workgroup barrier instead of after a
+// launch boundary. Same steps as k_dots_step followed by k_update (one Gram-Schmidt pass, full basis).
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_dots_update_1(LzArgs a, int j) {
+  __shared__ double red_d[kWaves * P];
+  __shared__ double cs[P];
+  __shared__ double csum[P][kMaxChunks];
+  __shared__ double red[kWaves];
+  const Ref ref = resolve(a);
+  const Task tk = a.tasks[ref.task];
+  if (step_skipped(a, a.state + ref.task, j)) return;
+  const int n = min(tk.n, kRowsPerBlock);
+  block_dots<T, P, kBlock, 0>((const T*)a.V + tk.vec_off, tk.n, 0, j, 0, n, nullptr, (const T*)a.W + tk.w_off,
+                              nullptr, a.part + tk.part_off, red_d);
+  __syncthreads();  // the partials stored above (global) are read back by other threads of the workgroup
+  update_body<T, P, 0>(a, ref, j, 1, 1, 0, cs, csum, red);
 }
 
 template <typename T>
@@ -455,6 +481,23 @@ hipError_t launch_update(int dtype, int j, bool from_w, bool final_pass, bool se
   const int fw = from_w ? 1 : 0, fp = final_pass ? 1 : 0, sp = second_pass ? 1 : 0;
   if (dtype == EBTC_F64) EBTC_GS_LAUNCH(k_update, double, a, j, fw, fp, sp);
   else EBTC_GS_LAUNCH(k_update, float, a, j, fw, fp, sp);
+  return hipGetLastError();
+}
+
+hipError_t launch_dots_update_1(int dtype, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
+  if (a.window != 0) return hipErrorInvalidValue;
+  const int wc = window_count(a, j);
+  const dim3 g((unsigned)nb), b(kBlock);
+#define EBTC_DU1(T)                                                                            \
+  do {                                                                                         \
+    if (wc <= 8) hipLaunchKernelGGL((k_dots_update_1<T, 8>), g, b, 0, s, a, j);                \
+    else if (wc <= 16) hipLaunchKernelGGL((k_dots_update_1<T, 16>), g, b, 0, s, a, j);         \
+    else if (wc <= 32) hipLaunchKernelGGL((k_dots_update_1<T, 32>), g, b, 0, s, a, j);         \
+    else hipLaunchKernelGGL((k_dots_update_1<T, 64>), g, b, 0, s, a, j);                       \
+  } while (0)
+  if (dtype == EBTC_F64) EBTC_DU1(double);
+  else EBTC_DU1(float);
+#undef EBTC_DU1
   return hipGetLastError();
 }
 
