@@ -51,7 +51,9 @@ enum ebtc_dtype { EBTC_F32 = 0, EBTC_F64 = 1 };
 
 enum ebtc_schedule {
   EBTC_SCHED_AUTO = 0,     /* library picks (batched)                                              */
-  EBTC_SCHED_PLAIN = 1,    /* one realization at a time: about 2m + 4 kernel launches per realization */
+  EBTC_SCHED_PLAIN = 1,    /* one realization at a time: per Lanczos step an SpMV, a Gram-Schmidt dot
+                              and an update launch (dots and update are one launch when every
+                              realization has at most 2048 nodes), plus a few per realization     */
   EBTC_SCHED_BATCHED = 2   /* all realizations of all graphs advance together, one launch per
                               Lanczos phase, optionally replayed from a captured hipGraph          */
 };
