@@ -33,3 +33,14 @@ def random_graph(n, p, seed, weighted=False):
     if weighted:
         U *= rng.uniform(0.5, 1.5, size=(n, n))
     return U + U.T
+
+
+def lollipop(k, tail):
+    """K_k with a path of `tail` further nodes hanging off its last node: the leading eigenvector sits
+    on the clique, far from the uniform start vector of eq. (4)."""
+    n = k + tail
+    A = np.zeros((n, n))
+    A[:k, :k] = 1.0 - np.eye(k)
+    for i in range(k - 1, n - 1):
+        A[i, i + 1] = A[i + 1, i] = 1.0
+    return A

@@ -40,6 +40,14 @@ MUTATIONS = [
     ("dense.py", "return U @ (np.exp(lam) * c)", "return U.T @ (np.exp(lam) * c)"),
     ("taylor.py", "acc = [acc[i] + Fraction(walks[i], fact) for i in range(n)]",
      "acc = [acc[i] + Fraction(walks[i], fact * l) for i in range(n)]"),
+    # Saad's relative estimate: the normalisation dropped, the 1-norm, the first component
+    ("tridiag.py", "return float(beta_last * abs(y[-1]) / ny) if ny > 0 else 0.0",
+     "return float(beta_last * abs(y[-1])) if ny > 0 else 0.0"),
+    ("tridiag.py", "ny = float(np.linalg.norm(y))", "ny = float(np.linalg.norm(y, 1))"),
+    ("tridiag.py", "return float(beta_last * abs(y[-1]) / ny) if ny > 0 else 0.0",
+     "return float(beta_last * abs(y[0]) / ny) if ny > 0 else 0.0"),
+    ("lanczos.py", "est = 0.0 if flags & FLAG_BREAKDOWN else tridiag.saad_estimate(y, beta[k - 1])",
+     "est = 0.0 if flags & FLAG_BREAKDOWN else tridiag.saad_estimate(y, beta[k - 2])"),
 ]
 
 
@@ -121,6 +129,37 @@ def battery(o) -> list[str]:
                                             - o.gradient.frechet_edge(W, g, i, j, symmetric=False)) < 1e-9)
     check("grad-divdiff-vs-frechet", lambda: (lambda G: abs(G[i, j] + G[j, i] - o.gradient.frechet_edge(W, g, i, j)) < 1e-9)(
         o.gradient.grad_divdiff(W, g)))
+
+    # Saad's estimate: P_5 at m = 2 by hand (alpha = 8/5, -4/15; beta = sqrt(6)/5, sqrt(5)/3), the
+    # 2 x 2 exponential in closed form; invariance under A -> A + 3I without the shift; decay with
+    # the true error on a lollipop graph
+    def saad_p5():
+        r = o.lanczos.lanczos_expv(sp.csr_matrix(gs.path(5)), m=2)
+        a0, a1, b0, b1 = 8 / 5, -4 / 15, math.sqrt(6) / 5, math.sqrt(5) / 3
+        mu, d = (a0 + a1) / 2, (a0 - a1) / 2
+        rr = math.hypot(d, b0)
+        y = np.array([math.cosh(rr) + d * math.sinh(rr) / rr, b0 * math.sinh(rr) / rr])
+        return abs(r.est - b1 * abs(y[1]) / np.linalg.norm(y)) < 1e-14
+
+    def saad_relative():
+        L = gs.lollipop(8, 40)
+        e = [o.lanczos.lanczos_expv(sp.csr_matrix(L + c * np.eye(48)), m=8, shift=False).est for c in (0.0, 3.0)]
+        return abs(e[1] - e[0]) < 1e-9 * e[0]
+
+    def saad_decays():
+        L = gs.lollipop(8, 60)
+        ex = sla.expm(L) @ np.ones(68)
+        for m in (4, 8):
+            r = o.lanczos.lanczos_expv(sp.csr_matrix(L), m=m)
+            u = np.exp(r.theta) * r.u
+            err = np.linalg.norm(u - ex) / np.linalg.norm(u)
+            if not (err <= r.est <= 40.0 * err):
+                return False
+        return True
+
+    check("saad-p5-by-hand", saad_p5)
+    check("saad-relative", saad_relative)
+    check("saad-decays", saad_decays)
     return fails
 
 

@@ -260,6 +260,80 @@ def test_adaptive_stop_and_cap():
     assert r_loose.m_used < r.m_used
 
 
+# ------------------------------------------------------------------ Saad's a-posteriori estimate
+
+def p5_lanczos_by_hand():
+    """Two Lanczos steps on the path P_5 from 1/sqrt(5), worked out by hand in exact arithmetic.
+
+    alpha_0 = 1^T A 1 / 5 = 8/5 (twice the 4 edges over 5 nodes). A v_0 - alpha_0 v_0 = (d - 8/5)/sqrt(5)
+    with degrees d = (1,2,2,2,1): (-0.6, 0.4, 0.4, 0.4, -0.6)/sqrt(5), so beta_0 = sqrt(1.2/5) = sqrt(6)/5
+    and v_1 = (-0.6, 0.4, 0.4, 0.4, -0.6)/sqrt(1.2). A v_1 = (0.4, -0.2, 0.8, -0.2, 0.4)/sqrt(1.2), so
+    alpha_1 = -0.32/1.2 = -4/15, and w = A v_1 - alpha_1 v_1 - beta_0 v_0 = (0, -1/3, 2/3, -1/3, 0)/sqrt(1.2)
+    gives beta_1 = sqrt((6/9)/1.2) = sqrt(5)/3.
+    """
+    return (8 / 5, -4 / 15), math.sqrt(6) / 5, math.sqrt(5) / 3
+
+
+def expm2_e1(a, b, c):
+    """exp([[a, b], [b, c]]) e1 in closed form: with mu = (a+c)/2, d = (a-c)/2, r = sqrt(d^2 + b^2),
+    exp(T) = e^mu (cosh(r) I + sinh(r)/r (T - mu I))."""
+    mu, d = (a + c) / 2, (a - c) / 2
+    r = math.hypot(d, b)
+    return math.exp(mu) * np.array([math.cosh(r) + d * math.sinh(r) / r, b * math.sinh(r) / r])
+
+
+def test_saad_estimate_two_by_two_by_hand():
+    """Saad's relative estimate beta_m |e_m^T exp(T_m) e1| / ||exp(T_m) e1||_2 (the stop rule of the
+    adaptive Krylov approximation, text after eq. (4)) on 2 x 2 tridiagonals whose exponential is a
+    closed form, through the oracle's whole Lanczos path (P_5, m = 2) and through the helper alone."""
+    (a0, a1), b0, b1 = p5_lanczos_by_hand()
+    r = lanczos.lanczos_expv(sp.csr_matrix(gs.path(5)), m=2)
+    assert r.m_used == 2 and r.flags == 0
+    assert abs(r.alpha[0] - a0) < 1e-15 and abs(r.alpha[1] - a1) < 1e-15
+    assert abs(r.beta[0] - b0) < 1e-15 and abs(r.beta[1] - b1) < 1e-15
+    y = expm2_e1(a0, b0, a1)
+    est = b1 * abs(y[1]) / math.hypot(y[0], y[1])
+    assert abs(r.est - est) < 1e-14 * est
+    # T = [[1, 2], [2, -2]]: r = 5/2, exp(T) e1 = e^{-1/2} (cosh 2.5 + 0.6 sinh 2.5, 0.8 sinh 2.5)
+    c, s = math.cosh(2.5), math.sinh(2.5)
+    want = 0.5 * 0.8 * s / math.hypot(c + 0.6 * s, 0.8 * s)
+    y2, _ = tridiag.expv_e1([1.0, -2.0], [2.0])
+    assert abs(tridiag.saad_estimate(y2, 0.5) - want) < 1e-15
+    assert abs(want - 0.22209888659244936) < 1e-15
+
+
+def test_saad_estimate_is_relative():
+    """The estimate is a relative error: exp(A + cI) 1 = e^c exp(A) 1 has the same relative error, the
+    same Lanczos basis and T shifted by c, so without the shift (y = exp(T) e1 grows by e^c) the
+    estimate must not change."""
+    for A in (gs.lollipop(8, 40), gs.random_graph(200, 0.04, 21)):
+        n = A.shape[0]
+        e = [lanczos.lanczos_expv(sp.csr_matrix(A + c * np.eye(n)), m=8, shift=False).est for c in (0.0, 3.0)]
+        assert e[0] > 1e-8 and abs(e[1] - e[0]) < 1e-9 * e[0]
+
+
+@pytest.mark.parametrize("name, A", [("lollipop8_60", gs.lollipop(8, 60)), ("er300", gs.random_graph(300, 0.05, 3))])
+def test_saad_estimate_tracks_the_true_error(name, A):
+    """Against the true relative error ||u_m - exp(A) 1|| / ||u_m|| (dense expm): while the error is
+    above rounding, the estimate stays above it and within a factor 40 (the first-term estimate uses
+    exp(T) where the exact error term has (exp(T) - I) T^{-1}, so it runs high by about lambda_max)
+    and falls with it."""
+    n = A.shape[0]
+    ex = sla.expm(A) @ np.ones(n)
+    prev = None
+    for m in range(4, 20, 2):
+        r = lanczos.lanczos_expv(sp.csr_matrix(A), m=m)
+        u = np.exp(r.theta) * r.u
+        err = np.linalg.norm(u - ex) / np.linalg.norm(u)
+        if err < 1e-10:
+            break
+        assert err <= r.est <= 40.0 * err, (name, m, err, r.est)
+        if prev is not None:
+            assert r.est < 0.2 * prev
+        prev = r.est
+    assert prev is not None
+
+
 # ------------------------------------------------------------------ subgraph centrality (Gauss rule)
 
 def test_gauss_subgraph_centrality_exact_when_the_krylov_space_closes():
