@@ -77,9 +77,40 @@ def run_gpu(hb, **kw):
     return b, out
 
 
-def check_against_oracle(hb, out, b, m, tol_key, K=None, tol=0.0, m_max=60, reorth_ref=2, check_m=True, workers=1):
+# Diagnostics bars. theta*: FP64 1e-12, FP32 1e-5, relative to max(1, |theta*|) (in FP32 the Ritz value
+# carries the data's rounding, and a theta* error moves the scaled scores by the same relative amount).
+# Saad's estimate beta |y_m| / ||y||: y_m is the small tail of y, accurate only to a few ulps of ||y||
+# = O(1), hence an absolute floor proportional to the last beta next to the relative term.
+DIAG_TOL = {"f64": dict(theta=1e-12, est_rel=1e-6, est_abs=1e-12),
+            "f32": dict(theta=1e-5, est_rel=1e-4, est_abs=1e-6)}
+
+
+def check_diag(diag, r0, gsc, tol_key, check_m=True, check_est=True):
+    """Per realization of one graph: m_used (exact when check_m is True), flags (exact where m_used
+    agrees), theta* and Saad's estimate against the oracle's GraphScores gsc."""
+    t = DIAG_TOL[tol_key]
+    R_g = gsc.m_used.size
+    m_gpu = diag["m_used"][r0:r0 + R_g]
+    fl = diag["flags"][r0:r0 + R_g]
+    th = diag["theta"][r0:r0 + R_g]
+    es = diag["est"][r0:r0 + R_g]
+    if check_m is True:
+        assert np.array_equal(m_gpu, gsc.m_used), (m_gpu, gsc.m_used)
+    same = m_gpu == gsc.m_used
+    assert np.array_equal(fl[same], gsc.flags[same]), (fl, gsc.flags)
+    assert np.all(np.abs(th - gsc.thetas) <= t["theta"] * np.maximum(1.0, np.abs(gsc.thetas))), (th, gsc.thetas)
+    if check_est:
+        for k in np.flatnonzero(same):
+            bl = float(gsc.beta[k][-1])
+            assert abs(es[k] - gsc.est[k]) <= t["est_rel"] * gsc.est[k] + t["est_abs"] * max(1.0, bl), \
+                (k, es[k], gsc.est[k], bl)
+
+
+def check_against_oracle(hb, out, b, m, tol_key, K=None, tol=0.0, m_max=60, reorth_ref=2, check_m=True, workers=1,
+                         check_est=True):
     """Scores against the oracle per graph; check_m: True = equal m_used, False = within one step,
-    None = not compared (a different recurrence that stops elsewhere)."""
+    None = not compared (a different recurrence that stops elsewhere). Flags, theta* and the estimate
+    are compared wherever m_used agrees (check_est=False skips the estimate)."""
     ref = oscores.batch_scores(hb, m=m, tol=tol, m_max=m_max, reorth=reorth_ref, workers=workers)
     s_all = out.scores.double().cpu().numpy()
     ls = out.log_scale.cpu().numpy()
@@ -99,6 +130,8 @@ def check_against_oracle(hb, out, b, m, tol_key, K=None, tol=0.0, m_max=60, reor
             assert np.array_equal(m_gpu, gsc.m_used), (m_gpu, gsc.m_used)
         elif check_m is not None:
             assert np.max(np.abs(m_gpu - gsc.m_used)) <= 1
+        if check_m is not None:
+            check_diag(diag, r0, gsc, tol_key, check_m=check_m, check_est=check_est)
         r0 += R_g
     return ref, report
 
@@ -354,6 +387,43 @@ def test_adaptive_mode_fp32(gpu_lib):
     check_against_oracle(hb, out, b, 0, "f32", K=20, tol=1e-6, m_max=60, check_m=False)
     d = out.diag_numpy()
     assert np.all(d["est"] < 1e-6) or np.any(d["flags"] & 2)
+
+
+@pytest.mark.parametrize("m_max", [2, 3, 5])
+def test_cap_and_diagnostics_fp64(gpu_lib, m_max):
+    # adaptive mode with a tolerance no Krylov space this small meets: every realization that does not
+    # break down must stop at the cap with CAPPED; the star (closes after two steps) and the cycle
+    # (after one) must report BREAKDOWN instead. m_used, flags, theta* and the estimate per realization
+    # against the oracle; scores at 1e-12
+    w = C.scaled(C.workload(0), N=4)
+    hb0 = C.build(w)
+    mats = [odense.csr_to_scipy(*hb0.csr(r)).toarray() for r in range(hb0.R)]
+    hb = DenseBatch([mats, [gs.bipartite(1, 150)], [gs.cycle(300)]], "f64")
+    b, out = run_gpu(hb, m=0, tol=1e-12, m_max=m_max)
+    ref, _ = check_against_oracle(hb, out, b, 0, "f64", K=10, tol=1e-12, m_max=m_max)
+    d = out.diag_numpy()
+    assert np.all(d["m_used"][:4] == m_max) and np.all(d["flags"][:4] == 2)  # CAPPED
+    assert np.all(d["est"][:4] > 1e-12)
+    assert d["m_used"][4] == min(2, m_max) and d["m_used"][5] == 1
+    assert d["flags"][5] == 1 and d["est"][5] == 0.0                         # BREAKDOWN
+    assert d["flags"][4] == 1
+
+
+@pytest.mark.parametrize("m_max", [2, 3, 5])
+def test_cap_and_diagnostics_fp32_uneven(gpu_lib, m_max):
+    # the uneven workload's families (ER, BA, WS with cliques or sparse targets) at reduced n, FP32
+    import dataclasses
+    w = C.workload(4)
+    pick = [s for f in ("er", "ba", "ws") for s in [t for t in w.graphs if t.family == f][:2]]
+    w = dataclasses.replace(w, graphs=tuple(dataclasses.replace(s, n=3000 + 517 * i, N=2,
+                                                                bg=(s.bg * (s.n - 1) / (2999 + 517 * i)
+                                                                    if s.family == "er" else s.bg))
+                                            for i, s in enumerate(pick)))
+    hb = C.build(w)
+    b, out = run_gpu(hb, m=0, tol=1e-12, m_max=m_max)
+    check_against_oracle(hb, out, b, 0, "f32", K=20, tol=1e-12, m_max=m_max)
+    d = out.diag_numpy()
+    assert np.all(d["m_used"] == m_max) and np.all(d["flags"] == 2)
 
 
 def test_reorth_two_passes(gpu_lib):
