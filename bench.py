@@ -2,17 +2,22 @@
 """Throughput of the Krylov exp(A)·1 communicability path on one MI355X.
 
 One step = the whole hot path over one batch already resident in HBM: all Lanczos solves of every
-realization (batched schedule, replayed hipGraph), the realization sum with per-graph log-scale and
-the top-K selection. Default workload: ER n=1e5, degree 20, 64 realizations, 50-node target, FP32,
-m=30 (the batched-realizations configuration).
+realization (automatic schedule -- one launch per phase over all realizations, or one launch for every
+realization's whole process when all graphs fit one 2048-row block -- replayed from a hipGraph), the
+realization sum with per-graph log-scale and the top-K selection. Default workload: ER n=1e5,
+degree 20, 64 realizations, 50-node target, FP32, m=30 (the batched-realizations configuration).
 
 Prints ONE JSON line on stdout (progress goes to stderr):
   value          graph-realizations/s (batched form), whole job on one GPU
   plain          the per-realization loop on the same batch, and the batched/plain factor
-  roofline       dominant kernel (SpMV + dot partials): algorithmic bytes per launch / average launch
-                 time, both measured live with HIP events on the launch stream, against 8 TB/s
-  cpu_baseline   the FP64 oracle timed on this host's cores over the same workload
+  roofline       dominant kernel: algorithmic bytes per launch / average launch time, both measured
+                 live with HIP events on the launch stream, against 8 TB/s; also the measured rate of
+                 a 1 GiB device-to-device copy and the kernel's fraction of it
+  cpu_baseline   the FP64 oracle timed on this host's cores over the same workload (CPU model,
+                 affinity count, and the same oracle on one core over a few realizations)
   parity         GPU scores vs the oracle (normwise and top-2K error, top-K set match)
+Under a profiler (rocprofv3) nothing forks: the realizations are generated in this process and the
+CPU baseline is skipped.
 
     python bench.py [--steps K] [--warmup W] [--config 1] [--gpus 1]
 """
@@ -150,15 +155,60 @@ def load_traffic(kernel_phase: str, alg_bytes_per_launch: float):
 
 
 def gpu_clocks():
-    """Clock levels of GPU 0 as rocm-smi reports them when called (before the run: the idle levels; the
-    clocks are not pinned and rise under load), or None."""
-    import subprocess
+    """Current clock levels of the first AMD GPU from sysfs (the lines marked '*' of pp_dpm_sclk and
+    pp_dpm_mclk: the idle levels before the run, since the clocks are not pinned and rise under load),
+    or None where sysfs does not show them."""
+    import glob
+    for dev in sorted(glob.glob("/sys/class/drm/card*/device")):
+        try:
+            with open(os.path.join(dev, "vendor")) as f:
+                if f.read().strip() != "0x1002":
+                    continue
+            out = {}
+            for name in ("pp_dpm_sclk", "pp_dpm_mclk"):
+                with open(os.path.join(dev, name)) as f:
+                    cur = [ln.strip() for ln in f if ln.strip().endswith("*")]
+                out[name] = cur[0] if cur else None
+            return out
+        except OSError:
+            continue
+    return None
+
+
+def under_profiler() -> bool:
+    """True when a profiler's library is preloaded (rocprofv3): the GPU is then initialised before this
+    process starts, so it must not fork worker processes."""
+    return "rocprof" in os.environ.get("LD_PRELOAD", "") or any(k.startswith("ROCPROF") for k in os.environ)
+
+
+def cpu_model() -> str | None:
     try:
-        out = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
-        card = next(iter(json.loads(out.stdout).values()))
-        return {k.rstrip(":"): v for k, v in card.items() if "clock" in k.lower()}
-    except Exception:  # no rocm-smi, no card, or output not JSON: the report just omits the clocks
-        return None
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def copy_bandwidth(torch, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Device-to-device copy rate in GB/s (bytes read + bytes written), median of `reps` copies of
+    nbytes each: the achievable HBM bandwidth this benchmark's kernels are compared against."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (float(np.median(times)) * 1e-3) / 1e9
 
 
 def main() -> int:
@@ -191,7 +241,8 @@ def main() -> int:
               "are independent, so several GPUs would shard them; this benchmark runs on one GPU).", file=sys.stderr)
         return 2
 
-    clocks = gpu_clocks()  # read before this process touches the GPU
+    clocks = gpu_clocks()
+    profiled = under_profiler()
 
     import numpy as np
     import torch
@@ -203,11 +254,14 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     try:
-        P = len(os.sched_getaffinity(0))
+        affinity = len(os.sched_getaffinity(0))
     except AttributeError:
-        P = os.cpu_count() or 1
-    P = min(P, 16)
+        affinity = os.cpu_count() or 1
+    P = min(affinity, 16)  # a one-GPU machine's share of the host: 16 cores
     workers = args.workers or P
+    if profiled:  # no worker processes from a process whose GPU is already initialised
+        workers = 1
+        log("profiler detected: generation in this process, no CPU baseline")
 
     w = C.workload(args.config)
     t0 = time.time()
@@ -243,13 +297,14 @@ def main() -> int:
         dst = torch.empty_like(src)
         dst.copy_(src)  # reads and writes exactly 1 GiB
         torch.cuda.synchronize()
-        rr = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=False, diag=False, **form)
+        rr = b.run(m=m, tol=tol, m_max=m_max, schedule="auto", hipgraph=False, diag=False, **form)
         ph = rr.profile()
         torch.cuda.synchronize()
         print(json.dumps({"profile_run": w.name, "realizations": hb.R, "spmv_form": tuned or form, "phases": ph}),
               flush=True)
         return 0
-    run = b.run(m=m, tol=tol, m_max=m_max, schedule="batched", hipgraph=True, diag=True, **form)
+    # auto: the single-kernel schedule when every graph fits one row block, else one launch per phase
+    run = b.run(m=m, tol=tol, m_max=m_max, schedule="auto", hipgraph=True, diag=True, **form)
 
     def step(r):
         out = r.launch()
@@ -366,16 +421,18 @@ def main() -> int:
                     sp_bytes += spmv_bytes(n, z, es, has_val)
                 dt_bytes += passes * dots_bytes(n, jj, es)
                 up_bytes += passes * update_bytes(n, jj, es)
+    cb_bytes = sum(combine_bytes(int(hb.n[hb.graph_of[r]]), int(m_used[r]), es) for r in range(hb.R))
     alg = {"spmv": sp_bytes, "dots": dt_bytes, "update": up_bytes, "first": fs_bytes}
-    if phases["dots"][1] == 0:  # vector staged in LDS: SpMV and dots are one kernel (w read counted once extra)
+    if phases["solve"][1] > 0:  # single-kernel schedule: every phase in one launch
+        alg = {"solve": sp_bytes + fs_bytes + dt_bytes + up_bytes + cb_bytes}
+    elif phases["dots"][1] == 0:  # vector staged in LDS: SpMV and dots are one kernel (w read counted once extra)
         alg = {"spmv": sp_bytes + dt_bytes, "update": up_bytes, "first": fs_bytes}
     dominant = max(alg, key=lambda p: phases[p][0])
     dom_ms, dom_launches = phases[dominant]
     achieved = alg[dominant] / (dom_ms * 1e-3) / 1e9
     per_launch = alg[dominant] / max(1, dom_launches)
     traffic = load_traffic(dominant, per_launch)
-    total_alg = sp_bytes + dt_bytes + up_bytes + sum(
-        combine_bytes(int(hb.n[hb.graph_of[r]]), int(m_used[r]), es) for r in range(hb.R))
+    total_alg = sp_bytes + fs_bytes + dt_bytes + up_bytes + cb_bytes
     log("phases (ms, launches): " + ", ".join(f"{p}={v[0]:.3f}/{v[1]}" for p, v in phases.items()))
     log("algorithmic GB/s: " + ", ".join(f"{p}={alg[p] / (phases[p][0] * 1e-3) / 1e9:.0f}" for p in alg
                                          if phases[p][0] > 0))
@@ -400,7 +457,8 @@ def main() -> int:
         "config": {"workload": w.name, "graphs": int(hb.n.size), "realizations": hb.R,
                    "n": [int(x) for x in hb.n], "nnz_total": int(hb.nnz_off[-1]), "m": m,
                    "adaptive_tol": w.tol if m == 0 else None, "reorth": args.reorth, "K": [int(x) for x in K[:4]],
-                   "schedule": "batched, hipGraph replay", "parallelism": "1 GPU",
+                   "schedule": ("single kernel" if phases["solve"][1] > 0 else "batched") + ", hipGraph replay",
+                   "parallelism": "1 GPU",
                    "spmv_form": tuned if tuned is not None else form},
         "plain": plain,
         "effective_GBps_whole_path": round(total_alg * args.steps / wall / 1e9, 1),
@@ -416,7 +474,12 @@ def main() -> int:
     if adjoint is not None:
         result["adjoint"] = adjoint
 
-    if not args.no_cpu_baseline:
+    copy_gbs = copy_bandwidth(torch)
+    result["roofline"]["copy_GBps_measured"] = round(copy_gbs, 1)
+    result["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    log(f"device copy {copy_gbs:.0f} GB/s; dominant kernel {achieved:.0f} GB/s")
+
+    if not args.no_cpu_baseline and not profiled:
         from oracle import scores as oscores
         G_or = args.oracle_graphs or int(hb.n.size)
         reals = [r for r in range(hb.R) if int(hb.graph_of[r]) < G_or]
@@ -426,10 +489,19 @@ def main() -> int:
         ref = oscores.batch_scores(hb, m=m, tol=w.tol, m_max=m_max, workers=P, realizations=reals)
         cpu_wall = time.perf_counter() - t0
         what = f"all {hb.R} realizations" if len(reals) == hb.R else f"the {len(reals)} realizations of the first {G_or} graphs"
+        # the same oracle on one core, over the first few realizations of the sample
+        one = reals[:max(1, min(len(reals), 4))]
+        t1 = time.perf_counter()
+        oscores.batch_scores(hb, m=m, tol=w.tol, m_max=m_max, workers=1, realizations=one)
+        one_wall = time.perf_counter() - t1
         result["cpu_baseline"] = {"value": round(len(reals) / cpu_wall, 3), "unit": "graph-realizations/s",
                                   "cores": P, "kind": "oracle",
                                   "sample": f"{what} of {w.name}, FP64 Lanczos (CGS2), "
-                                            f"{P} single-threaded worker processes, {cpu_wall:.1f}s wall"}
+                                            f"{P} single-threaded worker processes, {cpu_wall:.1f}s wall",
+                                  "cpu_model": cpu_model(), "affinity_cpus": affinity,
+                                  "one_core": {"value": round(len(one) / one_wall, 3),
+                                               "sample": f"{len(one)} realizations in one process, "
+                                                         f"{one_wall:.2f}s"}}
         errs = []
         top_ok = True
         idx_all, _ = b.topk(run.scores, K)

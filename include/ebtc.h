@@ -35,7 +35,7 @@ extern "C" {
 
 #define EBTC_VERSION_MAJOR 0
 #define EBTC_VERSION_MINOR 1
-#define EBTC_M_LIMIT 64      /* largest Krylov dimension (fixed m or adaptive cap) */
+#define EBTC_M_LIMIT 128     /* largest Krylov dimension (fixed m or adaptive cap) */
 #define EBTC_TOPK_LIMIT 4096 /* largest K per graph in ebtc_topk */
 
 enum ebtc_status {
@@ -50,12 +50,18 @@ enum ebtc_status {
 enum ebtc_dtype { EBTC_F32 = 0, EBTC_F64 = 1 };
 
 enum ebtc_schedule {
-  EBTC_SCHED_AUTO = 0,     /* library picks (batched)                                              */
+  EBTC_SCHED_AUTO = 0,     /* library picks: SINGLE when the batch allows it, else BATCHED         */
   EBTC_SCHED_PLAIN = 1,    /* one realization at a time: per Lanczos step an SpMV, a Gram-Schmidt dot
                               and an update launch (dots and update are one launch when every
                               realization has at most 2048 nodes), plus a few per realization     */
-  EBTC_SCHED_BATCHED = 2   /* all realizations of all graphs advance together, one launch per
+  EBTC_SCHED_BATCHED = 2,  /* all realizations of all graphs advance together, one launch per
                               Lanczos phase, optionally replayed from a captured hipGraph          */
+  EBTC_SCHED_SINGLE = 3    /* all realizations in one launch, one workgroup running each
+                              realization's whole Lanczos process (then one launch for the sum):
+                              needs every n_g <= 2048, m (adaptive: m_max) <= 64, reorth = 1 and
+                              the SpMV form AUTO, STREAM, SEGMENTED or BALANCED
+                              (EBTC_ENOTSUPPORTED otherwise). Same results as BATCHED with the
+                              CSR-stream arithmetic, bit for bit                                 */
 };
 
 enum ebtc_flags {
@@ -278,7 +284,9 @@ enum ebtc_phase {
   EBTC_PHASE_FIRST = 8,      /* step 0's product A 1 of the all-ones start: row sums, no gathers
                                 (the entry-balanced form computes a weighted graph's row sums with
                                 its own SpMV kernel over the ones, in equal shares of entries)     */
-  EBTC_PHASE_COUNT = 9
+  EBTC_PHASE_SOLVE = 9,      /* the single-kernel schedule's one launch (every phase above from
+                                start to combine)                                                 */
+  EBTC_PHASE_COUNT = 10
 };
 /* Measurement only: runs ebtc_scores' batched launch sequence once, eagerly (no hipGraph), with a
  * HIP event recorded on `stream` before and after every kernel launch, then synchronises the

@@ -14,23 +14,23 @@ LIB_PATH = os.path.join(HERE, "libebtc.so")
 
 EBTC_OK, EBTC_EINVAL, EBTC_EBADGRAPH, EBTC_EWORKSPACE, EBTC_EHIP, EBTC_ENOTSUPPORTED = range(6)
 EBTC_F32, EBTC_F64 = 0, 1
-SCHED_AUTO, SCHED_PLAIN, SCHED_BATCHED = 0, 1, 2
+SCHED_AUTO, SCHED_PLAIN, SCHED_BATCHED, SCHED_SINGLE = 0, 1, 2, 3
 FLAG_BREAKDOWN, FLAG_CAPPED, FLAG_NONFINITE = 1, 2, 4
-M_LIMIT = 64
+M_LIMIT = 128
 TOPK_LIMIT = 4096
 CKPT_DOUBLES = 2 * M_LIMIT + 4
 
 EXPORTED = [
     "ebtc_version", "ebtc_status_str", "ebtc_last_error", "ebtc_default_opts", "ebtc_batch_create",
-    "ebtc_batch_destroy", "ebtc_plan", "ebtc_scores", "ebtc_topk_ws_bytes", "ebtc_topk", "ebtc_spmv",
-    "ebtc_tridiag_expv", "ebtc_validate_ws_bytes", "ebtc_validate", "ebtc_profile_phases", "ebtc_plan_backward",
+    "ebtc_batch_destroy", "ebtc_plan", "ebtc_scores", "ebtc_topk_ws_bytes", "ebtc_topk",
+    "ebtc_spmv", "ebtc_tridiag_expv", "ebtc_validate_ws_bytes", "ebtc_validate", "ebtc_profile_phases", "ebtc_plan_backward",
     "ebtc_scores_backward", "ebtc_tune", "ebtc_subgraph_centrality_ws_bytes", "ebtc_subgraph_centrality",
     "ebtc_generate_plan", "ebtc_generate_count", "ebtc_generate_fill",
 ]
 GEN_FAMILIES = {"er": 0, "ws": 1, "ba": 2}
 SPMV_FORMS = {"auto": 0, "stream": 1, "lanes": 2, "staged": 3, "segmented": 4, "balanced": 5}
 TUNE_SLOTS = 9  # entries of ebtc_tune's ms_out
-PHASES = ["start", "spmv", "dots", "update", "tridiag", "combine", "sum", "prepare", "first"]
+PHASES = ["start", "spmv", "dots", "update", "tridiag", "combine", "sum", "prepare", "first", "solve"]
 
 
 class BatchDesc(ctypes.Structure):

@@ -21,7 +21,7 @@ import torch
 from . import _abi as A
 
 _DT = {"f32": (A.EBTC_F32, torch.float32, np.float32), "f64": (A.EBTC_F64, torch.float64, np.float64)}
-_SCHED = {"auto": A.SCHED_AUTO, "plain": A.SCHED_PLAIN, "batched": A.SCHED_BATCHED}
+_SCHED = {"auto": A.SCHED_AUTO, "plain": A.SCHED_PLAIN, "batched": A.SCHED_BATCHED, "single": A.SCHED_SINGLE}
 
 
 def _vp(t) -> ctypes.c_void_p:
@@ -32,12 +32,15 @@ def current_stream() -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def make_opts(m: int = 30, tol: float = 1e-6, m_max: int = 60, reorth: int = 1, schedule: str = "batched",
+def make_opts(m: int = 30, tol: float = 1e-6, m_max: int = 60, reorth: int = 1, schedule: str = "auto",
               hipgraph: bool = True, shift: bool = True, spmv: str = "auto", lanes: int = 0, hub: int = 0,
               seg_len: int = 0) -> A.Opts:
-    """Options of one call. spmv: "auto" (the tuned form, else "stream"), "stream", "lanes" (lanes per
-    row, default 8), "staged" (segment length seg_len, default the largest that fits in LDS) or
-    "segmented" (seg_len columns per segment, default 12288 FP32 / 6144 FP64)."""
+    """Options of one call. schedule: "auto" (the single-kernel form when every graph has at most 2048
+    nodes and reorth is 1, else "batched"), "batched" (one launch per phase over all realizations),
+    "single" (one launch runs every realization's whole process) or "plain" (one realization at a
+    time). spmv: "auto" (the tuned form, else "stream"), "stream", "lanes" (lanes per row, default 8),
+    "staged" (segment length seg_len, default the largest that fits in LDS), "segmented" (seg_len
+    columns per segment, default 12288 FP32 / 6144 FP64) or "balanced" (seg_len entries per share)."""
     return A.default_opts(m=m, tol=tol, m_max=m_max, reorth=reorth, schedule=_SCHED[schedule],
                           use_hipgraph=int(hipgraph), shift=int(shift), spmv=A.SPMV_FORMS[spmv], lanes_per_row=lanes,
                           hub_threshold=hub, seg_len=seg_len)

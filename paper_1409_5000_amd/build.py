@@ -14,11 +14,15 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libebtc.so")
-SOURCES = ["k_lanczos.hip", "k_spmv.hip", "k_tridiag.hip", "k_topk.hip", "k_adjoint.hip", "k_generate.hip", "api.cpp"]
+SOURCES = ["k_lanczos.hip", "k_spmv.hip", "k_tridiag.hip", "k_solve.hip", "k_topk.hip", "k_adjoint.hip",
+           "k_generate.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-# Packed FP32 instructions are disabled for every device compile.
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Packed FP32 instructions are disabled for every device compile. Multiply-adds are fused only within
+# one expression (-ffp-contract=on, not the default "fast", which may also fuse a product into an add
+# of a later statement): the per-phase kernels and the single-kernel solve share device functions,
+# and a fusion decided differently at two inlining sites would give them different bits.
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=on"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
          "-I", os.path.join(ROOT, "include")] + DEVICE_FLAGS
 

@@ -53,12 +53,12 @@ struct ExecKey {
   double* log_scale;
   void* ckpt;
   ebtc_diag* diag;
-  int m, m_max, reorth, shift, form, lanes, hub, seglen;
+  int m, m_max, reorth, shift, form, lanes, hub, seglen, sched;
   double tol;
   bool operator==(const ExecKey& o) const {
     return ws == o.ws && scores == o.scores && log_scale == o.log_scale && ckpt == o.ckpt && diag == o.diag &&
            m == o.m && m_max == o.m_max && reorth == o.reorth && shift == o.shift && form == o.form &&
-           lanes == o.lanes && hub == o.hub && seglen == o.seglen && tol == o.tol;
+           lanes == o.lanes && hub == o.hub && seglen == o.seglen && sched == o.sched && tol == o.tol;
   }
 };
 
@@ -84,6 +84,7 @@ struct ebtc_batch {
   int64_t total_scores = 0;  // sum_g n_g
   int64_t total_rows = 0;    // sum_r n_r
   int32_t n_max = 0;
+  int64_t z_max = 0;         // largest realization's entry count
   double mean_degree = 0.0;
   std::vector<Task> tasks;          // host staging of the device task table (kept alive for async copies)
   std::vector<GraphInfo> graphs;
@@ -102,12 +103,14 @@ namespace {
 
 int check_opts(const ebtc_opts* o) {
   if (!o) return fail(EBTC_EINVAL, "opts is NULL");
-  if (o->m < 0 || o->m > EBTC_M_LIMIT) return fail(EBTC_EINVAL, "m must be in [0, 64] (0 = adaptive)");
-  if (o->m == 0 && (o->m_max < 1 || o->m_max > EBTC_M_LIMIT)) return fail(EBTC_EINVAL, "m_max must be in [1, 64]");
+  if (o->m < 0 || o->m > EBTC_M_LIMIT)
+    return fail(EBTC_EINVAL, "m must be in [0, " + std::to_string(EBTC_M_LIMIT) + "] (0 = adaptive)");
+  if (o->m == 0 && (o->m_max < 1 || o->m_max > EBTC_M_LIMIT))
+    return fail(EBTC_EINVAL, "m_max must be in [1, " + std::to_string(EBTC_M_LIMIT) + "]");
   if (o->m == 0 && !(o->tol > 0.0)) return fail(EBTC_EINVAL, "adaptive mode needs tol > 0");
   if (o->reorth < 0 || o->reorth > 2)
     return fail(EBTC_EINVAL, "reorth must be 0 (memory-bounded two-pass), 1 or 2");
-  if (o->schedule < EBTC_SCHED_AUTO || o->schedule > EBTC_SCHED_BATCHED) return fail(EBTC_EINVAL, "unknown schedule");
+  if (o->schedule < EBTC_SCHED_AUTO || o->schedule > EBTC_SCHED_SINGLE) return fail(EBTC_EINVAL, "unknown schedule");
   if (o->spmv < EBTC_SPMV_AUTO || o->spmv > EBTC_SPMV_BALANCED) return fail(EBTC_EINVAL, "unknown spmv form");
   if (o->lanes_per_row != 0 && o->lanes_per_row != 4 && o->lanes_per_row != 8 && o->lanes_per_row != 16 &&
       o->lanes_per_row != 32)
@@ -347,6 +350,7 @@ LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout
 int prepare_kernels(const SpmvPlan& sp) {
   if (sp.seglen > 0) EBTC_HIP(prepare_staged_kernels());
   if (sp.segcols > 0) EBTC_HIP(prepare_seg_kernels());
+  EBTC_HIP(prepare_solve_kernels());
   return EBTC_OK;
 }
 
@@ -392,13 +396,34 @@ int first_in_sort(const ebtc_batch* b, const SpmvPlan& sp) {
   return sp.form == EBTC_SPMV_SEGMENTED && b->values != nullptr ? 1 : 0;
 }
 
+// Whether the single-kernel schedule can run this batch: one row block per realization, the whole
+// basis with one Gram-Schmidt pass, and an SpMV form whose arithmetic is the CSR stream's (the
+// single-kernel solve computes those bits).
+bool single_ok(const ebtc_batch* b, const ebtc_opts* o) {
+  const bool stream_bits = o->spmv == EBTC_SPMV_AUTO || o->spmv == EBTC_SPMV_STREAM ||
+                           o->spmv == EBTC_SPMV_SEGMENTED || o->spmv == EBTC_SPMV_BALANCED;
+  const int steps = o->m > 0 ? o->m : o->m_max;
+  return b->n_max <= kRowsPerBlock && o->reorth == 1 && stream_bits && steps <= kDotsWindow;
+}
+
+// The schedule a call runs: AUTO takes the single-kernel form where it applies.
+int resolve_schedule(const ebtc_batch* b, const ebtc_opts* o, int* sched) {
+  *sched = o->schedule;
+  if (*sched == EBTC_SCHED_AUTO) *sched = single_ok(b, o) ? EBTC_SCHED_SINGLE : EBTC_SCHED_BATCHED;
+  if (*sched == EBTC_SCHED_SINGLE && !single_ok(b, o))
+    return fail(EBTC_ENOTSUPPORTED, "the single-kernel schedule needs every n <= " + std::to_string(kRowsPerBlock) +
+                                        ", m (or m_max) <= " + std::to_string(kDotsWindow) +
+                                        ", reorth = 1 and the stream, segmented, balanced or auto SpMV form");
+  return EBTC_OK;
+}
+
 // Lanczos steps for the launches described by (a, nblocks); a.blkmap / a.single_task select the scope.
 int run_steps(const ebtc_batch* b, const ebtc_opts* o, const LzArgs& a, int64_t nblocks, int64_t first,
               int64_t count, int lanes, hipStream_t s, Prof* prof, bool with_start = true) {
   const bool has_val = b->values != nullptr;
   const int steps = o->m > 0 ? o->m : o->m_max;
   // every realization in one row block: dots and update of a step in one launch (one workgroup each)
-  const bool one_block = b->n_max <= kRowsPerBlock && o->reorth == 1 && a.window == 0;
+  const bool one_block = b->n_max <= kRowsPerBlock && o->reorth == 1 && a.window == 0 && steps <= kDotsWindow;
   if (with_start) EBTC_PHASE(prof, EBTC_PHASE_START, launch_start(b->dtype, a, nblocks, s));
   for (int j = 0; j < steps; ++j) {
     if (!(j == 0 && a.unit_start && a.first_in_prepare))
@@ -457,12 +482,21 @@ int run_pass2(const ebtc_batch* b, const ebtc_opts* o, const LzArgs& a1, int64_t
 }
 
 int enqueue_batched(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, void* scores, double* log_scale,
-                    void* ckpt, ebtc_diag* diag, const SpmvPlan& sp, hipStream_t s, Prof* prof = nullptr) {
+                    void* ckpt, ebtc_diag* diag, const SpmvPlan& sp, int sched, hipStream_t s, Prof* prof = nullptr) {
   LzArgs a = make_args(b, o, ws, L, sp);
   a.unit_start = 1;  // k_start (and k_restart) set v_0 = 1
   a.first_in_prepare = first_in_sort(b, sp);
   a.diag = diag;
   EBTC_LAUNCH(launch_blkmap(a.tasks, b->R, (int32_t*)(ws + L.off_blkmap), s));
+  const int32_t maxblk = (b->n_max + kRowsPerBlock - 1) / kRowsPerBlock;
+  if (sched == EBTC_SCHED_SINGLE) {
+    EBTC_PHASE(prof, EBTC_PHASE_SOLVE,
+               launch_solve_1(b->dtype, b->values != nullptr, a, b->R, o->m > 0 ? o->m : o->m_max, o->shift, o->tol,
+                              diag, (double*)ckpt, b->n_max, b->z_max, s));
+    EBTC_PHASE(prof, EBTC_PHASE_SUM, launch_sum(b->dtype, (const GraphInfo*)(ws + L.off_graphs), b->G, maxblk,
+                                                a.tasks, a.state, a.U, scores, log_scale, s));
+    return EBTC_OK;
+  }
   int rc = enqueue_prepare(b, sp, a, L.total_blocks, s, prof);
   if (rc) return rc;
   rc = run_steps(b, o, a, L.total_blocks, 0, b->R, sp.lanes, s, prof);
@@ -476,7 +510,6 @@ int enqueue_batched(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L
   } else {
     EBTC_PHASE(prof, EBTC_PHASE_COMBINE, launch_combine(b->dtype, a, L.total_blocks, s));
   }
-  const int32_t maxblk = (b->n_max + kRowsPerBlock - 1) / kRowsPerBlock;
   EBTC_PHASE(prof, EBTC_PHASE_SUM, launch_sum(b->dtype, (const GraphInfo*)(ws + L.off_graphs), b->G, maxblk, a.tasks,
                                               a.state, a.U, scores, log_scale, s));
   return EBTC_OK;
@@ -536,7 +569,7 @@ BwdLayout make_bwd_layout(const ebtc_batch* b, const ebtc_opts* o) {
   B.off_aV = off;
   off = align_up(off + es * (size_t)B.fwd.m_slots * b->total_rows);
   B.off_X = off;
-  off = align_up(off + sizeof(double) * kMLimit * kMLimit * b->R);
+  off = align_up(off + sizeof(double) * kXLd * kXLd * b->R);
   B.off_Z = off;
   off = align_up(off + es * (size_t)B.ld * b->total_rows);
   B.off_Vn = off;
@@ -664,6 +697,7 @@ int ebtc_batch_create(const ebtc_batch_desc* d, ebtc_batch** out) {
         return fail(EBTC_EBADGRAPH, "realization " + std::to_string(r) + ": negative rowptr_off");
       }
       b->nnz_r[r] = z;
+      b->z_max = std::max(b->z_max, z);
     }
   }
   b->total_scores = b->score_off[b->G];
@@ -717,19 +751,22 @@ int ebtc_scores(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, vo
   if (ws_bytes < L.total)
     return fail(EBTC_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(L.total));
   if (((uintptr_t)ws & 255) != 0) return fail(EBTC_EINVAL, "workspace must be 256-byte aligned");
+  int sched = 0;
+  rc = resolve_schedule(b, o, &sched);
+  if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   rc = prepare_kernels(sp);
   if (rc) return rc;
   char* w = (char*)ws;
   rc = upload_tables(b, w, L, s);
   if (rc) return rc;
-  if (o->schedule == EBTC_SCHED_PLAIN)
+  if (sched == EBTC_SCHED_PLAIN)
     return enqueue_plain(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, sp, s);
   if (!o->use_hipgraph)
-    return enqueue_batched(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, sp, s);
+    return enqueue_batched(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, sp, sched, s);
   const ExecKey key{ws,        scores_out, log_scale_out, ckpt_out, diag_out, o->m,
                     o->m_max,  o->reorth,  o->shift,      sp.form,  sp.lanes, sp.hub,
-                    sp.seglen + sp.segcols + sp.balent, o->tol};
+                    sp.seglen + sp.segcols + sp.balent,  sched,    o->tol};
   for (auto& e : b->execs) {
     if (e.key == key) {
       EBTC_HIP(hipGraphLaunch(e.exec, s));
@@ -738,7 +775,7 @@ int ebtc_scores(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, vo
   }
   if (!b->capture_stream) EBTC_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
   EBTC_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
-  rc = enqueue_batched(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, sp, b->capture_stream);
+  rc = enqueue_batched(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, sp, sched, b->capture_stream);
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(b->capture_stream, &graph);
   if (rc) {
@@ -775,6 +812,10 @@ int ebtc_profile_phases(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_b
   const Layout L = make_layout(b, o, sp);
   if (ws_bytes < L.total) return fail(EBTC_EWORKSPACE, "workspace too small");
   if (((uintptr_t)ws & 255) != 0) return fail(EBTC_EINVAL, "workspace must be 256-byte aligned");
+  int sched = 0;
+  rc = resolve_schedule(b, o, &sched);
+  if (rc) return rc;
+  if (sched == EBTC_SCHED_PLAIN) sched = EBTC_SCHED_BATCHED;  // phases are measured on a batched pass
   hipStream_t s = (hipStream_t)stream;
   rc = prepare_kernels(sp);
   if (rc) return rc;
@@ -783,7 +824,7 @@ int ebtc_profile_phases(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_b
   if (rc) return rc;
   Prof prof;
   prof.s = s;
-  rc = enqueue_batched(b, o, w, L, scores_out, log_scale_out, nullptr, nullptr, sp, s, &prof);
+  rc = enqueue_batched(b, o, w, L, scores_out, log_scale_out, nullptr, nullptr, sp, sched, s, &prof);
   if (rc) return rc;
   EBTC_HIP(hipStreamSynchronize(s));
   for (int p = 0; p < EBTC_PHASE_COUNT; ++p) {
@@ -990,7 +1031,7 @@ int check_sc_args(int32_t dtype, int32_t n, int32_t count, int32_t m) {
   if (dtype != EBTC_F32 && dtype != EBTC_F64) return fail(EBTC_EINVAL, "dtype must be EBTC_F32 or EBTC_F64");
   if (n < 1) return fail(EBTC_EINVAL, "n must be >= 1");
   if (count < 1) return fail(EBTC_EINVAL, "count must be >= 1");
-  if (m < 1 || m > EBTC_M_LIMIT) return fail(EBTC_EINVAL, "m must be in [1, 64]");
+  if (m < 1 || m > EBTC_M_LIMIT) return fail(EBTC_EINVAL, "m must be in [1, " + std::to_string(EBTC_M_LIMIT) + "]");
   if ((int64_t)count * ((n + kRowsPerBlock - 1) / kRowsPerBlock) >= ((int64_t)1 << 31))
     return fail(EBTC_ENOTSUPPORTED, "too many row blocks for one launch");
   return EBTC_OK;
@@ -1112,7 +1153,7 @@ int ebtc_tridiag_expv(int32_t count, int32_t k, const double* alpha, const doubl
                       double* theta_out, int32_t shift, void* stream) {
   g_err.clear();
   if (count < 0) return fail(EBTC_EINVAL, "count must be >= 0");
-  if (k < 1 || k > EBTC_M_LIMIT) return fail(EBTC_EINVAL, "k must be in [1, 64]");
+  if (k < 1 || k > EBTC_M_LIMIT) return fail(EBTC_EINVAL, "k must be in [1, " + std::to_string(EBTC_M_LIMIT) + "]");
   if (count == 0) return EBTC_OK;
   if (!alpha || !beta || !y_out || !theta_out) return fail(EBTC_EINVAL, "NULL pointer");
   EBTC_LAUNCH(launch_tridiag_arrays(count, k, alpha, beta, y_out, theta_out, shift, (hipStream_t)stream));

@@ -21,7 +21,7 @@ constexpr int kRowsPerThread = kRowsPerBlock / kBlock;
 constexpr int kStagedThreads = 1024; // threads of the LDS-staged SpMV workgroup (16 waves)
 constexpr int kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
 constexpr int kMLimit = EBTC_M_LIMIT;
-constexpr int kPartStride = 64;      // doubles per workgroup in the dot-partial arena
+constexpr int kPartStride = kMLimit; // doubles per workgroup in the dot-partial arena (one per basis vector)
 constexpr int kMaxChunks = 32;       // chunks of the canonical partial-sum order
 
 // One realization of the batch as the kernels see it (device table, 64 bytes).
@@ -86,7 +86,6 @@ struct RState {
   double alpha[kMLimit];
   double beta[kMLimit];
   double s[kMLimit + 1];
-  double c[kMLimit + 1];   // Gram-Schmidt coefficients on the raw basis for the current step
   double y[kMLimit];       // exp(T - theta I) e1
   double scal[kMLimit];    // scal[j] = max(|alpha_0..j|, beta_0..j-1): the breakdown reference of step j
   double theta;
@@ -170,7 +169,17 @@ hipError_t launch_update(int dtype, int j, bool from_w, bool final_pass, bool se
 // Dots and update of step j in one launch; every realization must fit one row block (n <= kRowsPerBlock)
 // and the basis window must be the whole basis (one Gram-Schmidt pass).
 hipError_t launch_dots_update_1(int dtype, int j, const LzArgs& a, int64_t nblocks, hipStream_t s);
+// Largest Gram-Schmidt window one dot-partial launch (and the fused dots-and-update kernel) covers;
+// wider windows take one dot launch per 64 basis vectors.
+constexpr int kDotsWindow = 64;
 hipError_t launch_combine(int dtype, const LzArgs& a, int64_t nblocks, hipStream_t s);
+// Single-kernel solve (k_solve.hip): `count` realizations (one workgroup each, n <= kRowsPerBlock, the
+// whole basis, one Gram-Schmidt pass) from the start vector to u = beta0 V y, with diag and checkpoint
+// as the final small exponential writes them.
+hipError_t launch_solve_1(int dtype, bool has_val, const LzArgs& a, int64_t count, int steps, int shift, double tol,
+                          ebtc_diag* diag, double* ckpt, int n_max, int64_t z_max, hipStream_t s);
+// Opts the single-kernel solve in to the full LDS; once per process, before any stream capture.
+hipError_t prepare_solve_kernels();
 // Memory-bounded form, second pass: restart from the start vector keeping theta, y, m_used, flags;
 // before step j, u (+)= beta0 y_j s_j Vraw_j (j = 0 assigns) and the realization stops after m_used.
 hipError_t launch_restart(int dtype, const LzArgs& a, int64_t nblocks, hipStream_t s);
@@ -219,6 +228,10 @@ hipError_t launch_build_zv(int dtype, const LzArgs& fwd, const LzArgs& adj, cons
                            int ld, int64_t nblocks, hipStream_t s);
 hipError_t launch_sddmm(int dtype, int ld, const LzArgs& fwd, const void* Z, const void* Vn, void* grad,
                         int64_t nblocks, hipStream_t s);
+
+// Leading dimension of the adjoint's block-exponential output per realization (the adjoint's Krylov
+// dimension is at most adjoint_max_m() <= kXLd).
+constexpr int kXLd = 64;
 
 // checkpoint layout per realization (doubles): alpha[kMLimit], beta[kMLimit], theta, beta0, m_used, flags
 constexpr int kCkptDoubles = 2 * kMLimit + 4;

@@ -65,6 +65,7 @@ __global__ __launch_bounds__(64) void k_start_norm(LzArgs a) {
 }
 
 constexpr int kMX = 40;  // largest Krylov dimension of the adjoint block exponential (LDS resident)
+static_assert(kMX <= kXLd, "adjoint output block");
 
 // C (k1 x k2) = P (k1 x kk) * Q (kk x k2), row-major with leading dimension kMX, all in LDS.
 __device__ inline void mm(double* C, const double* P, const double* Q, int k1, int kk, int k2) {
@@ -94,7 +95,7 @@ __device__ inline void tri_mm(double* C, const double* d, const double* o, const
 // exp([[S - theta I, e1 e1^T], [0, T - theta I]] ), c = e^{theta - Sigma_g} ||g|| beta0.
 // Horner evaluation of the degree-16 Taylor polynomial of the scaled matrix (norm <= 1/2), where the
 // tridiagonal factors make every Horner product O(k^2), then repeated squaring of the block-triangular
-// result. Output row-major k2 x k1 in xout (leading dimension kMLimit).
+// result. Output row-major k2 x k1 in xout (leading dimension kXLd).
 __global__ __launch_bounds__(kBlock) void k_block_exp(const RState* fwd, const RState* adj, const Task* tasks,
                                                       const double* log_scale, double* xout) {
   __shared__ double PA[kMX * kMX], PF[kMX * kMX], PB[kMX * kMX], TA[kMX * kMX], TF[kMX * kMX], TB[kMX * kMX];
@@ -103,11 +104,11 @@ __global__ __launch_bounds__(kBlock) void k_block_exp(const RState* fwd, const R
   const int r = blockIdx.x;
   const RState* f = fwd + r;
   const RState* q = adj + r;
-  double* X = xout + (size_t)r * kMLimit * kMLimit;
+  double* X = xout + (size_t)r * kXLd * kXLd;
   const int k1 = f->m_used, k2 = q->m_used;
   const int tid = threadIdx.x;
   if (k2 < 1 || q->beta0 == 0.0 || k1 < 1) {
-    for (int e = tid; e < kMLimit * kMLimit; e += kBlock) X[e] = 0.0;
+    for (int e = tid; e < kXLd * kXLd; e += kBlock) X[e] = 0.0;
     return;
   }
   const double theta = fmax(f->theta, q->theta);
@@ -186,8 +187,8 @@ __global__ __launch_bounds__(kBlock) void k_block_exp(const RState* fwd, const R
   }
   const int g = tasks[r].graph;
   const double c = exp(theta - log_scale[g]) * q->beta0 * f->beta0;
-  for (int e = tid; e < kMLimit * kMLimit; e += kBlock) {
-    const int i = e / kMLimit, j = e - i * kMLimit;
+  for (int e = tid; e < kXLd * kXLd; e += kBlock) {
+    const int i = e / kXLd, j = e - i * kXLd;
     X[e] = (i < k2 && j < k1) ? c * q->s[i] * PF[i * kMX + j] : 0.0;
   }
 }
@@ -207,8 +208,8 @@ __global__ __launch_bounds__(kBlock) void k_build_zv(LzArgs fwd, LzArgs adj, con
   const RState* f = fwd.state + ref.task;
   const RState* q = adj.state + ref.task;
   const int k1 = f->m_used, k2 = min(q->m_used, LD);
-  const double* xr = xall + (size_t)ref.task * kMLimit * kMLimit;
-  for (int e = threadIdx.x; e < LD * LD; e += kBlock) X[e] = xr[(e / LD) * kMLimit + e % LD];
+  const double* xr = xall + (size_t)ref.task * kXLd * kXLd;
+  for (int e = threadIdx.x; e < LD * LD; e += kBlock) X[e] = xr[(e / LD) * kXLd + e % LD];
   if ((int)threadIdx.x < LD) sb[threadIdx.x] = (int)threadIdx.x < k1 ? f->s[threadIdx.x] : 0.0;
   __syncthreads();
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);

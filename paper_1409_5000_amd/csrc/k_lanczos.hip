@@ -17,78 +17,16 @@
 // fully coalesced loads; the SpMV gathers from the one contiguous vector v_j.
 #include <algorithm>
 
-#include "device_common.h"
+#include "step_device.h"
 
 namespace ebtc {
 namespace {
 
-// Partial dots p_d = sum_rows Vraw_{lo+d}[r] * w[r] (d < cnt = j - lo + 1 <= P) of this workgroup's
-// rows, reduced over the workgroup (NT threads) and stored to part_blk[d]. Basis loads are issued
-// min(P, 8) vectors at a time (clamped to the last one, whose extra contributions are masked) so that
-// many loads are in flight per thread. RING > 0: vector i lives in slot i % RING (the ring of the
-// memory-bounded form). red: (NT / 64) * P doubles of LDS.
-template <typename T, int P, int NT, int RING>
-__device__ inline void block_dots(const T* __restrict__ Vr, int n, int lo, int j, int r0, int r1,
-                                  const T* wsrc_lds, const T* wsrc_glob, T* wstore, double* part_blk, double* red) {
-  static_assert(P == 2 || P == 8 || P == 16 || P == 32 || P == 64, "lane layout of ReduceScatter");
-  constexpr int RPT = kRowsPerBlock / NT;
-  constexpr int CH = P < 8 ? P : 8;
-  const int tid = threadIdx.x, cnt = j - lo + 1;
-  T p[P];
-#pragma unroll
-  for (int i = 0; i < P; ++i) p[i] = 0;
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int r = r0 + q * NT + tid;
-    if (r < r1) {
-      const T wv = wsrc_lds ? wsrc_lds[r - r0] : wsrc_glob[r];
-      if (wstore) wstore[r] = wv;
-#pragma unroll
-      for (int d0 = 0; d0 < P; d0 += CH) {
-        if (d0 < cnt) {
-          T v[CH];
-#pragma unroll
-          for (int c = 0; c < CH; ++c) {
-            const int i = lo + min(d0 + c, cnt - 1);
-            v[c] = Vr[(size_t)(RING ? i % RING : i) * n + r];
-          }
-#pragma unroll
-          for (int c = 0; c < CH; ++c) p[d0 + c] += (d0 + c < cnt) ? v[c] * wv : (T)0;
-        }
-      }
-    }
-  }
-  double pd[P];
-#pragma unroll
-  for (int i = 0; i < P; ++i) pd[i] = (double)p[i];
-  const int lane = tid & 63, wave = tid >> 6;
-  ReduceScatter<P, 32>::run(pd, lane);
-  constexpr int LP = 64 / P;  // lanes per value after the reduce-scatter: lane l holds value l / LP
-  if (lane % LP == 0) red[wave * P + lane / LP] = pd[0];
-  __syncthreads();
-  if (tid < P && tid < cnt) {
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < NT / 64; ++w) s += red[w * P + tid];
-    part_blk[tid] = s;
-  }
-}
 
-// First basis vector of the Gram-Schmidt window of step j (all of v_0..v_j without a window).
-__device__ inline int window_lo(const LzArgs& a, int j) { return a.window > 0 ? max(0, j - a.window + 1) : 0; }
-
-// Workgroup size of the step's dot partials for windows of P vectors of es-byte elements: the
-// two-vector ring, windows of up to 8 vectors and FP32 windows of up to 32 take kDotsThreads (two
-// rows per thread, 64 registers, eight waves per SIMD); the rest 256 threads (their accumulators need
-// the registers). The first steps use windows of 8 and 16 vectors: a 32-vector one would reduce and
-// store 32 partials per workgroup for one to sixteen dots.
-__host__ __device__ constexpr int dots_threads(int P, int es) {
-  return (P <= 8 || (es == 4 && P <= 32)) ? kDotsThreads : kBlock;
-}
-
-// k_dots_step: dot partials of w (written by the SpMV) against the window of Vraw_0..j.
+// k_dots_step: dot partials of w (written by the SpMV) against the window of Vraw_0..j, from its c0-th
+// vector on (at most P of them: a window wider than kDotsWindow takes one launch per kDotsWindow).
 template <typename T, int P, int RING>
-__global__ __launch_bounds__(dots_threads(P, sizeof(T))) void k_dots_step(LzArgs a, int j) {
+__global__ __launch_bounds__(dots_threads(P, sizeof(T))) void k_dots_step(LzArgs a, int j, int c0) {
   constexpr int NT = dots_threads(P, sizeof(T));
   __shared__ double red[(NT / 64) * P];
   const Ref ref = resolve(a);
@@ -97,13 +35,14 @@ __global__ __launch_bounds__(dots_threads(P, sizeof(T))) void k_dots_step(LzArgs
   if (step_skipped(a, st, j)) return;
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
   const T* Vr = (const T*)a.V + tk.vec_off;
-  block_dots<T, P, NT, RING>(Vr, n, window_lo(a, j), j, r0, r1, nullptr, (const T*)a.W + tk.w_off, nullptr,
-                             a.part + tk.part_off + (size_t)ref.blk * kPartStride, red);
+  const int lo = window_lo(a, j) + c0;
+  block_dots<T, P, NT, RING>(Vr, n, lo, min(j, lo + P - 1), r0, r1, nullptr, (const T*)a.W + tk.w_off, nullptr,
+                             a.part + tk.part_off + (size_t)ref.blk * kPartStride + c0, red);
 }
 
 // Second Gram-Schmidt pass: dots of the once-orthogonalised vector (stored in the slot of j+1).
 template <typename T, int P, int RING>
-__global__ __launch_bounds__(kBlock) void k_dots_again(LzArgs a, int j) {
+__global__ __launch_bounds__(kBlock) void k_dots_again(LzArgs a, int j, int c0) {
   __shared__ double red[kWaves * P];
   const Ref ref = resolve(a);
   const Task tk = a.tasks[ref.task];
@@ -111,84 +50,11 @@ __global__ __launch_bounds__(kBlock) void k_dots_again(LzArgs a, int j) {
   if (step_skipped(a, st, j)) return;
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
   const T* Vr = (const T*)a.V + tk.vec_off;
-  block_dots<T, P, kBlock, RING>(Vr, n, window_lo(a, j), j, r0, r1, nullptr, Vr + vslot(a, j + 1) * n,
-                           nullptr, a.part + tk.part_off + (size_t)ref.blk * kPartStride, red);
+  const int lo = window_lo(a, j) + c0;
+  block_dots<T, P, kBlock, RING>(Vr, n, lo, min(j, lo + P - 1), r0, r1, nullptr, Vr + vslot(a, j + 1) * n,
+                                 nullptr, a.part + tk.part_off + (size_t)ref.blk * kPartStride + c0, red);
 }
 
-// Phase B of step j: every workgroup reduces the dot partials of all workgroups of its realization
-// in the canonical order (identical coefficients everywhere, no inter-workgroup synchronisation),
-// then v~_{j+1} = src - sum_i c_i Vraw_i over the window (FP64 accumulation, rounded once), plus
-// the partial squared norm on the final pass.
-template <typename T, int P, int RING>
-__device__ inline void update_body(const LzArgs& a, const Ref& ref, int j, int from_w, int final_pass, int second,
-                                   double* cs, double (*csum)[kMaxChunks], double* red) {
-  const Task tk = a.tasks[ref.task];
-  RState* st = a.state + ref.task;
-  constexpr int CH = P < 8 ? P : 8;
-  const int tid = threadIdx.x, lo = window_lo(a, j), cnt = j - lo + 1;
-  const double* part = a.part + tk.part_off;
-  const int nblk = tk.nblk, chunk = part_chunk(nblk), nch = (nblk + chunk - 1) / chunk;
-  for (int item = tid; item < nch * cnt; item += kBlock) {
-    const int c = item / cnt, d = item - c * cnt;
-    double s = 0.0;
-    const int b1 = min(nblk, (c + 1) * chunk);
-    for (int b = c * chunk; b < b1; ++b) s += part[(size_t)b * kPartStride + d];
-    csum[d][c] = s;
-  }
-  __syncthreads();
-  if (tid < P) {
-    double coef = 0.0;
-    if (tid < cnt) {
-      double t = 0.0;
-      for (int c = 0; c < nch; ++c) t += csum[tid][c];
-      const double si = st->s[lo + tid];
-      const double h = si * t;
-      coef = h * si;
-      if (lo + tid == j && ref.blk == 0) {
-        const double alpha = second ? st->alpha[j] + h : h;
-        st->alpha[j] = alpha;
-        if (final_pass) {  // breakdown reference of step j: max(|alpha_0..j|, beta_0..j-1)
-          double sc = fabs(alpha);
-          if (j > 0) sc = fmax(sc, fmax(st->scal[j - 1], st->beta[j - 1]));
-          st->scal[j] = isfinite(alpha) ? sc : alpha;
-        }
-      }
-    }
-    cs[tid] = coef;
-  }
-  __syncthreads();
-  const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);
-  T* Vr = (T*)a.V + tk.vec_off;
-  const T* src = from_w ? (const T*)a.W + tk.w_off : Vr + vslot(a, j + 1) * n;
-  T* dst = Vr + vslot(a, j + 1) * n;
-  double nrm = 0.0;
-#pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
-    const int r = r0 + q * kBlock + tid;
-    if (r < r1) {
-      double acc = (double)src[r];
-#pragma unroll
-      for (int d0 = 0; d0 < P; d0 += CH) {
-        if (d0 < cnt) {
-          T v[CH];
-#pragma unroll
-          for (int c = 0; c < CH; ++c) {
-            const int i = lo + min(d0 + c, cnt - 1);
-            v[c] = Vr[(size_t)(RING ? i % RING : i) * n + r];
-          }
-#pragma unroll
-          for (int c = 0; c < CH; ++c) acc -= cs[d0 + c] * (double)v[c];
-        }
-      }
-      const T out = (T)acc;
-      dst[r] = out;
-      nrm += (double)out * (double)out;
-    }
-  }
-  if (!final_pass) return;
-  nrm = block_sum<kBlock>(nrm, red);
-  if (tid == 0) a.npart[tk.part_off / kPartStride + ref.blk] = nrm;
-}
 
 template <typename T, int P, int RING>
 __global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, int final_pass, int second) {
@@ -197,16 +63,21 @@ __global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, 
   __shared__ double red[kWaves];
   const Ref ref = resolve(a);
   if (step_skipped(a, a.state + ref.task, j)) return;
-  update_body<T, P, RING>(a, ref, j, from_w, final_pass, second, cs, csum, red);
+  const Task tk = a.tasks[ref.task];
+  update_body<T, P, RING>(a, tk, step_mem<T>(a, tk, ref.task), ref.blk, j, from_w, final_pass, second, cs, csum,
+                          red);
 }
 
 // Dots and update of step j in one launch, for batches whose realizations each fit one row block
 // (n <= kRowsPerBlock, one workgroup per realization): the workgroup's dot partials are then the
 // realization's totals, so the update reads them back after a workgroup barrier instead of after a
-// launch boundary. Same steps as k_dots_step followed by k_update (one Gram-Schmidt pass, full basis).
+// launch boundary. Same steps as k_dots_step followed by k_update (one Gram-Schmidt pass, full basis),
+// with k_dots_step's thread order for the partials, so the bits do not depend on which of the two
+// paths a batch takes.
 template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_dots_update_1(LzArgs a, int j) {
-  __shared__ double red_d[kWaves * P];
+  constexpr int NT = dots_threads(P, sizeof(T));
+  __shared__ double red_d[(NT / 64) * P];
   __shared__ double cs[P];
   __shared__ double csum[P][kMaxChunks];
   __shared__ double red[kWaves];
@@ -214,10 +85,10 @@ __global__ __launch_bounds__(kBlock) void k_dots_update_1(LzArgs a, int j) {
   const Task tk = a.tasks[ref.task];
   if (step_skipped(a, a.state + ref.task, j)) return;
   const int n = min(tk.n, kRowsPerBlock);
-  block_dots<T, P, kBlock, 0>((const T*)a.V + tk.vec_off, tk.n, 0, j, 0, n, nullptr, (const T*)a.W + tk.w_off,
-                              nullptr, a.part + tk.part_off, red_d);
+  block_dots<T, P, NT, 0, kBlock>((const T*)a.V + tk.vec_off, tk.n, 0, j, 0, n, nullptr, (const T*)a.W + tk.w_off,
+                                  nullptr, a.part + tk.part_off, red_d);
   __syncthreads();  // the partials stored above (global) are read back by other threads of the workgroup
-  update_body<T, P, 0>(a, ref, j, 1, 1, 0, cs, csum, red);
+  update_body<T, P, 0>(a, tk, step_mem<T>(a, tk, ref.task), ref.blk, j, 1, 1, 0, cs, csum, red);
 }
 
 template <typename T>
@@ -441,52 +312,73 @@ hipError_t launch_accum(int dtype, const LzArgs& a, int j, int64_t nb, hipStream
 }
 
 // Gram-Schmidt kernels by basis window: the memory-bounded form (window 2, ring of three slots)
-// takes the two-vector instantiation; the full basis takes 32 or 64 vectors per launch.
-#define EBTC_GS_LAUNCH(KERNEL, T, ...)                                                   \
+// takes the two-vector instantiation; the full basis takes 8, 16, 32 or 64 vectors per launch (WC:
+// the vectors this launch covers) and the update 8 to 128.
+#define EBTC_GS_LAUNCH(KERNEL, T, WC, ...)                                               \
   do {                                                                                   \
     if (a.window > 0) {                                                                  \
       if (a.window != 2) return hipErrorInvalidValue;                                    \
       hipLaunchKernelGGL((KERNEL<T, 2, 3>), g, b, 0, s, __VA_ARGS__);                    \
-    } else if (window_count(a, j) <= 8) {                                                \
+    } else if ((WC) <= 8) {                                                              \
       hipLaunchKernelGGL((KERNEL<T, 8, 0>), g, b, 0, s, __VA_ARGS__);                    \
-    } else if (window_count(a, j) <= 16) {                                               \
+    } else if ((WC) <= 16) {                                                             \
       hipLaunchKernelGGL((KERNEL<T, 16, 0>), g, b, 0, s, __VA_ARGS__);                   \
-    } else if (window_count(a, j) <= 32) {                                               \
+    } else if ((WC) <= 32) {                                                             \
       hipLaunchKernelGGL((KERNEL<T, 32, 0>), g, b, 0, s, __VA_ARGS__);                   \
     } else {                                                                             \
       hipLaunchKernelGGL((KERNEL<T, 64, 0>), g, b, 0, s, __VA_ARGS__);                   \
     }                                                                                    \
   } while (0)
 
+// Window size class of a dot launch covering wc vectors.
+int dots_p(const LzArgs& a, int wc) { return a.window > 0 ? 2 : wc <= 8 ? 8 : wc <= 16 ? 16 : (wc <= 32 ? 32 : 64); }
+
 hipError_t launch_dots_step(int dtype, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
   if (a.window > 0 && a.window != 2) return hipErrorInvalidValue;
   const int wc = window_count(a, j);
-  const int P = a.window > 0 ? 2 : wc <= 8 ? 8 : wc <= 16 ? 16 : (wc <= 32 ? 32 : 64);
-  const dim3 g((unsigned)nb), b(dots_threads(P, dtype == EBTC_F64 ? 8 : 4));
-  if (dtype == EBTC_F64) EBTC_GS_LAUNCH(k_dots_step, double, a, j);
-  else EBTC_GS_LAUNCH(k_dots_step, float, a, j);
-  return hipGetLastError();
+  for (int c0 = 0; c0 < wc; c0 += kDotsWindow) {
+    const int wcc = std::min(kDotsWindow, wc - c0);
+    const dim3 g((unsigned)nb), b(dots_threads(dots_p(a, wcc), dtype == EBTC_F64 ? 8 : 4));
+    if (dtype == EBTC_F64) EBTC_GS_LAUNCH(k_dots_step, double, wcc, a, j, c0);
+    else EBTC_GS_LAUNCH(k_dots_step, float, wcc, a, j, c0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_dots_again(int dtype, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
-  const dim3 g((unsigned)nb), b(kBlock);
-  if (dtype == EBTC_F64) EBTC_GS_LAUNCH(k_dots_again, double, a, j);
-  else EBTC_GS_LAUNCH(k_dots_again, float, a, j);
-  return hipGetLastError();
+  const int wc = window_count(a, j);
+  for (int c0 = 0; c0 < wc; c0 += kDotsWindow) {
+    const int wcc = std::min(kDotsWindow, wc - c0);
+    const dim3 g((unsigned)nb), b(kBlock);
+    if (dtype == EBTC_F64) EBTC_GS_LAUNCH(k_dots_again, double, wcc, a, j, c0);
+    else EBTC_GS_LAUNCH(k_dots_again, float, wcc, a, j, c0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_update(int dtype, int j, bool from_w, bool final_pass, bool second_pass, const LzArgs& a,
                          int64_t nb, hipStream_t s) {
   const dim3 g((unsigned)nb), b(kBlock);
   const int fw = from_w ? 1 : 0, fp = final_pass ? 1 : 0, sp = second_pass ? 1 : 0;
-  if (dtype == EBTC_F64) EBTC_GS_LAUNCH(k_update, double, a, j, fw, fp, sp);
-  else EBTC_GS_LAUNCH(k_update, float, a, j, fw, fp, sp);
+  const int wc = window_count(a, j);
+  if (a.window == 0 && wc > 64) {  // windows of 65 to 128 vectors
+    if (dtype == EBTC_F64) hipLaunchKernelGGL((k_update<double, 128, 0>), g, b, 0, s, a, j, fw, fp, sp);
+    else hipLaunchKernelGGL((k_update<float, 128, 0>), g, b, 0, s, a, j, fw, fp, sp);
+    return hipGetLastError();
+  }
+  if (dtype == EBTC_F64) EBTC_GS_LAUNCH(k_update, double, wc, a, j, fw, fp, sp);
+  else EBTC_GS_LAUNCH(k_update, float, wc, a, j, fw, fp, sp);
   return hipGetLastError();
 }
 
 hipError_t launch_dots_update_1(int dtype, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
   if (a.window != 0) return hipErrorInvalidValue;
   const int wc = window_count(a, j);
+  if (wc > kDotsWindow) return hipErrorInvalidValue;
   const dim3 g((unsigned)nb), b(kBlock);
 #define EBTC_DU1(T)                                                                            \
   do {                                                                                         \

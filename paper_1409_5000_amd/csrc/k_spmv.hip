@@ -19,36 +19,11 @@
 #include <algorithm>
 #include <type_traits>
 
-#include "device_common.h"
+#include "step_device.h"
 
 namespace ebtc {
 namespace {
 
-// Opens phase A of step j: closes step j-1 from its norm partials (all workgroups of the
-// realization compute the same bits; workgroup 0 records them). Returns false when the
-// realization is finished; *sj = 1/beta_{j-1} (or s_0 at j = 0).
-__device__ inline bool open_step(const LzArgs& a, const Task& tk, RState* st, int blk, int j, double* chunks,
-                                 double* sj) {
-  if (step_skipped(a, st, j)) return false;
-  if (j == 0) {
-    *sj = st->s[0];
-    return true;
-  }
-  const StepClose c = close_step(st, a.npart + tk.part_off / kPartStride, tk.nblk, j - 1, a.eps, chunks);
-  if (blk == 0 && threadIdx.x == 0) {
-    st->beta[j - 1] = c.beta;
-    if (c.flags) {
-      st->flags |= c.flags;
-      st->done = 1;
-      st->m_used = j;
-    } else {
-      st->s[j] = 1.0 / c.beta;
-    }
-  }
-  if (c.flags) return false;
-  *sj = 1.0 / c.beta;
-  return true;
-}
 
 // ------------------------------------------------------------------------------- direct gathers
 template <typename T, bool HAS_VAL, int L>
@@ -161,91 +136,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv_step(LzArgs a, int j) {
 // range longer than the LDS capacity is cut into row chunks; a single row beyond the capacity (a
 // hub) is reduced by the whole workgroup. The whole row block costs two memory round trips per
 // chunk instead of one per row per lane group.
-constexpr int kStreamRows = 256;
-constexpr int kStreamU = 8;
-template <typename T>
-struct StreamShape {
-  static constexpr int CAP = sizeof(T) == 8 ? 3072 : 6144;  // product slots (24 KB)
-};
-
-// SEQ_HUB: a row beyond the capacity is summed by one thread in entry order instead (the first
-// product's arithmetic, for a caller that must reproduce it).
-template <typename T, bool HAS_VAL, int NT = kBlock, int CAP = StreamShape<T>::CAP, bool SEQ_HUB = false>
-__device__ inline void spmv_stream_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                        const T* __restrict__ va, const T* __restrict__ x, int r0, int rows,
-                                        double scale, int* rp_lds, T* prod, T* w_out, double* red) {
-  constexpr int U = kStreamU;
-  const int tid = threadIdx.x;
-  for (int i = tid; i <= rows; i += NT) rp_lds[i] = rp[r0 + i];
-  __syncthreads();
-  int ra = 0;
-  while (ra < rows) {
-    const int nz0 = rp_lds[ra];
-    if (SEQ_HUB && rp_lds[ra + 1] - nz0 > CAP) {
-      if (tid == 0) {
-        double acc = 0.0;
-        for (int k = nz0; k < rp_lds[ra + 1]; ++k) {
-          const T xv = x[ci[k]];
-          if constexpr (HAS_VAL) acc += (double)(va[k] * xv); else acc += (double)xv;
-        }
-        w_out[ra] = (T)(acc * scale);
-      }
-      ++ra;
-      continue;
-    }
-    if (rp_lds[ra + 1] - nz0 > CAP) {  // hub row: whole workgroup, direct gathers
-      const int e = rp_lds[ra + 1];
-      T acc = 0;
-      for (int k = nz0 + tid; k < e; k += NT) {
-        const T xv = x[ci[k]];
-        if constexpr (HAS_VAL) acc += va[k] * xv; else acc += xv;
-      }
-      const double tot = block_sum<NT>((double)acc, red);
-      if (tid == 0) w_out[ra] = (T)(tot * scale);
-      ++ra;
-      continue;
-    }
-    // largest rb with rp[rb] - rp[ra] <= CAP (every thread finds the same rb)
-    int lo = ra + 1, hi = rows;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (rp_lds[mid] - nz0 <= CAP) lo = mid; else hi = mid - 1;
-    }
-    const int rb = lo;
-    const int cnt = rp_lds[rb] - nz0;
-    for (int k0 = tid; k0 < cnt; k0 += NT * U) {
-      int c[U];
-      T v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int k = k0 + u * NT;
-        // the matrix is read once per product: non-temporal loads leave the cache lines of the
-        // gathered vector resident
-        c[u] = k < cnt ? __builtin_nontemporal_load(ci + nz0 + k) : -1;
-        if constexpr (HAS_VAL) v[u] = k < cnt ? __builtin_nontemporal_load(va + nz0 + k) : (T)0;
-      }
-      T xv[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) xv[u] = c[u] >= 0 ? x[c[u]] : (T)0;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int k = k0 + u * NT;
-        if (k < cnt) {
-          if constexpr (HAS_VAL) prod[k] = v[u] * xv[u]; else prod[k] = xv[u];
-        }
-      }
-    }
-    __syncthreads();
-    for (int r = ra + tid; r < rb; r += NT) {
-      double acc = 0.0;  // FP64: sequential sums over long (BA hub) rows stay accurate
-      const int e = rp_lds[r + 1] - nz0;
-      for (int k = rp_lds[r] - nz0; k < e; ++k) acc += (double)prod[k];
-      w_out[r] = (T)(acc * scale);
-    }
-    __syncthreads();
-    ra = rb;
-  }
-}
 
 // Workgroup w of the launch handles rows [q * kStreamRows, (q+1) * kStreamRows) of Lanczos row block
 // w / 8 (q = w % 8); the realization of that block comes from the usual workgroup map.

@@ -126,7 +126,7 @@ def expected_ws(G, nreal, n, m_slots, es, rstate_bytes):
     off = align(off + 24 * G)
     off = align(off + 4 * blocks)
     off = align(off + rstate_bytes * R)
-    off = align(off + 8 * 64 * blocks)
+    off = align(off + 8 * A.M_LIMIT * blocks)  # dot partials: one per basis vector and row block
     off = align(off + 8 * blocks)
     off = align(off + es * m_slots * rows)
     off = align(off + es * rows)
@@ -134,7 +134,8 @@ def expected_ws(G, nreal, n, m_slots, es, rstate_bytes):
     return off
 
 
-RSTATE_BYTES = 8 * (64 + 64 + 65 + 65 + 64 + 64 + 3) + 4 * 4
+M = A.M_LIMIT
+RSTATE_BYTES = 8 * (M + M + (M + 1) + M + M + 4) + 4 * 4  # alpha, beta, s, y, scal; 4 scalars; 4 ints
 
 
 @pytest.mark.parametrize("dtype,es", [(A.EBTC_F32, 4), (A.EBTC_F64, 8)])
@@ -197,7 +198,8 @@ def test_plan_segmented_workspace_arithmetic():
 
 
 @pytest.mark.parametrize("kw,text", [
-    (dict(m=65), "m must be"), (dict(m=-1), "m must be"), (dict(m=0, m_max=0), "m_max"),
+    (dict(m=129), "m must be"), (dict(m=-1), "m must be"), (dict(m=0, m_max=0), "m_max"),
+    (dict(m=0, m_max=129), "m_max"),
     (dict(m=0, tol=0.0), "tol"), (dict(reorth=3), "reorth"), (dict(schedule=9), "schedule"),
     (dict(lanes_per_row=5), "lanes_per_row"), (dict(hub_threshold=-1), "hub_threshold"),
     (dict(seg_len=-1), "seg_len"), (dict(spmv=6), "spmv form"), (dict(spmv=-1), "spmv form"),
@@ -244,8 +246,8 @@ def test_component_entry_points_validate():
     assert L.ebtc_spmv(0, 0, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV + 64, 0, 0, 0, None) == A.EBTC_EINVAL
     assert L.ebtc_spmv(0, 10, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV, 0, 0, 0, None) == A.EBTC_EINVAL
     assert L.ebtc_spmv(0, 10, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV + 64, 6, 0, 0, None)
-    assert L.ebtc_spmv(0, 10, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV + 64, 0, 0, -2, None) == A.EBTC_EINVAL == A.EBTC_EINVAL
-    assert L.ebtc_tridiag_expv(1, 65, FAKE_DEV, FAKE_DEV, FAKE_DEV, FAKE_DEV, 1, None) == A.EBTC_EINVAL
+    assert L.ebtc_spmv(0, 10, FAKE_DEV, FAKE_DEV, None, FAKE_DEV, FAKE_DEV + 64, 0, 0, -2, None) == A.EBTC_EINVAL
+    assert L.ebtc_tridiag_expv(1, A.M_LIMIT + 1, FAKE_DEV, FAKE_DEV, FAKE_DEV, FAKE_DEV, 1, None) == A.EBTC_EINVAL
     assert L.ebtc_tridiag_expv(-1, 5, FAKE_DEV, FAKE_DEV, FAKE_DEV, FAKE_DEV, 1, None) == A.EBTC_EINVAL
     assert L.ebtc_tridiag_expv(0, 5, None, None, None, None, 1, None) == A.EBTC_OK
 
@@ -280,7 +282,7 @@ def test_subgraph_centrality_validates_and_sizes():
     w1 = ws.value
     assert L.ebtc_subgraph_centrality_ws_bytes(0, 5000, 6, 20, ctypes.byref(ws)) == 0 and ws.value > w1
     for args, text in [((7, 10, 1, 5), "dtype"), ((0, 0, 1, 5), "n must"), ((0, 10, 0, 5), "count"),
-                       ((0, 10, 1, 0), "m must"), ((0, 10, 1, 65), "m must")]:
+                       ((0, 10, 1, 0), "m must"), ((0, 10, 1, A.M_LIMIT + 1), "m must")]:
         assert L.ebtc_subgraph_centrality_ws_bytes(*args, ctypes.byref(ws)) == A.EBTC_EINVAL
         assert text in L.ebtc_last_error().decode()
     assert L.ebtc_subgraph_centrality(0, 10, None, FAKE_DEV, None, 1, FAKE_DEV, 5, FAKE_DEV, FAKE_DEV, 1 << 30,

@@ -210,7 +210,7 @@ def test_spmv_fp32_ragged(gpu_lib, weighted):
 
 # ------------------------------------------------------------------ component: tridiagonal exponential
 
-@pytest.mark.parametrize("k", [1, 2, 7, 30, 64])
+@pytest.mark.parametrize("k", [1, 2, 7, 30, 64, 65, 100, 128])
 def test_tridiag_expv_vs_oracle(gpu_lib, k):
     torch = torch_mod()
     rng = np.random.default_rng(k)
