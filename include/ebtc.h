@@ -180,6 +180,20 @@ int ebtc_plan(ebtc_batch* batch, const ebtc_opts* opts, size_t* ws_bytes, size_t
 int ebtc_scores(ebtc_batch* batch, const ebtc_opts* opts, void* ws, size_t ws_bytes, void* scores_out,
                 double* log_scale_out, void* ckpt_out, ebtc_diag* diag_out, void* stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation: ebtc_scores with the workspace taken from a fixed device
+ * array of the library (64 MiB per GPU, EBTC_NOALLOC_WS_BYTES, held on every GPU the library runs on
+ * until the process ends) instead of a caller buffer. Calls no allocating routine: the launches are
+ * eager (use_hipgraph is ignored; instantiating a graph would allocate), and the array's device address
+ * is looked up once per GPU on the first call there. Arguments, outputs, results and errors as for
+ * ebtc_scores, plus EBTC_EWORKSPACE when ebtc_plan's size for (batch, opts) exceeds the array (nothing
+ * is enqueued then). Every call on one GPU uses that GPU's one array: calls that overlap on a GPU
+ * (other threads, other streams, or a second call enqueued before the first has run on another
+ * stream) race and give undefined results; calls in order on one stream do not. */
+#define EBTC_NOALLOC_WS_BYTES ((size_t)64 << 20)
+int ebtc_scores_noalloc(ebtc_batch* batch, const ebtc_opts* opts, void* scores_out, double* log_scale_out,
+                        void* ckpt_out, ebtc_diag* diag_out, void* stream);
+
 /* ---------------------------------------------------------------- adjoint                        */
 /* Workspace bytes for ebtc_scores_backward (host-only). EBTC_ENOTSUPPORTED when the Krylov
  * dimension (m, or m_max in adaptive mode) exceeds 40. */

@@ -19,10 +19,11 @@ FLAG_BREAKDOWN, FLAG_CAPPED, FLAG_NONFINITE = 1, 2, 4
 M_LIMIT = 128
 TOPK_LIMIT = 4096
 CKPT_DOUBLES = 2 * M_LIMIT + 4
+NOALLOC_WS_BYTES = 64 << 20  # EBTC_NOALLOC_WS_BYTES
 
 EXPORTED = [
     "ebtc_version", "ebtc_status_str", "ebtc_last_error", "ebtc_default_opts", "ebtc_batch_create",
-    "ebtc_batch_destroy", "ebtc_plan", "ebtc_scores", "ebtc_topk_ws_bytes", "ebtc_topk",
+    "ebtc_batch_destroy", "ebtc_plan", "ebtc_scores", "ebtc_scores_noalloc", "ebtc_topk_ws_bytes", "ebtc_topk",
     "ebtc_spmv", "ebtc_tridiag_expv", "ebtc_validate_ws_bytes", "ebtc_validate", "ebtc_profile_phases", "ebtc_plan_backward",
     "ebtc_scores_backward", "ebtc_tune", "ebtc_subgraph_centrality_ws_bytes", "ebtc_subgraph_centrality",
     "ebtc_generate_plan", "ebtc_generate_count", "ebtc_generate_fill",
@@ -88,6 +89,7 @@ def lib() -> ctypes.CDLL:
         "ebtc_batch_destroy": (None, [vp]),
         "ebtc_plan": (c_int, [vp, POINTER(Opts), POINTER(sz), POINTER(sz)]),
         "ebtc_scores": (c_int, [vp, POINTER(Opts), vp, sz, vp, vp, vp, vp, vp]),
+        "ebtc_scores_noalloc": (c_int, [vp, POINTER(Opts), vp, vp, vp, vp, vp]),
         "ebtc_topk_ws_bytes": (c_int, [vp, POINTER(sz)]),
         "ebtc_topk": (c_int, [vp, vp, POINTER(c_int32), vp, vp, vp, sz, vp]),
         "ebtc_spmv": (c_int, [c_int32, c_int32, vp, vp, vp, vp, vp, c_int32, c_int32, c_int32, vp]),

@@ -210,6 +210,18 @@ class Batch:
         """Fresh output buffers on every call (see Run for repeated calls)."""
         return self.run(diag=diag, ckpt=ckpt, **kw).launch()
 
+    def scores_noalloc(self, out: ScoreResult | None = None, **kw) -> ScoreResult:
+        """ebtc_scores_noalloc: the library's fixed device array as the workspace (no allocation by the
+        library). Outputs are allocated here unless `out` (a previous result) supplies them."""
+        opts = make_opts(**kw)
+        if out is None:
+            out = ScoreResult(torch.empty(self.total_scores, dtype=self.tdtype, device=self.device),
+                              torch.empty(self.G, dtype=torch.float64, device=self.device), None, None,
+                              torch.empty(self.R * ctypes.sizeof(A.Diag), dtype=torch.uint8, device=self.device))
+        A.check(A.lib().ebtc_scores_noalloc(self.handle, ctypes.byref(opts), _vp(out.scores), _vp(out.log_scale),
+                                            _vp(out.ckpt), _vp(out.raw_diag), current_stream()))
+        return out
+
     def topk(self, scores: torch.Tensor, k) -> tuple[torch.Tensor, torch.Tensor]:
         kv = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.int32), (self.G,)))
         ws = ctypes.c_size_t()

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -797,6 +798,71 @@ int ebtc_scores(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, vo
   b->execs.push_back({key, graph, exec});
   EBTC_HIP(hipGraphLaunch(exec, s));
   return EBTC_OK;
+}
+
+}  // extern "C"
+
+// ---- workspace of ebtc_scores_noalloc: a fixed device array, one per GPU, held until the process ends
+namespace {
+
+constexpr size_t kScratchBytes = EBTC_NOALLOC_WS_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of the current GPU's copy of `scratch`, looked up once per device (the array's name
+// is a host-side stand-in in host code; only this address may be passed to kernels or copies).
+int scratch_address(void** out) {
+  int dev = -1;
+  EBTC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices) return fail(EBTC_ENOTSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    EBTC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (p == nullptr || ((uintptr_t)p & 255) != 0) return fail(EBTC_EHIP, "scratch address unusable");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return EBTC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ebtc_scores_noalloc(ebtc_batch* b, const ebtc_opts* o, void* scores_out, double* log_scale_out, void* ckpt_out,
+                        ebtc_diag* diag_out, void* stream) {
+  g_err.clear();
+  if (!b) return fail(EBTC_EINVAL, "NULL batch");
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (!scores_out || !log_scale_out) return fail(EBTC_EINVAL, "NULL scores or log_scale output");
+  const SpmvPlan sp = spmv_plan(b, o);
+  rc = check_plan(b, sp);
+  if (rc) return rc;
+  const Layout L = make_layout(b, o, sp);
+  if (L.total > kScratchBytes)
+    return fail(EBTC_EWORKSPACE, "the batch needs a workspace of " + std::to_string(L.total) +
+                                     " bytes; the static scratch holds " + std::to_string(kScratchBytes) +
+                                     " (use ebtc_scores with a caller workspace)");
+  int sched = 0;
+  rc = resolve_schedule(b, o, &sched);
+  if (rc) return rc;
+  void* ws = nullptr;
+  rc = scratch_address(&ws);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  rc = prepare_kernels(sp);
+  if (rc) return rc;
+  char* w = (char*)ws;
+  rc = upload_tables(b, w, L, s);
+  if (rc) return rc;
+  // eager launches: instantiating a hipGraph would allocate
+  if (sched == EBTC_SCHED_PLAIN)
+    return enqueue_plain(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, sp, s);
+  return enqueue_batched(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, sp, sched, s);
 }
 
 int ebtc_profile_phases(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, void* scores_out,

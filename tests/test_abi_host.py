@@ -226,6 +226,30 @@ def test_scores_rejects_before_enqueue():
     A.lib().ebtc_batch_destroy(h)
 
 
+def test_scores_noalloc_rejects_before_enqueue():
+    # NULL outputs, a batch whose workspace exceeds the static array, and a schedule the batch cannot
+    # take all fail on the host, before any HIP call (the scratch address is looked up only after them)
+    d, keep = make_desc()
+    rc, h = create(d)
+    o = A.default_opts(m=10)
+    assert A.lib().ebtc_scores_noalloc(h, ctypes.byref(o), None, None, None, None, None) == A.EBTC_EINVAL
+    A.lib().ebtc_batch_destroy(h)
+    d, keep = make_desc(nreal=(4,), n=(1_000_000,), nnz=(10_000_000,) * 4)
+    rc, h = create(d)
+    ws, _ = ctypes.c_size_t(), None
+    assert A.lib().ebtc_plan(h, ctypes.byref(o), ctypes.byref(ws), None) == A.EBTC_OK
+    assert ws.value > A.NOALLOC_WS_BYTES
+    rc = A.lib().ebtc_scores_noalloc(h, ctypes.byref(o), FAKE_DEV, FAKE_DEV, None, None, None)
+    assert rc == A.EBTC_EWORKSPACE and "static scratch" in A.lib().ebtc_last_error().decode()
+    o = A.default_opts(m=10, schedule=A.SCHED_SINGLE, m_max=60)
+    d2, keep2 = make_desc(nreal=(1,), n=(3000,), nnz=(20,))
+    rc, h2 = create(d2)
+    rc = A.lib().ebtc_scores_noalloc(h2, ctypes.byref(o), FAKE_DEV, FAKE_DEV, None, None, None)
+    assert rc == A.EBTC_ENOTSUPPORTED and "single-kernel" in A.lib().ebtc_last_error().decode()
+    A.lib().ebtc_batch_destroy(h)
+    A.lib().ebtc_batch_destroy(h2)
+
+
 def test_topk_rejects_bad_k():
     d, keep = make_desc(n=(10,))
     rc, h = create(d)
