@@ -220,7 +220,7 @@ def main() -> int:
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workers", type=int, default=0)
-    ap.add_argument("--spmv", default="tuned", choices=["tuned", "stream", "lanes", "staged", "segmented", "balanced"],
+    ap.add_argument("--spmv", default="tuned", choices=["tuned", "stream", "lanes", "staged", "segmented", "balanced", "paneled"],
                     help="SpMV form: tuned = time the forms on this batch first (ebtc_tune) and use the fastest")
     ap.add_argument("--lanes", type=int, default=0, help="lane-group form: lanes per row (0 = 8)")
     ap.add_argument("--seg-len", type=int, default=0, help="LDS-staged form: segment length (0 = largest)")

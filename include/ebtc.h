@@ -129,13 +129,23 @@ enum ebtc_spmv_form {
                                 gather of that segment from it. Needs ceil(n / seg_len) <= 32;
                                 row blocks with more than 65535 entries, or a row with more than 255
                                 entries in one segment, use the CSR-stream form                     */
-  EBTC_SPMV_BALANCED = 5     /* the CSR-stream arithmetic with workgroups over equal shares of a
+  EBTC_SPMV_BALANCED = 5,    /* the CSR-stream arithmetic with workgroups over equal shares of a
                                 realization's entries (seg_len each) instead of equal row counts: rows
                                 stay whole, so the sums are the stream form's; for graphs whose
                                 first rows hold most entries (preferential attachment). Each call
                                 first finds every share's rows                                     */
+  EBTC_SPMV_PANELED = 6      /* for vectors too large for the column-segmented form: each call first
+                                puts the entries of groups of row units (64-256 rows) in column-panel
+                                order (seg_len columns per panel, 0 = 12288 FP32 / 6144 FP64); each
+                                step then forms the products panel by panel, one vector slice in LDS
+                                serving a group's entries, and a second pass sums every row's products
+                                in entry order (the stream form's sums, bit for bit). Units with more
+                                entries than the row-sum pass holds in LDS (1.5 times the densest
+                                realization's mean per unit, at most 32768 FP32 / 16384 FP64) or a row
+                                beyond the stream form's LDS capacity use the CSR-stream arithmetic;
+                                at most 1024 panels per realization                                */
 };
-#define EBTC_TUNE_SLOTS 9 /* entries of ebtc_tune's ms_out */
+#define EBTC_TUNE_SLOTS 10 /* entries of ebtc_tune's ms_out */
 
 /* Per-realization diagnostics (device array [R], written by ebtc_scores). */
 typedef struct {
@@ -277,8 +287,9 @@ int ebtc_subgraph_centrality(int32_t dtype, int32_t n, const int32_t* row_ptr, c
  *   form_out, lanes_out, seglen_out  host (nullable): the chosen form and its parameters
  *   ms_out  host [EBTC_TUNE_SLOTS] (nullable): ms per launch of stream, lanes 4, 8, 16, 32,
  *           LDS-staged, column-segmented with 6144 and 12288 FP32 (3072 and 6144 FP64) columns per
- *           segment, and entry-balanced; the segmented and balanced figures include their once-per-
- *           call preparation spread over the call's m steps (-1 where the form was not tried)
+ *           segment, entry-balanced and paneled; the segmented, balanced and paneled figures include
+ *           their once-per-call preparation spread over the call's m steps (-1 where the form was not
+ *           tried)
  * Errors: EINVAL (NULL batch or workspace, bad opts), EWORKSPACE, EHIP. On error the batch keeps its
  * previous choice. */
 int ebtc_tune(ebtc_batch* batch, const ebtc_opts* opts, void* ws, size_t ws_bytes, int32_t* form_out,

@@ -29,8 +29,8 @@ EXPORTED = [
     "ebtc_generate_plan", "ebtc_generate_count", "ebtc_generate_fill",
 ]
 GEN_FAMILIES = {"er": 0, "ws": 1, "ba": 2}
-SPMV_FORMS = {"auto": 0, "stream": 1, "lanes": 2, "staged": 3, "segmented": 4, "balanced": 5}
-TUNE_SLOTS = 9  # entries of ebtc_tune's ms_out
+SPMV_FORMS = {"auto": 0, "stream": 1, "lanes": 2, "staged": 3, "segmented": 4, "balanced": 5, "paneled": 6}
+TUNE_SLOTS = 10  # entries of ebtc_tune's ms_out
 PHASES = ["start", "spmv", "dots", "update", "tridiag", "combine", "sum", "prepare", "first", "solve"]
 
 

@@ -40,7 +40,8 @@ def make_opts(m: int = 30, tol: float = 1e-6, m_max: int = 60, reorth: int = 1, 
     "single" (one launch runs every realization's whole process) or "plain" (one realization at a
     time). spmv: "auto" (the tuned form, else "stream"), "stream", "lanes" (lanes per row, default 8),
     "staged" (segment length seg_len, default the largest that fits in LDS), "segmented" (seg_len
-    columns per segment, default 12288 FP32 / 6144 FP64) or "balanced" (seg_len entries per share)."""
+    columns per segment, default 12288 FP32 / 6144 FP64), "balanced" (seg_len entries per share) or
+    "paneled" (seg_len columns per panel, default 12288 FP32 / 6144 FP64)."""
     return A.default_opts(m=m, tol=tol, m_max=m_max, reorth=reorth, schedule=_SCHED[schedule],
                           use_hipgraph=int(hipgraph), shift=int(shift), spmv=A.SPMV_FORMS[spmv], lanes_per_row=lanes,
                           hub_threshold=hub, seg_len=seg_len)
@@ -249,9 +250,10 @@ class Batch:
             if A.lib().ebtc_plan(self.handle, ctypes.byref(seg), ctypes.byref(ws), None) == A.EBTC_OK:
                 need = max(need, ws.value)
                 break
-        bal = make_opts(**{**kw, "spmv": "balanced"})
-        if A.lib().ebtc_plan(self.handle, ctypes.byref(bal), ctypes.byref(ws), None) == A.EBTC_OK:
-            need = max(need, ws.value)
+        for alt in ("balanced", "paneled"):
+            o2 = make_opts(**{**kw, "spmv": alt})
+            if A.lib().ebtc_plan(self.handle, ctypes.byref(o2), ctypes.byref(ws), None) == A.EBTC_OK:
+                need = max(need, ws.value)
         wst = torch.empty(max(1, need), dtype=torch.uint8, device=self.device)
         form, lanes, segl = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         ms = (ctypes.c_double * A.TUNE_SLOTS)()
@@ -259,7 +261,7 @@ class Batch:
                                   ctypes.byref(lanes), ctypes.byref(segl), ms, current_stream()))
         names = {v: k for k, v in A.SPMV_FORMS.items()}
         labels = ["stream", "lanes4", "lanes8", "lanes16", "lanes32", "staged", f"segmented{small}",
-                  f"segmented{2 * small}", "balanced"]
+                  f"segmented{2 * small}", "balanced", "paneled"]
         return {"form": names[form.value], "lanes": lanes.value, "seg_len": segl.value,
                 "ms_per_launch": {l: ms[i] for i, l in enumerate(labels) if ms[i] >= 0}}
 

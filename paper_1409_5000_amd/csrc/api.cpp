@@ -42,6 +42,10 @@ struct Layout {
   size_t off_segflag = 0, off_segcnt = 0, off_segwoff = 0, off_segblk = 0, off_segcol = 0, off_segval = 0;
   // entry-balanced SpMV arenas (present when the plan uses that form)
   size_t off_bal = 0, off_balbeg = 0;
+  // panel-form arenas (present when the plan uses that form)
+  size_t off_panflag = 0, off_panrun = 0, off_pancol = 0, off_panperm = 0, off_panval = 0, off_panprod = 0,
+         off_panitems = 0, off_pangroups = 0;
+  int64_t npan_items = 0, npan_groups = 0;
   int balent = 0;
   int64_t nbal = 0;  // shares of SpmvPlan::balent entries over all realizations
   size_t total = 0;
@@ -92,6 +96,11 @@ struct ebtc_batch {
   std::vector<int64_t> nnz_r;       // per-realization entry counts (validation upload)
   std::vector<int64_t> bal_begin;   // [R + 1] first entry-balanced share of each realization
   int32_t bal_entries = 0;          // the share size bal_begin was computed for
+  std::vector<PanItem> pan_items;   // the panel form's products-pass work items, realization by realization
+  std::vector<int64_t> pan_begin;   // [R + 1] first work item of each realization
+  std::vector<PanItem> pan_groups;  // the panel form's unit groups (the sort's scan), realization by realization
+  std::vector<int64_t> pan_gbegin;  // [R + 1] first group of each realization
+  int32_t pan_cols_done = 0, pan_unit_done = 0;  // the panel width and unit pan_items were computed for
   std::vector<int32_t> topk_k;
   std::vector<int64_t> topk_off;
   std::vector<ExecEntry> execs;
@@ -112,7 +121,7 @@ int check_opts(const ebtc_opts* o) {
   if (o->reorth < 0 || o->reorth > 2)
     return fail(EBTC_EINVAL, "reorth must be 0 (memory-bounded two-pass), 1 or 2");
   if (o->schedule < EBTC_SCHED_AUTO || o->schedule > EBTC_SCHED_SINGLE) return fail(EBTC_EINVAL, "unknown schedule");
-  if (o->spmv < EBTC_SPMV_AUTO || o->spmv > EBTC_SPMV_BALANCED) return fail(EBTC_EINVAL, "unknown spmv form");
+  if (o->spmv < EBTC_SPMV_AUTO || o->spmv > EBTC_SPMV_PANELED) return fail(EBTC_EINVAL, "unknown spmv form");
   if (o->lanes_per_row != 0 && o->lanes_per_row != 4 && o->lanes_per_row != 8 && o->lanes_per_row != 16 &&
       o->lanes_per_row != 32)
     return fail(EBTC_EINVAL, "lanes_per_row must be 0, 4, 8, 16 or 32");
@@ -129,6 +138,10 @@ struct SpmvPlan {
   int segcols = 0;  // column-segmented: columns per segment
   int smax = 0;     // column-segmented: segments of the largest realization
   int balent = 0;   // entry-balanced: entries per share
+  int pancols = 0;  // paneled: columns per panel
+  int pmax = 0;     // paneled: panels of the largest realization
+  int panunit = 0;  // paneled: rows per unit
+  int panlds = 0;   // paneled: entries of a unit held by the row-sum pass
 };
 
 SpmvPlan spmv_plan(const ebtc_batch* b, const ebtc_opts* o);
@@ -141,6 +154,10 @@ int check_plan(const ebtc_batch* b, const SpmvPlan& p) {
       return fail(EBTC_EINVAL, "the entry-balanced SpMV takes shares of 256 to 2^24 entries (seg_len)");
     if (bal_shares(b, p.balent).back() > INT32_MAX) return fail(EBTC_EINVAL, "too many entry-balanced shares");
   }
+  if (p.form == EBTC_SPMV_PANELED && p.pmax > kPanMaxPanels)
+    return fail(EBTC_EINVAL, "the paneled SpMV takes at most " + std::to_string(kPanMaxPanels) + " panels: n_max " +
+                                 std::to_string(b->n_max) + " > " + std::to_string(kPanMaxPanels) + " x " +
+                                 std::to_string(p.pancols));
   if (p.form == EBTC_SPMV_SEGMENTED && p.smax > kSegMax)
     return fail(EBTC_EINVAL, "the column-segmented SpMV needs at most " + std::to_string(kSegMax) +
                                  " segments: n_max " + std::to_string(b->n_max) + " > " +
@@ -175,6 +192,49 @@ int bal_default(const ebtc_batch* b) {
   int e = kBalEntriesMax;
   while (e > kBalEntriesMin && z / e < kBalTargetShares) e >>= 1;
   return e;
+}
+
+// The panel form's unit groups and products-pass work items: per realization, groups of units sized so
+// that staging a panel's slice costs at most about a tenth of the product traffic of the group's run of
+// that panel (2 + 2 s bytes per entry: column, value, product), halved while the batch has fewer than
+// 1536 items; items panel by panel, group by group.
+const std::vector<PanItem>& pan_table(ebtc_batch* b, int S, int U) {
+  if (b->pan_cols_done == S && b->pan_unit_done == U && b->pan_begin.size() == (size_t)b->R + 1) return b->pan_items;
+  const double es = elem_size(b->dtype);
+  auto build = [&](int shrink) {
+    b->pan_items.clear();
+    b->pan_groups.clear();
+    b->pan_begin.assign((size_t)b->R + 1, 0);
+    b->pan_gbegin.assign((size_t)b->R + 1, 0);
+    int64_t r = 0;
+    for (int32_t g = 0; g < b->G; ++g) {
+      const int32_t nr = b->n[g];
+      const int units = (nr + U - 1) / U, P = (nr + S - 1) / S;
+      for (int32_t k = 0; k < b->nreal[g]; ++k, ++r) {
+        const double per = std::max(1.0, (double)b->nnz_r[r] / ((double)units * P));  // entries per (unit, panel)
+        int gsz = (int)std::ceil(10.0 * S * es / ((2.0 + 2.0 * es) * per));
+        gsz = std::max(1, std::min(units, gsz >> shrink));
+        const size_t g0 = b->pan_groups.size();
+        for (int u0 = 0; u0 < units; u0 += gsz) b->pan_groups.push_back({(int32_t)r, 0, u0, std::min(units, u0 + gsz)});
+        for (int p = 0; p < P; ++p)
+          for (size_t q = g0; q < b->pan_groups.size(); ++q)
+            b->pan_items.push_back({(int32_t)r, p, b->pan_groups[q].b0, b->pan_groups[q].b1});
+        b->pan_begin[r + 1] = (int64_t)b->pan_items.size();
+        b->pan_gbegin[r + 1] = (int64_t)b->pan_groups.size();
+      }
+    }
+  };
+  int shrink = 0;
+  build(shrink);
+  while (b->pan_items.size() < 1536 && shrink < 16) {
+    ++shrink;
+    const size_t before = b->pan_items.size();
+    build(shrink);
+    if (b->pan_items.size() == before) break;
+  }
+  b->pan_cols_done = S;
+  b->pan_unit_done = U;
+  return b->pan_items;
 }
 
 Layout make_layout(const ebtc_batch* b, const ebtc_opts* o, const SpmvPlan& sp) {
@@ -224,6 +284,28 @@ Layout make_layout(const ebtc_batch* b, const ebtc_opts* o, const SpmvPlan& sp) 
     L.off_segval = off;
     if (b->values) off = align_up(off + es * z);
   }
+  if (sp.form == EBTC_SPMV_PANELED) {
+    const size_t z = (size_t)b->nnz_off[b->R];
+    const int64_t units = blocks * (kRowsPerBlock / sp.panunit);
+    L.npan_items = (int64_t)pan_table(const_cast<ebtc_batch*>(b), sp.pancols, sp.panunit).size();
+    L.npan_groups = (int64_t)b->pan_groups.size();
+    L.off_panflag = off;
+    off = align_up(off + sizeof(int32_t) * (size_t)units);
+    L.off_panrun = off;
+    off = align_up(off + sizeof(int2) * (size_t)sp.pmax * (size_t)units);
+    L.off_pancol = off;
+    off = align_up(off + sizeof(uint16_t) * z);
+    L.off_panperm = off;
+    off = align_up(off + sizeof(uint16_t) * z);
+    L.off_panval = off;
+    if (b->values) off = align_up(off + es * z);
+    L.off_panprod = off;
+    off = align_up(off + es * z);
+    L.off_panitems = off;
+    off = align_up(off + sizeof(PanItem) * (size_t)L.npan_items);
+    L.off_pangroups = off;
+    off = align_up(off + sizeof(PanItem) * (size_t)L.npan_groups);
+  }
   if (sp.form == EBTC_SPMV_BALANCED) {
     L.nbal = bal_shares(b, sp.balent).back();
     L.balent = sp.balent;
@@ -268,6 +350,12 @@ int upload_tables(ebtc_batch* b, char* ws, const Layout& L, hipStream_t s) {
   fill_tables(b, L);
   EBTC_HIP(hipMemcpyAsync(ws + L.off_tasks, b->tasks.data(), sizeof(Task) * b->R, hipMemcpyHostToDevice, s));
   EBTC_HIP(hipMemcpyAsync(ws + L.off_graphs, b->graphs.data(), sizeof(GraphInfo) * b->G, hipMemcpyHostToDevice, s));
+  if (L.npan_items > 0) {
+    EBTC_HIP(hipMemcpyAsync(ws + L.off_panitems, b->pan_items.data(), sizeof(PanItem) * (size_t)L.npan_items,
+                            hipMemcpyHostToDevice, s));
+    EBTC_HIP(hipMemcpyAsync(ws + L.off_pangroups, b->pan_groups.data(), sizeof(PanItem) * (size_t)L.npan_groups,
+                            hipMemcpyHostToDevice, s));
+  }
   if (L.nbal > 0) {
     const std::vector<int64_t>& t = bal_table(b, L.balent);
     EBTC_HIP(hipMemcpyAsync(ws + L.off_balbeg, t.data(), sizeof(int64_t) * (b->R + 1), hipMemcpyHostToDevice, s));
@@ -288,6 +376,23 @@ SpmvPlan spmv_form(const ebtc_batch* b, int form, int lanes, int seg_len, int hu
     p.smax = (b->n_max + p.segcols - 1) / p.segcols;
   }
   if (form == EBTC_SPMV_BALANCED) p.balent = seg_len > 0 ? seg_len : bal_default(b);
+  if (form == EBTC_SPMV_PANELED) {
+    p.pancols = std::min(seg_len > 0 ? seg_len : pan_max_cols(b->dtype), pan_max_cols(b->dtype));
+    p.pmax = (b->n_max + p.pancols - 1) / p.pancols;
+    // units: the most rows (256, 128 or 64) whose entries, at 1.5 times the densest realization's mean
+    // degree, fit the stream arithmetic's LDS buffer, which the row-sum pass holds anyway; the budget
+    // is that buffer, or 1.5 times a 64-row unit's mean entries when even those do not fit
+    double deg = 0.0;
+    int64_t r = 0;
+    for (int32_t g = 0; g < b->G; ++g)
+      for (int32_t k = 0; k < b->nreal[g]; ++k, ++r)
+        deg = std::max(deg, (double)b->nnz_r[r] / std::max(1, b->n[g]));
+    const int cap = stream_cap(b->dtype);
+    p.panunit = 256;
+    while (p.panunit > 64 && p.panunit * deg * 1.5 > cap) p.panunit >>= 1;
+    const double need = std::ceil(p.panunit * deg * 1.5 / 256.0) * 256.0;
+    p.panlds = (int)std::min<double>(pan_max_lds(b->dtype), std::max<double>(cap, need));
+  }
   p.hub = hub ? hub : 16 * (p.lanes ? p.lanes : 8);
   return p;
 }
@@ -338,6 +443,21 @@ LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout
     for (int32_t g = 0; g < b->G; ++g)
       if (b->n[g] % vw != 0) a.seg_vec = 0;
   }
+  if (sp.form == EBTC_SPMV_PANELED) {
+    a.pan_cols = sp.pancols;
+    a.pan_pmax = sp.pmax;
+    a.pan_unit = sp.panunit;
+    a.pan_lds = sp.panlds;
+    a.pan_flag = (int32_t*)(ws + L.off_panflag);
+    a.pan_run = (int2*)(ws + L.off_panrun);
+    a.pan_col = (uint16_t*)(ws + L.off_pancol);
+    a.pan_perm = (uint16_t*)(ws + L.off_panperm);
+    a.pan_val = b->values ? (void*)(ws + L.off_panval) : nullptr;
+    a.pan_prod = ws + L.off_panprod;
+    a.pan_items = (const PanItem*)(ws + L.off_panitems);
+    a.pan_nitems = (int32_t)L.npan_items;
+    a.pan_groups = (const PanItem*)(ws + L.off_pangroups);
+  }
   if (sp.form == EBTC_SPMV_BALANCED) {
     a.bal = (BalPart*)(ws + L.off_bal);
     a.bal_begin = (const int64_t*)(ws + L.off_balbeg);
@@ -351,6 +471,7 @@ LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout
 int prepare_kernels(const SpmvPlan& sp) {
   if (sp.seglen > 0) EBTC_HIP(prepare_staged_kernels());
   if (sp.segcols > 0) EBTC_HIP(prepare_seg_kernels());
+  if (sp.pancols > 0) EBTC_HIP(prepare_pan_kernels());
   EBTC_HIP(prepare_solve_kernels());
   return EBTC_OK;
 }
@@ -456,6 +577,15 @@ int enqueue_prepare(const ebtc_batch* b, const SpmvPlan& sp, const LzArgs& a, in
     EBTC_PHASE(prof, EBTC_PHASE_PREPARE, launch_bal_rows(a, one ? a.single_task : 0, one ? 1 : (int)b->R, s));
     return EBTC_OK;
   }
+  if (sp.form == EBTC_SPMV_PANELED) {
+    const bool one = a.blkmap == nullptr;  // the plain schedule: one realization
+    const int64_t g0 = one ? b->pan_gbegin[a.single_task] : 0;
+    const int64_t g1 = one ? b->pan_gbegin[a.single_task + 1] : b->pan_gbegin[b->R];
+    const PanItem* groups = a.pan_groups + g0;
+    EBTC_PHASE(prof, EBTC_PHASE_PREPARE,
+               launch_pan_prepare(b->dtype, b->values != nullptr, a, nblocks, groups, (int)(g1 - g0), s));
+    return EBTC_OK;
+  }
   if (sp.form != EBTC_SPMV_SEGMENTED) return EBTC_OK;
   EBTC_PHASE(prof, EBTC_PHASE_PREPARE, launch_seg_prepare(b->dtype, b->values != nullptr, a, nblocks, sp.smax, s));
   return EBTC_OK;
@@ -526,6 +656,10 @@ int enqueue_plain(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L, 
   for (int64_t r = 0; r < b->R; ++r) {
     a.single_task = (int32_t)r;
     if (a.bal != nullptr) a.nbal = (int32_t)(b->bal_begin[r + 1] - b->bal_begin[r]);
+    if (a.pan_cols > 0) {
+      a.pan_items = (const PanItem*)(ws + L.off_panitems) + b->pan_begin[r];
+      a.pan_nitems = (int32_t)(b->pan_begin[r + 1] - b->pan_begin[r]);
+    }
     const int64_t nb = b->tasks[r].nblk;
     int rc = enqueue_prepare(b, sp, a, nb, s, nullptr);
     if (rc) return rc;
@@ -767,7 +901,7 @@ int ebtc_scores(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, vo
     return enqueue_batched(b, o, w, L, scores_out, log_scale_out, ckpt_out, diag_out, sp, sched, s);
   const ExecKey key{ws,        scores_out, log_scale_out, ckpt_out, diag_out, o->m,
                     o->m_max,  o->reorth,  o->shift,      sp.form,  sp.lanes, sp.hub,
-                    sp.seglen + sp.segcols + sp.balent,  sched,    o->tol};
+                    sp.seglen + sp.segcols + sp.balent + sp.pancols,  sched,    o->tol};
   for (auto& e : b->execs) {
     if (e.key == key) {
       EBTC_HIP(hipGraphLaunch(e.exec, s));
@@ -936,6 +1070,10 @@ int ebtc_tune(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, int3
     const SpmvPlan p = spmv_form(b, EBTC_SPMV_BALANCED, 0, 0, 0);
     if (make_layout(b, o, p).total <= ws_bytes) cands.push_back({p, 8});
   }
+  {
+    const SpmvPlan p = spmv_form(b, EBTC_SPMV_PANELED, 0, 0, 0);
+    if (p.pmax <= kPanMaxPanels && make_layout(b, o, p).total <= ws_bytes) cands.push_back({p, 9});
+  }
   for (const Cand& c : cands) {
     rc = prepare_kernels(c.p);
     if (rc) return rc;
@@ -977,6 +1115,15 @@ int ebtc_tune(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, int3
     if (e == hipSuccess && p.form == EBTC_SPMV_SEGMENTED)
       e = launch_seg_prepare(b->dtype, has_val, a, L.total_blocks, p.smax, s);
     if (e == hipSuccess && p.form == EBTC_SPMV_BALANCED) e = launch_bal_rows(a, 0, (int)b->R, s);
+    if (e == hipSuccess && p.form == EBTC_SPMV_PANELED) {
+      e = hipMemcpyAsync(w + Lc.off_panitems, b->pan_items.data(), sizeof(PanItem) * (size_t)Lc.npan_items,
+                         hipMemcpyHostToDevice, s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(w + Lc.off_pangroups, b->pan_groups.data(), sizeof(PanItem) * (size_t)Lc.npan_groups,
+                           hipMemcpyHostToDevice, s);
+      if (e == hipSuccess)
+        e = launch_pan_prepare(b->dtype, has_val, a, L.total_blocks, a.pan_groups, (int)Lc.npan_groups, s);
+    }
     if (e == hipSuccess) e = hipEventRecord(ev[1], s);
     if (e == hipSuccess) e = launch_spmv_step(b->dtype, has_val, p.lanes, 0, a, L.total_blocks, s);
     if (e == hipSuccess) e = hipEventRecord(ev[2], s);
@@ -990,7 +1137,8 @@ int ebtc_tune(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, int3
       rc = fail(EBTC_EHIP, std::string("tuning launch: ") + hipGetErrorString(e));
       break;
     }
-    ms[cands[c].slot] = t_spmv / kReps + (p.form == EBTC_SPMV_SEGMENTED || p.form == EBTC_SPMV_BALANCED ? t_prep / steps : 0.0);
+    const bool prepared = p.form == EBTC_SPMV_SEGMENTED || p.form == EBTC_SPMV_BALANCED || p.form == EBTC_SPMV_PANELED;
+    ms[cands[c].slot] = t_spmv / kReps + (prepared ? t_prep / steps : 0.0);
     if (best < 0 || ms[cands[c].slot] < ms[cands[best].slot]) best = (int)c;
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
@@ -998,7 +1146,10 @@ int ebtc_tune(ebtc_batch* b, const ebtc_opts* o, void* ws, size_t ws_bytes, int3
   const SpmvPlan& p = cands[best].p;
   b->tuned_form = p.form;
   b->tuned_lanes = p.lanes;
-  b->tuned_seglen = p.form == EBTC_SPMV_SEGMENTED ? p.segcols : p.form == EBTC_SPMV_BALANCED ? p.balent : p.seglen;
+  b->tuned_seglen = p.form == EBTC_SPMV_SEGMENTED ? p.segcols
+                    : p.form == EBTC_SPMV_BALANCED ? p.balent
+                    : p.form == EBTC_SPMV_PANELED  ? p.pancols
+                                                   : p.seglen;
   if (form_out) *form_out = b->tuned_form;
   if (lanes_out) *lanes_out = b->tuned_lanes;
   if (seglen_out) *seglen_out = b->tuned_seglen;

@@ -70,6 +70,22 @@ static_assert(sizeof(BalPart) == 16, "BalPart layout");
 // of row walks per workgroup).
 constexpr int kBalEntriesMin = 4096, kBalEntriesMax = 16384, kBalTargetShares = 8192;
 
+// One work item of the panel form's products pass: panel `panel` of row units [b0, b1) of
+// realization `task` (unit indices local to the realization). The once-per-call scan takes the same
+// struct for a group of units (panel unused).
+struct PanItem {
+  int32_t task;
+  int32_t panel;
+  int32_t b0;
+  int32_t b1;
+};
+static_assert(sizeof(PanItem) == 16, "PanItem layout");
+// Panel form: the row-sum pass's LDS for one unit's products (at most 128 KB), the largest unit
+// (rows), and the largest number of panels per realization (the sort's count table).
+constexpr int kPanCapBytes = 128 * 1024;
+constexpr int kPanMaxUnit = 256;
+constexpr int kPanMaxPanels = 1024;
+
 struct GraphInfo {
   int64_t score_off;   // offset of the graph's block in the score output
   int32_t n;
@@ -136,6 +152,23 @@ struct LzArgs {
   const int64_t* bal_begin;  // [R + 1] first share of each realization (host-computed)
   int32_t nbal;
   int32_t bal_entries;     // entries per share
+  // panel form (pan_cols > 0): each group of row units' entries put in (panel, unit) order once per
+  // call; each step a products pass (one vector slice in LDS serves a group's entries of a panel) and a
+  // row-sum pass per unit
+  int32_t pan_cols;        // columns per panel
+  int32_t pan_pmax;        // most panels of a realization in the launch (the stride of pan_run)
+  int32_t pan_unit;        // rows per unit (64, 128 or 256)
+  int32_t pan_lds;         // entries of a unit the row-sum pass holds in LDS (more: stream arithmetic)
+  int32_t* pan_flag;       // [units] 1 = sorted, 0 = the unit uses the CSR-stream arithmetic
+  int2* pan_run;           // [units][pan_pmax] {first entry, count} of the unit's run of panel p, entries
+                           // counted from the realization's first
+  uint16_t* pan_col;       // [entries] column - p * pan_cols
+  uint16_t* pan_perm;      // [entries] the entry's position in its unit's CSR range
+  void* pan_val;           // [entries] values in the same order (nullptr for pattern-only graphs)
+  void* pan_prod;          // [entries] the step's products, same order
+  const PanItem* pan_items;  // products-pass work items
+  const PanItem* pan_groups;  // [groups] unit groups of the once-per-call scan (panel unused)
+  int32_t pan_nitems;
   // memory-bounded form (window > 0): Gram-Schmidt against the last `window` basis vectors only, the
   // raw basis kept in a ring of window + 1 slots (vector i in slot i % (window + 1))
   int32_t window;
@@ -200,6 +233,15 @@ hipError_t prepare_seg_kernels();
 hipError_t launch_seg_prepare(int dtype, bool has_val, const LzArgs& a, int64_t nblocks, int smax, hipStream_t s);
 // Row bounds of the entry-balanced form's shares of realizations [t0, t0 + count).
 hipError_t launch_bal_rows(const LzArgs& a, int t0, int count, hipStream_t s);
+// Panel form: largest panel (columns) for the products pass's LDS slice, largest LDS budget of the
+// row-sum pass (entries), and the once-per-call sort (count, scan over `groups`, place).
+int pan_max_cols(int dtype);
+int pan_max_lds(int dtype);
+// Entries of the CSR-stream arithmetic's LDS buffer (rows beyond it are summed as hub rows).
+int stream_cap(int dtype);
+hipError_t prepare_pan_kernels();
+hipError_t launch_pan_prepare(int dtype, bool has_val, const LzArgs& a, int64_t nblocks, const PanItem* groups,
+                              int ngroups, hipStream_t s);
 
 // ---- launchers (k_tridiag.hip)
 // mode 0: final (closes step m_steps-1 when still open; writes y/theta/est, diag, checkpoint);

@@ -889,6 +889,337 @@ int seg_prepare_cap(int smax) {
   return (int)std::min<size_t>(16384, cap / 256 * 256);
 }
 
+// ------------------------------------------------------------------------------- paneled
+// For vectors of megabytes (n = 1e6: 82 column panels of 12288 FP32 elements) the column-segmented
+// form would stage every segment once per row block, so its slice traffic grows with n; the gathers of
+// the stream form miss L2. Here the two are decoupled. Rows are cut into units of pan_unit rows (64,
+// 128 or 256, dividing the 2048-row block), units into groups. Once per call the entries of each group
+// are put in (panel, unit) order: k_pan_count counts each unit's entries per panel, k_pan_scan turns
+// the counts into run offsets in that order, k_pan_place writes each entry's 16-bit in-panel column,
+// its 16-bit position in the unit's CSR range and its value at the next free slot of its run (the order
+// inside a run does not matter: the row-sum pass puts every product back at its CSR position). Each
+// step then runs two passes:
+//   products  one workgroup per (realization, panel, group): the panel's slice of v_j is staged in LDS
+//             once and serves the group's entries of that panel, one contiguous range read and written
+//             with coalesced loads and stores (prod = value * slice[column], in the working precision,
+//             as the stream form forms them). Items are ordered by panel, and each XCD takes a
+//             contiguous range of them, so the slices an XCD reads stay in its L2;
+//   row sums  one workgroup per unit: the unit's per-panel runs, scattered into LDS by CSR position,
+//             then each row's products added in entry order in FP64 (the stream form's sums, bit for
+//             bit), times s_j. The step's opening (beta_{j-1}, s_j, breakdown) is taken by the products
+//             pass, whose items are fewer, and read here from the realization's state.
+// A unit with more entries than the row-sum pass holds in LDS (pan_lds), or with a row beyond the
+// stream form's capacity (whose sum that form forms another way), is left out of the sort and summed
+// with the stream arithmetic in the row-sum pass.
+constexpr int kPanPrepThreads = 256;
+constexpr int kPanScanThreads = 1024;
+constexpr int kPanProdThreads = 512;
+constexpr int kPanRowThreads = 256;
+
+template <typename T>
+struct PanShape {
+  static constexpr int MAXCOLS = sizeof(T) == 8 ? 6144 : 12288;  // slice of the products pass (48 KB)
+};
+
+// Dynamic LDS of the row-sum pass: the unit's products (at least the stream arithmetic's buffer, which
+// the pass falls back to), then the runs' prefix sums and offsets.
+template <typename T>
+__host__ __device__ inline size_t pan_rows_lds(int pan_lds, int pmax) {
+  const size_t prod = (size_t)(pan_lds > StreamShape<T>::CAP ? pan_lds : StreamShape<T>::CAP) * sizeof(T);
+  return (prod + 15) / 16 * 16 + (size_t)(2 * pmax + 2) * sizeof(int);
+}
+
+struct PanRef {
+  int task;
+  int u;       // unit index in the realization
+  int64_t gu;  // unit index in the launch's unit arrays
+};
+
+// Units of the launch: kRowsPerBlock / pan_unit per row block, in block order.
+__device__ inline PanRef pan_ref(const LzArgs& a) {
+  const int k = kRowsPerBlock / a.pan_unit;
+  const int lb = logical_block(), lblk = lb / k, sub = lb - lblk * k;
+  int t, blk;
+  if (a.blkmap == nullptr) {
+    t = a.single_task;
+    blk = lblk;
+  } else {
+    t = a.blkmap[lblk];
+    blk = lblk - a.tasks[t].blk_begin;
+  }
+  return {t, blk * k + sub, ((int64_t)a.tasks[t].blk_begin + blk) * k + sub};
+}
+
+template <typename T>
+__global__ __launch_bounds__(kPanPrepThreads) void k_pan_count(LzArgs a) {
+  constexpr int NT = kPanPrepThreads;
+  __shared__ int rp_lds[kPanMaxUnit + 1];
+  __shared__ int cnt[kPanMaxPanels];
+  __shared__ int bad;
+  const PanRef ref = pan_ref(a);
+  const Task tk = a.tasks[ref.task];
+  const int n = tk.n, U = a.pan_unit, r0 = ref.u * U, rows = min(n - r0, U), tid = threadIdx.x;
+  const int S = a.pan_cols, P = (n + S - 1) / S;
+  if (rows <= 0) {  // the trailing units of a realization's last block
+    if (tid == 0) a.pan_flag[ref.gu] = 0;
+    return;
+  }
+  int2* run = a.pan_run + ref.gu * a.pan_pmax;
+  const int32_t* rp = a.row_ptr + tk.rowptr_off;
+  for (int i = tid; i <= rows; i += NT) rp_lds[i] = rp[r0 + i];
+  for (int p = tid; p < P; p += NT) cnt[p] = 0;
+  if (tid == 0) bad = P > a.pan_pmax ? 1 : 0;
+  __syncthreads();
+  const int e0 = rp_lds[0], nz = rp_lds[rows] - e0;
+  for (int r = tid; r < rows; r += NT)
+    if (rp_lds[r + 1] - rp_lds[r] > StreamShape<T>::CAP) bad = 1;
+  __syncthreads();
+  const bool ok = !bad && nz <= a.pan_lds;
+  if (ok) {
+    const int32_t* ci = a.col_idx + tk.nnz_off + e0;
+    for (int e = tid; e < nz; e += NT) atomicAdd(&cnt[min(max(ci[e] / S, 0), P - 1)], 1);
+    __syncthreads();
+  }
+  for (int p = tid; p < min(P, a.pan_pmax); p += NT) run[p] = make_int2(0, ok ? cnt[p] : 0);
+  if (tid == 0) a.pan_flag[ref.gu] = ok ? 1 : 0;
+}
+
+// Run offsets of one group (units [b0, b1) of a realization), in (panel, unit) order, from the entry
+// offset of the group's first row on.
+__global__ __launch_bounds__(kPanScanThreads) void k_pan_scan(LzArgs a, const PanItem* groups) {
+  constexpr int NT = kPanScanThreads;
+  __shared__ int wtot[NT / 64];
+  const PanItem g = groups[blockIdx.x];
+  const Task tk = a.tasks[g.task];
+  const int n = tk.n, U = a.pan_unit, S = a.pan_cols, P = (n + S - 1) / S, tid = threadIdx.x;
+  const int gsz = g.b1 - g.b0, E = P * gsz;
+  const int64_t gu0 = (int64_t)tk.blk_begin * (kRowsPerBlock / U) + g.b0;
+  int carry = a.row_ptr[tk.rowptr_off + min(n, g.b0 * U)];
+  for (int i0 = 0; i0 < E; i0 += NT) {
+    const int i = i0 + tid, p = i / gsz, uu = i - p * gsz;
+    int2* cell = a.pan_run + (gu0 + uu) * a.pan_pmax + p;
+    const int v = i < E ? cell->y : 0;
+    int total = 0;
+    const int ex = block_excl_scan<NT>(v, wtot, &total);
+    if (i < E) cell->x = carry + ex;
+    carry += total;
+  }
+}
+
+template <typename T, bool HAS_VAL>
+__global__ __launch_bounds__(kPanPrepThreads) void k_pan_place(LzArgs a) {
+  constexpr int NT = kPanPrepThreads;
+  __shared__ int rp_lds[2];
+  __shared__ int cursor[kPanMaxPanels];
+  const PanRef ref = pan_ref(a);
+  if (!a.pan_flag[ref.gu]) return;
+  const Task tk = a.tasks[ref.task];
+  const int n = tk.n, U = a.pan_unit, r0 = ref.u * U, rows = min(n - r0, U), tid = threadIdx.x;
+  const int S = a.pan_cols, P = (n + S - 1) / S;
+  const int2* run = a.pan_run + ref.gu * a.pan_pmax;
+  const int32_t* rp = a.row_ptr + tk.rowptr_off;
+  if (tid == 0) {
+    rp_lds[0] = rp[r0];
+    rp_lds[1] = rp[r0 + rows];
+  }
+  for (int p = tid; p < P; p += NT) cursor[p] = run[p].x;
+  __syncthreads();
+  const int e0 = rp_lds[0], nz = rp_lds[1] - e0;
+  const int32_t* ci = a.col_idx + tk.nnz_off + e0;
+  const T* va = HAS_VAL ? (const T*)a.values + tk.nnz_off + e0 : nullptr;
+  uint16_t* oc = a.pan_col + tk.nnz_off;
+  uint16_t* op = a.pan_perm + tk.nnz_off;
+  T* ov = HAS_VAL ? (T*)a.pan_val + tk.nnz_off : nullptr;
+  for (int e = tid; e < nz; e += NT) {
+    const int c = ci[e], p = min(max(c / S, 0), P - 1);
+    const int pos = atomicAdd(&cursor[p], 1);
+    oc[pos] = (uint16_t)min(max(c - p * S, 0), S - 1);
+    op[pos] = (uint16_t)e;
+    if constexpr (HAS_VAL) ov[pos] = va[e];
+  }
+}
+
+// Products of one work item: panel `panel` of units [b0, b1), one contiguous range of entries.
+template <typename T, bool HAS_VAL>
+__global__ __launch_bounds__(kPanProdThreads) void k_pan_products(LzArgs a, int j) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NT = kPanProdThreads, U = 8;
+  T* slice = (T*)smem;
+  __shared__ double chunks[kMaxChunks];
+  const PanItem it = a.pan_items[logical_block()];
+  const Task tk = a.tasks[it.task];
+  // the step's opening (beta_{j-1} from the partials, breakdown) is taken here, once per item instead
+  // of once per row unit; the realization's first item records it for the row-sum pass
+  double sj;
+  if (!open_step(a, tk, a.state + it.task, it.panel == 0 && it.b0 == 0 ? 0 : 1, j, chunks, &sj)) return;
+  const int n = tk.n, S = a.pan_cols, c0 = it.panel * S, len = min(S, n - c0), tid = threadIdx.x;
+  const int64_t gu0 = (int64_t)tk.blk_begin * (kRowsPerBlock / a.pan_unit);
+  const int2 first = a.pan_run[(gu0 + it.b0) * a.pan_pmax + it.panel];
+  const int2 last = a.pan_run[(gu0 + it.b1 - 1) * a.pan_pmax + it.panel];
+  const int vb = first.x, ve = last.x + last.y;
+  const T* x = (const T*)a.V + tk.vec_off + vslot(a, j) * n + c0;
+  for (int i = tid; i < len; i += NT) slice[i] = x[i];
+  __syncthreads();
+  const uint16_t* col = a.pan_col + tk.nnz_off;
+  const T* val = HAS_VAL ? (const T*)a.pan_val + tk.nnz_off : nullptr;
+  T* prod = (T*)a.pan_prod + tk.nnz_off;
+  // four entries per thread and load: groups of four from the 4-aligned entry at or below vb (the
+  // realization's arrays start 256-byte aligned only when its entry offset is a multiple of 4, so the
+  // vector accesses are used only then)
+  if ((tk.nnz_off & 3) == 0) {
+    const int g0 = vb >> 2, g1 = (ve + 3) >> 2;
+    const uint64_t* col4 = (const uint64_t*)col;
+    for (int q0 = g0 + tid; q0 < g1; q0 += NT * U) {
+      uint64_t c[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + u * NT;
+        c[u] = q < g1 ? __builtin_nontemporal_load(col4 + q) : (uint64_t)0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + u * NT;
+        if (q >= g1) continue;
+        const uint16_t cc[4] = {(uint16_t)c[u], (uint16_t)(c[u] >> 16), (uint16_t)(c[u] >> 32),
+                                (uint16_t)(c[u] >> 48)};
+        if (4 * q >= vb && 4 * q + 4 <= ve) {  // a whole group: one vector store per lane
+          typedef T T4 __attribute__((ext_vector_type(4)));
+          T4 pr;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const T xv = slice[cc[i]];
+            if constexpr (HAS_VAL) pr[i] = val[4 * q + i] * xv; else pr[i] = xv;
+          }
+          __builtin_nontemporal_store(pr, (T4*)(prod + 4 * q));
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int v = 4 * q + i;
+            if (v < vb || v >= ve) continue;
+            const T xv = slice[cc[i]];
+            T pr;
+            if constexpr (HAS_VAL) pr = val[v] * xv; else pr = xv;
+            __builtin_nontemporal_store(pr, prod + v);
+          }
+        }
+      }
+    }
+    return;
+  }
+  for (int v0 = vb + tid; v0 < ve; v0 += NT * U) {
+    uint16_t c[U];
+    T w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int v = v0 + u * NT;
+      c[u] = v < ve ? __builtin_nontemporal_load(col + v) : (uint16_t)0;
+      if constexpr (HAS_VAL) w[u] = v < ve ? __builtin_nontemporal_load(val + v) : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int v = v0 + u * NT;
+      if (v < ve) {
+        const T xv = slice[c[u]];
+        T pr;
+        if constexpr (HAS_VAL) pr = w[u] * xv; else pr = xv;
+        __builtin_nontemporal_store(pr, prod + v);
+      }
+    }
+  }
+}
+
+template <typename T, bool HAS_VAL>
+__global__ __launch_bounds__(kPanRowThreads) void k_pan_rows(LzArgs a, int j) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NT = kPanRowThreads, U = 16;
+  T* pl = (T*)smem;  // the unit's products in CSR order
+  const size_t prod_bytes = (pan_rows_lds<T>(a.pan_lds, a.pan_pmax) - (size_t)(2 * a.pan_pmax + 2) * sizeof(int));
+  int* pre = (int*)(smem + prod_bytes);  // [P + 1] first flattened entry of each run
+  int* rx = pre + a.pan_pmax + 1;        // [P] each run's first entry
+  __shared__ int rp_lds[kPanMaxUnit + 1];
+  __shared__ double red[NT / 64];
+  __shared__ int wtot[NT / 64];
+  const PanRef ref = pan_ref(a);
+  const Task tk = a.tasks[ref.task];
+  RState* st = a.state + ref.task;
+  const int n = tk.n, Ur = a.pan_unit, r0 = ref.u * Ur, rows = min(n - r0, Ur), tid = threadIdx.x;
+  if (rows <= 0 || step_skipped(a, st, j)) return;
+  const double sj = st->s[j];  // recorded by the products pass (st->s[0] at step 0)
+  const int32_t* rp = a.row_ptr + tk.rowptr_off;
+  T* w = (T*)a.W + tk.w_off + r0;
+  if (!a.pan_flag[ref.gu]) {  // the CSR-stream arithmetic, gathering from the vector in memory
+    const T* va = HAS_VAL ? (const T*)a.values + tk.nnz_off : nullptr;
+    spmv_stream_rows<T, HAS_VAL, NT, StreamShape<T>::CAP, false, false, true, kBlock>(
+        rp, a.col_idx + tk.nnz_off, va, (const T*)a.V + tk.vec_off + vslot(a, j) * n, r0, rows, sj, rp_lds, pl, w,
+        red);
+    return;
+  }
+  const int S = a.pan_cols, P = (n + S - 1) / S;
+  const int2* run = a.pan_run + ref.gu * a.pan_pmax;
+  for (int i = tid; i <= rows; i += NT) rp_lds[i] = rp[r0 + i];
+  int carry = 0;
+  for (int p0 = 0; p0 < P; p0 += NT) {
+    const int p = p0 + tid;
+    const int2 rv = p < P ? run[p] : make_int2(0, 0);
+    int total = 0;
+    const int ex = block_excl_scan<NT>(rv.y, wtot, &total);
+    if (p < P) {
+      pre[p] = carry + ex;
+      rx[p] = rv.x;
+    }
+    carry += total;
+  }
+  if (tid == 0) pre[P] = carry;
+  __syncthreads();
+  const int e0 = rp_lds[0], total = carry;
+  const uint16_t* perm = a.pan_perm + tk.nnz_off;
+  const T* prod = (const T*)a.pan_prod + tk.nnz_off;
+  int top = 1;  // the largest power of two below P: the search's first stride
+  while (top * 2 < P) top *= 2;
+  for (int v0 = tid; v0 < total; v0 += NT * U) {
+    // the last run starting at or before each entry, by a search of fixed length (the U searches
+    // interleave their LDS reads)
+    int lo[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) lo[u] = 0;
+    for (int stride = P > 1 ? top : 0; stride > 0; stride >>= 1) {
+      // unconditional reads (index clamped) and a select: the U reads issue back to back
+      int pv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) pv[u] = pre[min(lo[u] + stride, P - 1)];
+#pragma unroll
+      for (int u = 0; u < U; ++u) lo[u] = (lo[u] + stride < P && pv[u] <= v0 + u * NT) ? lo[u] + stride : lo[u];
+    }
+    uint16_t q[U];
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int f = v0 + u * NT;
+      const int pos = rx[lo[u]] + (f - pre[lo[u]]);
+      q[u] = f < total ? __builtin_nontemporal_load(perm + pos) : (uint16_t)0;
+      v[u] = f < total ? __builtin_nontemporal_load(prod + pos) : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (v0 + u * NT < total) pl[q[u]] = v[u];
+  }
+  __syncthreads();
+  for (int r = tid; r < rows; r += NT) {
+    double acc = 0.0;
+    int k = rp_lds[r] - e0;
+    const int k1 = rp_lds[r + 1] - e0;
+    for (; k + U <= k1; k += U) {
+      T t[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) t[u] = pl[k + u];
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc += (double)t[u];
+    }
+    for (; k < k1; ++k) acc += (double)pl[k];
+    w[r] = (T)(acc * sj);
+  }
+}
+
 // ------------------------------------------------------------------------------- standalone y = A x
 template <typename T, bool HAS_VAL, int L>
 __global__ __launch_bounds__(kBlock) void k_spmv_direct_1(int32_t n, const int32_t* rp, const int32_t* ci,
@@ -954,6 +1285,15 @@ hipError_t step_direct(int lanes, int j, const LzArgs& a, int64_t nb, hipStream_
 
 template <typename T, bool HAS_VAL>
 hipError_t step_any(int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s) {
+  if (a.pan_cols > 0) {
+    hipLaunchKernelGGL((k_pan_products<T, HAS_VAL>), dim3((unsigned)a.pan_nitems), dim3(kPanProdThreads),
+                       (size_t)a.pan_cols * sizeof(T), s, a, j);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_pan_rows<T, HAS_VAL>), dim3((unsigned)(nb * (kRowsPerBlock / a.pan_unit))),
+                       dim3(kPanRowThreads), pan_rows_lds<T>(a.pan_lds, a.pan_pmax), s, a, j);
+    return hipGetLastError();
+  }
   if (a.bal != nullptr) {
     if (j == 0 && a.unit_start)
       hipLaunchKernelGGL((k_spmv_bal<T, HAS_VAL, true>), dim3((unsigned)a.nbal), dim3(kBlock), 0, s, a, j);
@@ -1057,6 +1397,61 @@ hipError_t prepare_seg_kernels() {
 
 int seg_max_cols(int dtype) {
   return dtype == EBTC_F64 ? SegShape<double>::MAXCOLS : SegShape<float>::MAXCOLS;
+}
+
+namespace {
+
+template <typename T>
+hipError_t prepare_pan_t() {
+  hipError_t e = allow_lds(k_pan_products<T, true>, PanShape<T>::MAXCOLS * sizeof(T));
+  if (e == hipSuccess) e = allow_lds(k_pan_products<T, false>, PanShape<T>::MAXCOLS * sizeof(T));
+  const size_t rows_max = pan_rows_lds<T>(pan_max_lds(sizeof(T) == 8 ? EBTC_F64 : EBTC_F32), kPanMaxPanels);
+  if (e == hipSuccess) e = allow_lds(k_pan_rows<T, true>, rows_max);
+  if (e == hipSuccess) e = allow_lds(k_pan_rows<T, false>, rows_max);
+  return e;
+}
+
+}  // namespace
+
+hipError_t prepare_pan_kernels() {
+  static hipError_t e = [] {
+    hipError_t r = prepare_pan_t<float>();
+    if (r == hipSuccess) r = prepare_pan_t<double>();
+    return r;
+  }();
+  return e;
+}
+
+int pan_max_cols(int dtype) { return dtype == EBTC_F64 ? PanShape<double>::MAXCOLS : PanShape<float>::MAXCOLS; }
+
+int pan_max_lds(int dtype) { return (int)(kPanCapBytes / (dtype == EBTC_F64 ? 8 : 4)); }
+
+int stream_cap(int dtype) { return dtype == EBTC_F64 ? StreamShape<double>::CAP : StreamShape<float>::CAP; }
+
+hipError_t launch_pan_prepare(int dtype, bool has_val, const LzArgs& a, int64_t nb, const PanItem* groups,
+                              int ngroups, hipStream_t s) {
+  if (a.pan_cols <= 0 || a.pan_cols > pan_max_cols(dtype) || a.pan_pmax < 1 || a.pan_pmax > kPanMaxPanels ||
+      (a.pan_unit != 64 && a.pan_unit != 128 && a.pan_unit != 256) || a.pan_lds < 1 || a.pan_lds > pan_max_lds(dtype) ||
+      a.pan_lds > 65536)
+    return hipErrorInvalidValue;
+  const dim3 g((unsigned)(nb * (kRowsPerBlock / a.pan_unit))), b(kPanPrepThreads);
+  if (dtype == EBTC_F64) hipLaunchKernelGGL((k_pan_count<double>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_pan_count<float>), g, b, 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (ngroups > 0) {
+    hipLaunchKernelGGL(k_pan_scan, dim3((unsigned)ngroups), dim3(kPanScanThreads), 0, s, a, groups);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (dtype == EBTC_F64) {
+    if (has_val) hipLaunchKernelGGL((k_pan_place<double, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_pan_place<double, false>), g, b, 0, s, a);
+  } else {
+    if (has_val) hipLaunchKernelGGL((k_pan_place<float, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_pan_place<float, false>), g, b, 0, s, a);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_bal_rows(const LzArgs& a, int t0, int count, hipStream_t s) {

@@ -46,8 +46,10 @@ struct StreamShape {
 // product's arithmetic, for a caller that must reproduce it).
 // RP_LDS: rp_lds already holds the rows' pointers (rp unused). NT_LOADS: the entries are read with the
 // non-temporal policy (they live in HBM and are read once per product); off when they sit in LDS.
+// HUB_NT: a row beyond the capacity is reduced in the order of a workgroup of HUB_NT threads (the
+// first HUB_NT threads form the per-thread sums; the other waves add exact zeros).
 template <typename T, bool HAS_VAL, int NT = kBlock, int CAP = StreamShape<T>::CAP, bool SEQ_HUB = false,
-          bool RP_LDS = false, bool NT_LOADS = true>
+          bool RP_LDS = false, bool NT_LOADS = true, int HUB_NT = NT>
 __device__ inline void spmv_stream_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                         const T* __restrict__ va, const T* __restrict__ x, int r0, int rows,
                                         double scale, int* rp_lds, T* prod, T* w_out, double* red) {
@@ -73,12 +75,14 @@ __device__ inline void spmv_stream_rows(const int32_t* __restrict__ rp, const in
       continue;
     }
     if (rp_lds[ra + 1] - nz0 > CAP) {  // hub row: whole workgroup, direct gathers
+      static_assert(HUB_NT <= NT && HUB_NT % 64 == 0, "hub reduction layout");
       const int e = rp_lds[ra + 1];
       T acc = 0;
-      for (int k = nz0 + tid; k < e; k += NT) {
-        const T xv = x[ci[k]];
-        if constexpr (HAS_VAL) acc += va[k] * xv; else acc += xv;
-      }
+      if (tid < HUB_NT)
+        for (int k = nz0 + tid; k < e; k += HUB_NT) {
+          const T xv = x[ci[k]];
+          if constexpr (HAS_VAL) acc += va[k] * xv; else acc += xv;
+        }
       const double tot = block_sum<NT>((double)acc, red);
       if (tid == 0) w_out[ra] = (T)(tot * scale);
       ++ra;
@@ -151,6 +155,11 @@ __device__ inline void block_dots(const T* __restrict__ Vr, int n, int lo, int j
 #pragma unroll 1
   for (int t0 = 0; t0 < NT; t0 += NREAL) {
     const int vt = t0 + tid;  // the thread of NT whose sums this pass forms
+    constexpr int LP0 = 64 / P;
+    if (NREAL < NT && t0 >= r1 - r0) {  // no rows in this pass: its partials are zeros
+      if ((tid & 63) % LP0 == 0) red[(vt >> 6) * P + (tid & 63) / LP0] = 0.0;
+      continue;
+    }
     T p[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) p[i] = 0;

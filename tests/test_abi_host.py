@@ -202,7 +202,7 @@ def test_plan_segmented_workspace_arithmetic():
     (dict(m=0, m_max=129), "m_max"),
     (dict(m=0, tol=0.0), "tol"), (dict(reorth=3), "reorth"), (dict(schedule=9), "schedule"),
     (dict(lanes_per_row=5), "lanes_per_row"), (dict(hub_threshold=-1), "hub_threshold"),
-    (dict(seg_len=-1), "seg_len"), (dict(spmv=6), "spmv form"), (dict(spmv=-1), "spmv form"),
+    (dict(seg_len=-1), "seg_len"), (dict(spmv=7), "spmv form"), (dict(spmv=-1), "spmv form"),
 ])
 def test_plan_rejects_bad_opts(kw, text):
     d, keep = make_desc()
