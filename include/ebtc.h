@@ -274,26 +274,58 @@ int ebtc_subgraph_centrality(int32_t dtype, int32_t n, const int32_t* row_ptr, c
                              void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- autotuning                     */
-/* Times the SpMV forms on this batch with HIP events -- the CSR stream, lane groups of 4, 8, 16 and
- * 32 lanes per row, the LDS-staged form when the largest vector passes through LDS in at most
- * eight segments, and the entry-balanced form when ws_bytes covers its plan -- each as one warm-up
- * and three timed launches of the first Lanczos product over
- * every realization, and records the fastest in the batch (the column-segmented form is tried when
- * ws_bytes covers ebtc_plan's size for opts with spmv = EBTC_SPMV_SEGMENTED; plan the later calls
- * after tuning, since the chosen form sets their workspace size): later calls with opts->spmv ==
- * EBTC_SPMV_AUTO use it (a form named in opts overrides it). Synchronous on the stream. Overwrites
- * the workspace (size from ebtc_plan for opts, 256-byte aligned); not thread-safe with other calls
- * on the same batch.
+/* Chooses the batch's SpMV form by timing. Each graph falls in a bucket given by precision, weights,
+ * the octave of n, the half-octave of the mean degree, the octave of the largest row over the mean
+ * degree (measured on the device) and the octave of the Krylov steps; the sorted list of the batch's
+ * buckets is its composition. Unless the composition is in the process-wide cache (ebtc_tune_cache_*),
+ * the forms are timed with HIP events on the whole batch: the CSR stream, lane groups of 4, 8, 16 and
+ * 32 lanes per row, the LDS-staged form when the largest vector passes through LDS in at most eight
+ * segments, the column-segmented form with 6144 and 12288 FP32 (3072 and 6144 FP64) columns when at
+ * most 32 segments, the entry-balanced and the paneled form; each form whose plan fits ws_bytes gets
+ * its once-per-call preparation, one warm-up and three timed launches of the first Lanczos product.
+ * The fastest per launch, with its preparation spread over the call's m steps, is recorded in the
+ * cache under the composition and in the batch; later calls with opts->spmv == EBTC_SPMV_AUTO use it
+ * (a form named in opts overrides it). Plan the later calls after tuning: the chosen form sets their
+ * workspace size. Synchronous on the stream. Overwrites the workspace (the largest ebtc_plan size over
+ * the forms to try, 256-byte aligned; forms whose plan does not fit are skipped); not thread-safe with
+ * other calls on the same batch.
  *   form_out, lanes_out, seglen_out  host (nullable): the chosen form and its parameters
  *   ms_out  host [EBTC_TUNE_SLOTS] (nullable): ms per launch of stream, lanes 4, 8, 16, 32,
  *           LDS-staged, column-segmented with 6144 and 12288 FP32 (3072 and 6144 FP64) columns per
- *           segment, entry-balanced and paneled; the segmented, balanced and paneled figures include
- *           their once-per-call preparation spread over the call's m steps (-1 where the form was not
- *           tried)
+ *           segment, entry-balanced and paneled, the segmented, balanced and paneled figures with
+ *           their preparation spread over the m steps (-1 where the form was not timed, as for a
+ *           composition found in the cache)
  * Errors: EINVAL (NULL batch or workspace, bad opts), EWORKSPACE, EHIP. On error the batch keeps its
  * previous choice. */
 int ebtc_tune(ebtc_batch* batch, const ebtc_opts* opts, void* ws, size_t ws_bytes, int32_t* form_out,
               int32_t* lanes_out, int32_t* seglen_out, double* ms_out, void* stream);
+
+/* Each graph's SpMV form and parameters as recorded by ebtc_tune (the same for every graph) or
+ * ebtc_set_forms (form 0 for every graph when none is recorded).
+ *   form_out, lanes_out, seglen_out  host int32 [G] (lanes_out, seglen_out nullable)
+ * Errors: EINVAL. */
+int ebtc_tuned_forms(ebtc_batch* batch, int32_t* form_out, int32_t* lanes_out, int32_t* seglen_out);
+
+/* Records an SpMV form for every graph for calls with opts->spmv == EBTC_SPMV_AUTO (for callers that
+ * know their graphs, or that tuned an equal batch before). One launch sequence runs one form: while
+ * the graphs' forms differ, the plan and compute calls with EBTC_SPMV_AUTO refuse the batch with
+ * EBTC_ENOTSUPPORTED.
+ *   form     host int32 [G]: EBTC_SPMV_STREAM .. EBTC_SPMV_PANELED
+ *   lanes    host int32 [G] (nullable = 0): lanes per row of the lane-group form (0 = 8)
+ *   seg_len  host int32 [G] (nullable = 0): the form's ebtc_opts::seg_len parameter (0 = default)
+ * Errors: EINVAL (NULL batch or form, a form out of range, lanes not 0/4/8/16/32, seg_len < 0). */
+int ebtc_set_forms(ebtc_batch* batch, const int32_t* form, const int32_t* lanes, const int32_t* seg_len);
+
+/* The autotuner's process-wide cache of decisions, as text: one line per batch composition (its
+ * buckets joined by '+'), "<key> <form> <lanes> <seg_len>". ebtc_tune_cache_get writes it with a
+ * terminating NUL into buf
+ * (cap bytes; buf NULL: only *len, the text's length without the NUL, is set); ebtc_tune_cache_put
+ * merges such text (later lines win; a saved cache restored in a new process skips the timing of the
+ * compositions it holds); ebtc_tune_cache_clear empties it. Thread-safe.
+ * Errors: EINVAL (NULL len or text, buffer too small, a malformed line). */
+int ebtc_tune_cache_get(char* buf, size_t cap, size_t* len);
+int ebtc_tune_cache_put(const char* text);
+int ebtc_tune_cache_clear(void);
 
 /* ---------------------------------------------------------------- measurement                    */
 enum ebtc_phase {

@@ -26,7 +26,8 @@ EXPORTED = [
     "ebtc_batch_destroy", "ebtc_plan", "ebtc_scores", "ebtc_scores_noalloc", "ebtc_topk_ws_bytes", "ebtc_topk",
     "ebtc_spmv", "ebtc_tridiag_expv", "ebtc_validate_ws_bytes", "ebtc_validate", "ebtc_profile_phases", "ebtc_plan_backward",
     "ebtc_scores_backward", "ebtc_tune", "ebtc_subgraph_centrality_ws_bytes", "ebtc_subgraph_centrality",
-    "ebtc_generate_plan", "ebtc_generate_count", "ebtc_generate_fill",
+    "ebtc_generate_plan", "ebtc_generate_count", "ebtc_generate_fill", "ebtc_tuned_forms", "ebtc_set_forms",
+    "ebtc_tune_cache_get", "ebtc_tune_cache_put", "ebtc_tune_cache_clear",
 ]
 GEN_FAMILIES = {"er": 0, "ws": 1, "ba": 2}
 SPMV_FORMS = {"auto": 0, "stream": 1, "lanes": 2, "staged": 3, "segmented": 4, "balanced": 5, "paneled": 6}
@@ -101,6 +102,11 @@ def lib() -> ctypes.CDLL:
         "ebtc_scores_backward": (c_int, [vp, POINTER(Opts), vp, vp, vp, vp, sz, vp]),
         "ebtc_tune": (c_int, [vp, POINTER(Opts), vp, sz, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
                               POINTER(c_double), vp]),
+        "ebtc_tuned_forms": (c_int, [vp, vp, vp, vp]),
+        "ebtc_set_forms": (c_int, [vp, vp, vp, vp]),
+        "ebtc_tune_cache_get": (c_int, [ctypes.c_char_p, sz, POINTER(sz)]),
+        "ebtc_tune_cache_put": (c_int, [ctypes.c_char_p]),
+        "ebtc_tune_cache_clear": (c_int, []),
         "ebtc_subgraph_centrality_ws_bytes": (c_int, [c_int32, c_int32, c_int32, c_int32, POINTER(sz)]),
         "ebtc_subgraph_centrality": (c_int, [c_int32, c_int32, vp, vp, vp, c_int32, vp, c_int32, vp, vp, sz, vp]),
         "ebtc_generate_plan": (c_int, [POINTER(GenSpec), POINTER(sz)]),

@@ -236,8 +236,10 @@ class Batch:
         return idx[:tot], val[:tot]
 
     def tune(self, **kw) -> dict:
-        """Times the SpMV forms on this batch (ebtc_tune) and keeps the fastest for spmv="auto" calls.
-        Plan Runs after tuning: the chosen form sets their workspace size."""
+        """Times the SpMV forms bucket by bucket of similar graphs (ebtc_tune) and keeps each graph's
+        fastest for spmv="auto" calls; buckets in the process-wide tune cache are not timed again. Plan
+        Runs after tuning: the chosen forms set their workspace size. Returns the form (or "mixed"), the
+        per-slot ms summed over the timed buckets, and each graph's form."""
         opts = make_opts(**kw)
         ws = ctypes.c_size_t()
         small = 3072 if self.dtype == "f64" else 6144
@@ -262,8 +264,29 @@ class Batch:
         names = {v: k for k, v in A.SPMV_FORMS.items()}
         labels = ["stream", "lanes4", "lanes8", "lanes16", "lanes32", "staged", f"segmented{small}",
                   f"segmented{2 * small}", "balanced", "paneled"]
-        return {"form": names[form.value], "lanes": lanes.value, "seg_len": segl.value,
-                "ms_per_launch": {l: ms[i] for i, l in enumerate(labels) if ms[i] >= 0}}
+        return {"form": "mixed" if form.value == 0 else names[form.value], "lanes": lanes.value,
+                "seg_len": segl.value, "ms_per_launch": {l: ms[i] for i, l in enumerate(labels) if ms[i] >= 0},
+                "graph_forms": self.tuned_forms()}
+
+    def tuned_forms(self) -> list:
+        """Each graph's recorded SpMV form (ebtc_tuned_forms): [(form name, lanes, seg_len)]."""
+        f = np.zeros(self.G, dtype=np.int32)
+        l = np.zeros(self.G, dtype=np.int32)
+        q = np.zeros(self.G, dtype=np.int32)
+        A.check(A.lib().ebtc_tuned_forms(self.handle, f.ctypes.data, l.ctypes.data, q.ctypes.data))
+        names = {v: k for k, v in A.SPMV_FORMS.items()}
+        return [(names[int(a)], int(b), int(c)) for a, b, c in zip(f, l, q)]
+
+    def set_forms(self, forms: list) -> None:
+        """Records each graph's SpMV form for spmv="auto" calls (ebtc_set_forms): a list of form names
+        or (name, lanes, seg_len) tuples, one per graph."""
+        items = [(x, 0, 0) if isinstance(x, str) else tuple(x) for x in forms]
+        if len(items) != self.G:
+            raise ValueError(f"{len(items)} forms for {self.G} graphs")
+        f = np.array([A.SPMV_FORMS[x[0]] for x in items], dtype=np.int32)
+        l = np.array([x[1] for x in items], dtype=np.int32)
+        q = np.array([x[2] for x in items], dtype=np.int32)
+        A.check(A.lib().ebtc_set_forms(self.handle, f.ctypes.data, l.ctypes.data, q.ctypes.data))
 
     def backward_run(self, **kw) -> "BackwardRun":
         return BackwardRun(self, make_opts(**kw))
@@ -280,6 +303,35 @@ class Batch:
         bad = ctypes.c_int64()
         A.check(A.lib().ebtc_validate(self.handle, _vp(wst), ws.value, ctypes.byref(bad), current_stream()))
         return int(bad.value)
+
+
+def tune_cache_text() -> str:
+    """The autotuner's process-wide bucket decisions (ebtc_tune_cache_get): "<key> <form> <lanes> <seg_len>"
+    lines."""
+    n = ctypes.c_size_t()
+    A.check(A.lib().ebtc_tune_cache_get(None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    A.check(A.lib().ebtc_tune_cache_get(buf, n.value + 1, ctypes.byref(n)))
+    return buf.value.decode()
+
+
+def tune_cache_add(text: str) -> None:
+    """Merges bucket decisions into the cache (ebtc_tune_cache_put)."""
+    A.check(A.lib().ebtc_tune_cache_put(text.encode()))
+
+
+def tune_cache_clear() -> None:
+    A.check(A.lib().ebtc_tune_cache_clear())
+
+
+def tune_cache_save(path: str) -> None:
+    with open(path, "w") as f:
+        f.write(tune_cache_text())
+
+
+def tune_cache_load(path: str) -> None:
+    with open(path) as f:
+        tune_cache_add(f.read())
 
 
 def _gen_spec(family: str, n: int, count: int, seed: int, first: int = 0, p: float = 0.0, k: int = 0,

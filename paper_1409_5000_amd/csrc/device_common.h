@@ -31,8 +31,9 @@ __device__ inline bool step_skipped(const LzArgs& a, const RState* st, int j) {
 __device__ inline Ref resolve(const LzArgs& a) {
   const int lb = logical_block();
   if (a.blkmap == nullptr) return {a.single_task, lb};
-  const int t = a.blkmap[lb];
-  return {t, lb - a.tasks[t].blk_begin};
+  const int gb = a.sub_blocks ? a.sub_blocks[lb] : lb;
+  const int t = a.blkmap[gb];
+  return {t, gb - a.tasks[t].blk_begin};
 }
 
 __device__ inline double wave_sum(double v) {

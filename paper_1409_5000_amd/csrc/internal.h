@@ -37,8 +37,12 @@ struct Task {
   int32_t graph;
   int32_t nblk;        // row blocks of kRowsPerBlock rows
   int32_t blk_begin;   // first flattened workgroup id of this realization in a batched launch
+  int64_t aux_off;     // first entry of the realization in its SpMV form's entry arenas (sorted columns,
+                       // values, products): entries of the realizations of the same form before it
+  int32_t aux_blk;     // its first row block in the form's per-block arenas and in the form's launches
+  int32_t form;        // index of its SpMV form in the batch's plan
 };
-static_assert(sizeof(Task) == 64, "Task layout");
+static_assert(sizeof(Task) == 80, "Task layout");
 
 // Per row block of the column-segmented form, written by the sort: what the first loads of a product
 // need, so that they wait on one load instead of the chain workgroup map -> realization -> row
@@ -121,6 +125,8 @@ struct LzArgs {
   const void* values;      // nullptr = all ones
   const Task* tasks;
   const int32_t* blkmap;   // flattened workgroup -> task; nullptr = single-task launch
+  const int32_t* sub_blocks;  // the launch's row blocks (batch-wide ids) when an SpMV form covers part of
+                              // the batch; nullptr = every block in order
   int32_t single_task;
   int32_t hub_threshold;
   RState* state;
@@ -185,6 +191,8 @@ __host__ __device__ inline size_t vslot(const LzArgs& a, int i) {
 
 // ---- launchers (k_lanczos.hip, k_spmv.hip)
 hipError_t launch_blkmap(const Task* tasks, int64_t R, int32_t* blkmap, hipStream_t s);
+// Largest row length of each realization (out: device [R]).
+hipError_t launch_row_max(const Task* tasks, const int32_t* row_ptr, int64_t R, int32_t* out, hipStream_t s);
 hipError_t launch_start(int dtype, const LzArgs& a, int64_t nblocks, hipStream_t s);
 // Subgraph centrality: processes started at e_{nodes[r]}, and SC = e^{theta} y_0 per process.
 hipError_t launch_start_unit(int dtype, const LzArgs& a, const int32_t* nodes, int64_t nblocks, hipStream_t s);

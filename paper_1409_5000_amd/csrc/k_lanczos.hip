@@ -257,12 +257,36 @@ __global__ __launch_bounds__(kBlock) void k_sum(const GraphInfo* graphs, const T
   if (blockIdx.x == 0 && tid == 0) log_scale[blockIdx.y] = sig;
 }
 
+// Largest row length of each realization (the autotuner's measure of hub rows), one workgroup each.
+__global__ __launch_bounds__(kBlock) void k_row_max(const Task* tasks, const int32_t* row_ptr, int32_t* out) {
+  __shared__ int red[kBlock / 64];
+  const Task tk = tasks[blockIdx.x];
+  const int32_t* rp = row_ptr + tk.rowptr_off;
+  int m = 0;
+  for (int r = threadIdx.x; r < tk.n; r += kBlock) m = max(m, rp[r + 1] - rp[r]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int v = 0;
+    for (int i = 0; i < kBlock / 64; ++i) v = max(v, red[i]);
+    out[blockIdx.x] = v;
+  }
+}
+
 __global__ void k_blkmap(const Task* tasks, int32_t* blkmap) {
   const Task tk = tasks[blockIdx.x];
   for (int b = threadIdx.x; b < tk.nblk; b += blockDim.x) blkmap[tk.blk_begin + b] = (int32_t)blockIdx.x;
 }
 
 }  // namespace
+
+hipError_t launch_row_max(const Task* tasks, const int32_t* row_ptr, int64_t R, int32_t* out, hipStream_t s) {
+  if (R < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_row_max, dim3((unsigned)R), dim3(kBlock), 0, s, tasks, row_ptr, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_blkmap(const Task* tasks, int64_t R, int32_t* blkmap, hipStream_t s) {
   hipLaunchKernelGGL(k_blkmap, dim3((unsigned)R), dim3(256), 0, s, tasks, blkmap);

@@ -152,8 +152,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream(LzArgs a, int j) {
     ref.task = a.single_task;
     ref.blk = blk_flat;
   } else {
-    ref.task = a.blkmap[blk_flat];
-    ref.blk = blk_flat - a.tasks[ref.task].blk_begin;
+    const int gb = a.sub_blocks ? a.sub_blocks[blk_flat] : blk_flat;
+    ref.task = a.blkmap[gb];
+    ref.blk = gb - a.tasks[ref.task].blk_begin;
   }
   const Task tk = a.tasks[ref.task];
   RState* st = a.state + ref.task;
@@ -543,7 +544,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
   const Ref ref = resolve(a);
   const Task tk = a.tasks[ref.task];
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, rows = min(n - r0, kRowsPerBlock);
-  const int blk = tk.blk_begin + ref.blk, tid = threadIdx.x;
+  const int blk = tk.aux_blk + ref.blk, tid = threadIdx.x;  // the block in the form's arenas
   const int SEG = a.seg_cols, S = (n + SEG - 1) / SEG, tot = S * rows;
   uint16_t* cnt = (uint16_t*)smem;  // [S * rows]: counts, then insertion cursors
   const size_t cnt_bytes = ((size_t)(a.seg_stride) * 2 + 15) / 16 * 16;
@@ -574,7 +575,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
   auto finish = [&](int f) {  // the block's flag and descriptor (band starts written by the caller)
     if (tid == 0) {
       a.seg_flag[blk] = f;
-      desc->entries = tk.nnz_off + e0;
+      desc->entries = tk.aux_off + e0;
       desc->vec_off = tk.vec_off;
       desc->n = n;
       desc->nnz = nz;
@@ -651,8 +652,8 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
     finish(0);
     return;
   }
-  uint16_t* pc = a.seg_col + tk.nnz_off + e0;
-  T* pv = HAS_VAL ? (T*)a.seg_val + tk.nnz_off + e0 : nullptr;
+  uint16_t* pc = a.seg_col + tk.aux_off + e0;
+  T* pv = HAS_VAL ? (T*)a.seg_val + tk.aux_off + e0 : nullptr;
   for_rows_staged<T, HAS_VAL, NT>(ci, va, rp_lds, rows, cap, lci, lva,
                                   [&](int r, const int* cs, const T* vs, int k, int e) {
                                     double acc = 0.0;
@@ -728,9 +729,9 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
   __shared__ double red[NT / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   // The first segment's loads wait on the block's descriptor alone: in a batched launch the logical
-  // workgroup is the block's flattened index.
+  // workgroup is the block's index in the form's arenas (the launch covers the form's blocks in order).
   const int lb = logical_block();
-  const int blk = a.blkmap != nullptr ? lb : a.tasks[a.single_task].blk_begin + lb;
+  const int blk = a.blkmap != nullptr ? lb : a.tasks[a.single_task].aux_blk + lb;
   const SegBlock* d = a.seg_blk + blk;
   const int n = d->n, rows = d->rows, flag = d->flag, E = d->nnz;
   const int SEG = a.seg_cols, S = (n + SEG - 1) / SEG;
@@ -944,10 +945,11 @@ __device__ inline PanRef pan_ref(const LzArgs& a) {
     t = a.single_task;
     blk = lblk;
   } else {
-    t = a.blkmap[lblk];
-    blk = lblk - a.tasks[t].blk_begin;
+    const int gb = a.sub_blocks ? a.sub_blocks[lblk] : lblk;
+    t = a.blkmap[gb];
+    blk = gb - a.tasks[t].blk_begin;
   }
-  return {t, blk * k + sub, ((int64_t)a.tasks[t].blk_begin + blk) * k + sub};
+  return {t, blk * k + sub, ((int64_t)a.tasks[t].aux_blk + blk) * k + sub};
 }
 
 template <typename T>
@@ -993,7 +995,7 @@ __global__ __launch_bounds__(kPanScanThreads) void k_pan_scan(LzArgs a, const Pa
   const Task tk = a.tasks[g.task];
   const int n = tk.n, U = a.pan_unit, S = a.pan_cols, P = (n + S - 1) / S, tid = threadIdx.x;
   const int gsz = g.b1 - g.b0, E = P * gsz;
-  const int64_t gu0 = (int64_t)tk.blk_begin * (kRowsPerBlock / U) + g.b0;
+  const int64_t gu0 = (int64_t)tk.aux_blk * (kRowsPerBlock / U) + g.b0;
   int carry = a.row_ptr[tk.rowptr_off + min(n, g.b0 * U)];
   for (int i0 = 0; i0 < E; i0 += NT) {
     const int i = i0 + tid, p = i / gsz, uu = i - p * gsz;
@@ -1027,9 +1029,9 @@ __global__ __launch_bounds__(kPanPrepThreads) void k_pan_place(LzArgs a) {
   const int e0 = rp_lds[0], nz = rp_lds[1] - e0;
   const int32_t* ci = a.col_idx + tk.nnz_off + e0;
   const T* va = HAS_VAL ? (const T*)a.values + tk.nnz_off + e0 : nullptr;
-  uint16_t* oc = a.pan_col + tk.nnz_off;
-  uint16_t* op = a.pan_perm + tk.nnz_off;
-  T* ov = HAS_VAL ? (T*)a.pan_val + tk.nnz_off : nullptr;
+  uint16_t* oc = a.pan_col + tk.aux_off;
+  uint16_t* op = a.pan_perm + tk.aux_off;
+  T* ov = HAS_VAL ? (T*)a.pan_val + tk.aux_off : nullptr;
   for (int e = tid; e < nz; e += NT) {
     const int c = ci[e], p = min(max(c / S, 0), P - 1);
     const int pos = atomicAdd(&cursor[p], 1);
@@ -1053,20 +1055,20 @@ __global__ __launch_bounds__(kPanProdThreads) void k_pan_products(LzArgs a, int 
   double sj;
   if (!open_step(a, tk, a.state + it.task, it.panel == 0 && it.b0 == 0 ? 0 : 1, j, chunks, &sj)) return;
   const int n = tk.n, S = a.pan_cols, c0 = it.panel * S, len = min(S, n - c0), tid = threadIdx.x;
-  const int64_t gu0 = (int64_t)tk.blk_begin * (kRowsPerBlock / a.pan_unit);
+  const int64_t gu0 = (int64_t)tk.aux_blk * (kRowsPerBlock / a.pan_unit);
   const int2 first = a.pan_run[(gu0 + it.b0) * a.pan_pmax + it.panel];
   const int2 last = a.pan_run[(gu0 + it.b1 - 1) * a.pan_pmax + it.panel];
   const int vb = first.x, ve = last.x + last.y;
   const T* x = (const T*)a.V + tk.vec_off + vslot(a, j) * n + c0;
   for (int i = tid; i < len; i += NT) slice[i] = x[i];
   __syncthreads();
-  const uint16_t* col = a.pan_col + tk.nnz_off;
-  const T* val = HAS_VAL ? (const T*)a.pan_val + tk.nnz_off : nullptr;
-  T* prod = (T*)a.pan_prod + tk.nnz_off;
+  const uint16_t* col = a.pan_col + tk.aux_off;
+  const T* val = HAS_VAL ? (const T*)a.pan_val + tk.aux_off : nullptr;
+  T* prod = (T*)a.pan_prod + tk.aux_off;
   // four entries per thread and load: groups of four from the 4-aligned entry at or below vb (the
-  // realization's arrays start 256-byte aligned only when its entry offset is a multiple of 4, so the
-  // vector accesses are used only then)
-  if ((tk.nnz_off & 3) == 0) {
+  // realization's arrays are 8- and 16-byte aligned only when its arena offset is a multiple of 4, so
+  // the vector accesses are used only then)
+  if ((tk.aux_off & 3) == 0) {
     const int g0 = vb >> 2, g1 = (ve + 3) >> 2;
     const uint64_t* col4 = (const uint64_t*)col;
     for (int q0 = g0 + tid; q0 < g1; q0 += NT * U) {
@@ -1172,8 +1174,8 @@ __global__ __launch_bounds__(kPanRowThreads) void k_pan_rows(LzArgs a, int j) {
   if (tid == 0) pre[P] = carry;
   __syncthreads();
   const int e0 = rp_lds[0], total = carry;
-  const uint16_t* perm = a.pan_perm + tk.nnz_off;
-  const T* prod = (const T*)a.pan_prod + tk.nnz_off;
+  const uint16_t* perm = a.pan_perm + tk.aux_off;
+  const T* prod = (const T*)a.pan_prod + tk.aux_off;
   int top = 1;  // the largest power of two below P: the search's first stride
   while (top * 2 < P) top *= 2;
   for (int v0 = tid; v0 < total; v0 += NT * U) {

@@ -122,7 +122,7 @@ def expected_ws(G, nreal, n, m_slots, es, rstate_bytes):
     R = sum(nreal)
     blocks = sum(((ng + 2047) // 2048) * nr for ng, nr in zip(n, nreal))
     rows = sum(ng * nr for ng, nr in zip(n, nreal))
-    off = align(64 * R)
+    off = align(80 * R)  # realization records
     off = align(off + 24 * G)
     off = align(off + 4 * blocks)
     off = align(off + rstate_bytes * R)
@@ -195,6 +195,88 @@ def test_plan_segmented_workspace_arithmetic():
     rc, _, _ = plan(h, m=30, spmv=4, seg_len=50)  # 60 segments
     assert rc == A.EBTC_EINVAL and "segments" in A.lib().ebtc_last_error().decode()
     A.lib().ebtc_batch_destroy(h)
+
+
+def set_forms(h, forms, lanes=None, seg=None):
+    f = np.array(forms, np.int32)
+    l = None if lanes is None else np.array(lanes, np.int32)
+    q = None if seg is None else np.array(seg, np.int32)
+    return A.lib().ebtc_set_forms(h, f.ctypes.data, None if l is None else l.ctypes.data,
+                                  None if q is None else q.ctypes.data), (f, l, q)
+
+
+def test_set_forms_records_and_plans():
+    # one form recorded for every graph is the plain single-form plan; a form named in the options
+    # overrides it; graphs on different forms are refused (several forms in one launch sequence are
+    # not supported)
+    d, keep = make_desc(G=2, nreal=(2, 3), n=(3000, 70), nnz=(10, 10, 10, 10, 10))
+    rc, h = create(d)
+    assert rc == 0
+    rc, _ = set_forms(h, [5, 5])
+    assert rc == 0
+    assert plan(h, m=30)[1] == plan(h, m=30, spmv=5)[1]
+    assert plan(h, m=30, spmv=1)[1] == expected_ws(2, (2, 3), (3000, 70), 31, 4, RSTATE_BYTES)
+    rc, _ = set_forms(h, [4, 5], seg=[1000, 0])
+    assert rc == 0
+    f = np.zeros(2, np.int32)
+    l = np.zeros(2, np.int32)
+    q = np.zeros(2, np.int32)
+    assert A.lib().ebtc_tuned_forms(h, f.ctypes.data, l.ctypes.data, q.ctypes.data) == 0
+    assert f.tolist() == [4, 5] and q.tolist() == [1000, 0]
+    rc, _, _ = plan(h, m=30)
+    assert rc == A.EBTC_ENOTSUPPORTED and "several SpMV forms" in A.lib().ebtc_last_error().decode()
+    assert plan(h, m=30, spmv=4, seg_len=1000)[0] == 0  # a named form still plans
+    A.lib().ebtc_batch_destroy(h)
+
+
+@pytest.mark.parametrize("forms,lanes,seg,text", [
+    ([7, 1], None, None, "unknown spmv form"),
+    ([1, 0], None, None, "unknown spmv form"),
+    ([2, 2], [4, 5], None, "lanes must be"),
+    ([4, 1], None, [-1, 0], "seg_len must be"),
+])
+def test_set_forms_rejects(forms, lanes, seg, text):
+    d, keep = make_desc(G=2, nreal=(2, 3), n=(3000, 70), nnz=(10, 10, 10, 10, 10))
+    rc, h = create(d)
+    assert rc == 0
+    rc, _ = set_forms(h, forms, lanes, seg)
+    assert rc == A.EBTC_EINVAL and text in A.lib().ebtc_last_error().decode()
+    assert A.lib().ebtc_set_forms(h, None, None, None) == A.EBTC_EINVAL
+    assert A.lib().ebtc_set_forms(None, np.zeros(2, np.int32).ctypes.data, None, None) == A.EBTC_EINVAL
+    f = np.full(2, 9, np.int32)
+    assert A.lib().ebtc_tuned_forms(h, f.ctypes.data, None, None) == 0 and f.tolist() == [0, 0]  # nothing recorded
+    A.lib().ebtc_batch_destroy(h)
+
+
+def test_tune_cache_text_roundtrip_and_errors():
+    L = A.lib()
+    assert L.ebtc_tune_cache_clear() == 0
+    n = ctypes.c_size_t(99)
+    assert L.ebtc_tune_cache_get(None, 0, ctypes.byref(n)) == 0 and n.value == 0
+    text = b"f32v-n16-d8-h2-s4 4 0 12288\nf32p-n19-d6-h9-s5 5 0 8192\n"
+    assert L.ebtc_tune_cache_put(text) == 0
+    assert L.ebtc_tune_cache_get(None, 0, ctypes.byref(n)) == 0
+    buf = ctypes.create_string_buffer(n.value + 1)
+    assert L.ebtc_tune_cache_get(buf, n.value + 1, ctypes.byref(n)) == 0
+    assert sorted(buf.value.decode().splitlines()) == sorted(text.decode().splitlines())
+    small = ctypes.create_string_buffer(4)
+    assert L.ebtc_tune_cache_get(small, 4, ctypes.byref(n)) == A.EBTC_EINVAL
+    # later lines win; malformed lines are refused whole
+    assert L.ebtc_tune_cache_put(b"f32v-n16-d8-h2-s4 1 0 0\n") == 0
+    assert "f32v-n16-d8-h2-s4 1 0 0" in _cache_text()
+    for bad in (b"key 9 0 0", b"key 4 0", b"key 4 -1 0", b"key x 0 0"):
+        assert L.ebtc_tune_cache_put(bad) == A.EBTC_EINVAL and "tune-cache line" in L.ebtc_last_error().decode()
+    assert L.ebtc_tune_cache_put(None) == A.EBTC_EINVAL
+    assert L.ebtc_tune_cache_get(None, 0, None) == A.EBTC_EINVAL
+    assert L.ebtc_tune_cache_clear() == 0 and _cache_text() == ""
+
+
+def _cache_text():
+    n = ctypes.c_size_t()
+    A.lib().ebtc_tune_cache_get(None, 0, ctypes.byref(n))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    A.lib().ebtc_tune_cache_get(buf, n.value + 1, ctypes.byref(n))
+    return buf.value.decode()
 
 
 @pytest.mark.parametrize("kw,text", [

@@ -129,6 +129,7 @@ def test_balanced_backward_equals_stream(gpu_lib):
 def test_tuner_times_the_balanced_form(gpu_lib):
     hb = hub_batch("f32", False)
     b = api().Batch.from_host(hb)
+    api().tune_cache_clear()  # time every bucket afresh
     t = b.tune(m=20)
     assert t["ms_per_launch"]["balanced"] > 0.0
     out = b.scores(m=20)  # the tuned form

@@ -30,6 +30,7 @@ def workers() -> int:
 def run_tuned(hb, m, tol=1e-6, m_max=60):
     torch = torch_mod()
     b = api().Batch.from_host(hb)
+    api().tune_cache_clear()  # time every bucket afresh
     t = b.tune(m=m, tol=tol, m_max=m_max)
     run = b.run(m=m, tol=tol, m_max=m_max)  # batched, hipGraph, the tuned form
     run.launch()
