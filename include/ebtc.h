@@ -222,9 +222,17 @@ int ebtc_plan_backward(ebtc_batch* batch, const ebtc_opts* opts, size_t* ws_byte
  *   log_scale    device [G] double, the forward's Sigma_g
  *   grad_scores  device [sum_g n_g] of dtype, the cotangent of the scores
  *   grad_values  device [nnz_off[R]] of dtype, written
- *   ws, ws_bytes device workspace of at least ebtc_plan_backward's size */
+ *   ws, ws_bytes device workspace of at least ebtc_plan_backward's size
+ *   ckpt         device [R][2 EBTC_M_LIMIT + 4] doubles (nullable): the forward call's ckpt_out. The
+ *                recomputed forward process is compared with it bit for bit (alpha, beta, theta*,
+ *                beta0, steps, flags of every realization), which holds exactly when the batch's
+ *                values and the options are the forward's
+ *   ckpt_mismatch device int32 (required with ckpt): the number of realizations that differ
+ * Errors: EINVAL (NULL arguments, ckpt without ckpt_mismatch, bad opts), ENOTSUPPORTED (reorth 0, or
+ * a Krylov dimension above the adjoint's), EWORKSPACE, EHIP. */
 int ebtc_scores_backward(ebtc_batch* batch, const ebtc_opts* opts, const double* log_scale, const void* grad_scores,
-                         void* grad_values, void* ws, size_t ws_bytes, void* stream);
+                         void* grad_values, void* ws, size_t ws_bytes, const double* ckpt, int32_t* ckpt_mismatch,
+                         void* stream);
 
 /* ---------------------------------------------------------------- selection                      */
 /* Device workspace bytes for ebtc_topk (host-only). */

@@ -99,7 +99,7 @@ def lib() -> ctypes.CDLL:
         "ebtc_validate": (c_int, [vp, vp, sz, POINTER(c_int64), vp]),
         "ebtc_profile_phases": (c_int, [vp, POINTER(Opts), vp, sz, vp, vp, POINTER(c_double), POINTER(c_int64), vp]),
         "ebtc_plan_backward": (c_int, [vp, POINTER(Opts), POINTER(sz)]),
-        "ebtc_scores_backward": (c_int, [vp, POINTER(Opts), vp, vp, vp, vp, sz, vp]),
+        "ebtc_scores_backward": (c_int, [vp, POINTER(Opts), vp, vp, vp, vp, sz, vp, vp, vp]),
         "ebtc_tune": (c_int, [vp, POINTER(Opts), vp, sz, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
                               POINTER(c_double), vp]),
         "ebtc_tuned_forms": (c_int, [vp, vp, vp, vp]),

@@ -112,11 +112,17 @@ class BackwardRun:
         self.ws = torch.empty(max(1, ws.value), dtype=torch.uint8, device=batch.device)
         self.grad = torch.empty(max(1, int(batch.nnz_off[-1])), dtype=batch.tdtype, device=batch.device)
 
-    def launch(self, log_scale: torch.Tensor, grad_scores: torch.Tensor) -> torch.Tensor:
+    def launch(self, log_scale: torch.Tensor, grad_scores: torch.Tensor, ckpt: torch.Tensor | None = None):
+        """The gradient; with the forward call's checkpoint also the number of realizations whose
+        recomputed forward process differs from it (a device int32 tensor: 0 when the recomputation
+        is the forward's, bit for bit)."""
         g = grad_scores.to(self.batch.tdtype).contiguous()
+        mism = torch.empty(1, dtype=torch.int32, device=self.batch.device) if ckpt is not None else None
         A.check(A.lib().ebtc_scores_backward(self.batch.handle, ctypes.byref(self.opts), _vp(log_scale), _vp(g),
-                                             _vp(self.grad), _vp(self.ws), self.ws_bytes, current_stream()))
-        return self.grad[: int(self.batch.nnz_off[-1])]
+                                             _vp(self.grad), _vp(self.ws), self.ws_bytes, _vp(ckpt), _vp(mism),
+                                             current_stream()))
+        grad = self.grad[: int(self.batch.nnz_off[-1])]
+        return grad if ckpt is None else (grad, mism)
 
 
 class Batch:
@@ -291,10 +297,21 @@ class Batch:
     def backward_run(self, **kw) -> "BackwardRun":
         return BackwardRun(self, make_opts(**kw))
 
-    def scores_backward(self, log_scale: torch.Tensor, grad_scores: torch.Tensor, **kw) -> torch.Tensor:
+    def scores_backward(self, log_scale: torch.Tensor, grad_scores: torch.Tensor, ckpt: torch.Tensor | None = None,
+                        **kw) -> torch.Tensor:
         """Gradient of sum_g <grad_scores_g, S~_g> with respect to every stored CSR entry (log-scales
-        fixed); `kw` are the options of the forward call."""
-        return self.backward_run(**kw).launch(log_scale, grad_scores)
+        fixed); `kw` are the options of the forward call. With the forward call's checkpoint (a
+        ScoreResult's ckpt, from scores(ckpt=True)) the recomputed forward process must equal it bit
+        for bit, else RuntimeError (the values or the options are not the forward's)."""
+        out = self.backward_run(**kw).launch(log_scale, grad_scores, ckpt)
+        if ckpt is None:
+            return out
+        grad, mism = out
+        bad = int(mism.item())
+        if bad:
+            raise RuntimeError(f"the backward's recomputed forward differs from the forward checkpoint in {bad} "
+                               "realization(s): the batch's values or the options changed since the forward call")
+        return grad
 
     def validate(self) -> int:
         ws = ctypes.c_size_t()
@@ -445,15 +462,17 @@ class Communicability(torch.autograd.Function):
     def forward(ctx, values, batch, opts):
         if batch.values is None or values.data_ptr() != batch.values.data_ptr():
             raise ValueError("values must be the tensor the batch was created on")
-        out = batch.scores(diag=False, **opts)
+        out = batch.scores(diag=False, ckpt=True, **opts)
         ctx.batch = batch
         ctx.opts = dict(opts)
-        ctx.save_for_backward(out.log_scale)
+        ctx.save_for_backward(out.log_scale, out.ckpt)
         ctx.mark_non_differentiable(out.log_scale)
         return out.scores, out.log_scale
 
     @staticmethod
     def backward(ctx, grad_scores, _grad_log_scale):
-        (log_scale,) = ctx.saved_tensors
-        g = ctx.batch.scores_backward(log_scale, grad_scores, **ctx.opts)
+        # the forward's checkpoint guards the recomputation: values changed in place between forward
+        # and backward raise instead of giving the gradient of other weights
+        log_scale, ckpt = ctx.saved_tensors
+        g = ctx.batch.scores_backward(log_scale, grad_scores, ckpt=ckpt, **ctx.opts)
         return g, None, None

@@ -1527,13 +1527,15 @@ int ebtc_plan_backward(ebtc_batch* b, const ebtc_opts* o, size_t* ws_bytes) {
 }
 
 int ebtc_scores_backward(ebtc_batch* b, const ebtc_opts* o, const double* log_scale, const void* grad_scores,
-                         void* grad_values, void* ws, size_t ws_bytes, void* stream) {
+                         void* grad_values, void* ws, size_t ws_bytes, const double* ckpt, int32_t* ckpt_mismatch,
+                         void* stream) {
   g_err.clear();
   if (!b) return fail(EBTC_EINVAL, "NULL batch");
   int rc = check_bwd_opts(o);
   if (rc) return rc;
   if (!log_scale || !grad_scores || !grad_values || !ws)
     return fail(EBTC_EINVAL, "NULL log_scale, grad_scores, grad_values or workspace");
+  if (ckpt && !ckpt_mismatch) return fail(EBTC_EINVAL, "a checkpoint to compare needs ckpt_mismatch");
   const BatchPlan bp = spmv_plan(b, o);
   rc = check_plan(b, bp);
   if (rc) return rc;
@@ -1558,6 +1560,9 @@ int ebtc_scores_backward(ebtc_batch* b, const ebtc_opts* o, const double* log_sc
   if (rc) return rc;
   const int steps = o->m > 0 ? o->m : o->m_max;
   EBTC_LAUNCH(launch_tridiag_state(fa, 0, b->R, 0, 0, steps, o->shift, o->tol, nullptr, nullptr, s));
+  // the recomputation against the forward call's checkpoint: every reduction runs in a fixed order, so
+  // any difference means the inputs or the options are not the forward's
+  if (ckpt) EBTC_LAUNCH(launch_ckpt_check(fa.state, ckpt, b->R, ckpt_mismatch, s));
   // 2. adjoint Lanczos started at the cotangent (shares W and the partial-sum arenas)
   LzArgs aa = fa;
   aa.unit_start = 0;  // started at the cotangent

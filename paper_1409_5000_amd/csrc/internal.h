@@ -278,6 +278,9 @@ hipError_t launch_build_zv(int dtype, const LzArgs& fwd, const LzArgs& adj, cons
                            int ld, int64_t nblocks, hipStream_t s);
 hipError_t launch_sddmm(int dtype, int ld, const LzArgs& fwd, const void* Z, const void* Vn, void* grad,
                         int64_t nblocks, hipStream_t s);
+// Counts the realizations whose recomputed forward state differs bit for bit from the forward call's
+// checkpoint (ckpt: [R][kCkptDoubles]) into *mismatch (device int32, cleared first).
+hipError_t launch_ckpt_check(const RState* st, const double* ckpt, int64_t R, int32_t* mismatch, hipStream_t s);
 
 // Leading dimension of the adjoint's block-exponential output per realization (the adjoint's Krylov
 // dimension is at most adjoint_max_m() <= kXLd).

@@ -324,9 +324,37 @@ hipError_t sddmm_ld(int ld, const LzArgs& fwd, const void* Z, const void* Vn, vo
   return hipGetLastError();
 }
 
+// The forward recomputation against the forward call's checkpoint, bit for bit: alpha_0..k-1,
+// beta_0..k-1, theta*, beta0, the step count k and the flags of each realization (one thread each).
+// Every realization that differs adds one to *mismatch, which k_zero_count clears first.
+__global__ void k_zero_count(int32_t* count) { *count = 0; }
+
+__global__ __launch_bounds__(kBlock) void k_ckpt_check(const RState* st, const double* ckpt, int64_t R,
+                                                       int32_t* mismatch) {
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= R) return;
+  const RState& s = st[r];
+  const double* c = ckpt + r * kCkptDoubles;
+  auto same = [](double a, double b) { return __double_as_longlong(a) == __double_as_longlong(b); };
+  const int k = s.m_used;
+  bool ok = (double)k == c[2 * kMLimit + 2] && (double)s.flags == c[2 * kMLimit + 3] && same(s.theta, c[2 * kMLimit]) &&
+            same(s.beta0, c[2 * kMLimit + 1]) && k >= 0 && k <= kMLimit;
+  for (int i = 0; ok && i < k; ++i) ok = same(s.alpha[i], c[i]) && same(s.beta[i], c[kMLimit + i]);
+  if (!ok) atomicAdd(mismatch, 1);
+}
+
 }  // namespace
 
 int adjoint_max_m() { return kMX; }
+
+hipError_t launch_ckpt_check(const RState* st, const double* ckpt, int64_t R, int32_t* mismatch, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, mismatch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || R < 1) return e;
+  hipLaunchKernelGGL(k_ckpt_check, dim3((unsigned)((R + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, st, ckpt, R,
+                     mismatch);
+  return hipGetLastError();
+}
 
 hipError_t launch_start_vec(int dtype, const LzArgs& a, const GraphInfo* graphs, const void* g, int64_t nb,
                             hipStream_t s) {

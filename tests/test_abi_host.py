@@ -308,6 +308,26 @@ def test_scores_rejects_before_enqueue():
     A.lib().ebtc_batch_destroy(h)
 
 
+def test_scores_backward_rejects_before_enqueue():
+    d, keep = make_desc()
+    rc, h = create(d)
+    o = A.default_opts(m=10)
+    L = A.lib()
+    args = (h, ctypes.byref(o), FAKE_DEV, FAKE_DEV, FAKE_DEV, FAKE_DEV, 1 << 40)
+    assert L.ebtc_scores_backward(h, ctypes.byref(o), None, FAKE_DEV, FAKE_DEV, FAKE_DEV, 1 << 40, None, None,
+                                  None) == A.EBTC_EINVAL
+    # a checkpoint to compare needs the mismatch counter
+    assert L.ebtc_scores_backward(*args, FAKE_DEV, None, None) == A.EBTC_EINVAL
+    assert "ckpt_mismatch" in L.ebtc_last_error().decode()
+    o2 = A.default_opts(m=10, reorth=0)
+    assert L.ebtc_scores_backward(h, ctypes.byref(o2), FAKE_DEV, FAKE_DEV, FAKE_DEV, FAKE_DEV, 1 << 40, None, None,
+                                  None) == A.EBTC_ENOTSUPPORTED
+    o3 = A.default_opts(m=41)
+    assert L.ebtc_scores_backward(h, ctypes.byref(o3), FAKE_DEV, FAKE_DEV, FAKE_DEV, FAKE_DEV, 1 << 40, None, None,
+                                  None) == A.EBTC_ENOTSUPPORTED
+    A.lib().ebtc_batch_destroy(h)
+
+
 def test_scores_noalloc_rejects_before_enqueue():
     # NULL outputs, a batch whose workspace exceeds the static array, and a schedule the batch cannot
     # take all fail on the host, before any HIP call (the scratch address is looked up only after them)

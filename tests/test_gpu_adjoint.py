@@ -244,6 +244,39 @@ def test_autograd_function_matches_backward(gpu_lib):
     assert torch.equal(values.grad, direct)
 
 
+def test_backward_checks_the_forward_checkpoint(gpu_lib):
+    # the forward call's checkpoint (alpha, beta, theta*, beta0, steps, flags) against the backward's
+    # recomputed forward: equal bit for bit, so the count is 0 and the gradient is the unchecked one;
+    # a changed checkpoint entry is counted; weights changed in place between the autograd forward
+    # and backward make the backward raise
+    torch = torch_mod()
+    w = C.scaled(C.workload(3), n=3000, N=3)
+    hb = C.build(w)
+    b = api().Batch.from_host(hb)
+    out = b.scores(m=w.m, ckpt=True)
+    g = torch.zeros(int(hb.n[0]), dtype=torch.float32, device="cuda")
+    g[torch.as_tensor(b_targets(hb)).to("cuda")] = 1.0
+    plain = b.scores_backward(out.log_scale, g, m=w.m).clone()
+    bwd = b.backward_run(m=w.m)
+    grad, mism = bwd.launch(out.log_scale, g, out.ckpt)
+    torch.cuda.synchronize()
+    assert int(mism.item()) == 0 and torch.equal(grad, plain)
+    bad = out.ckpt.clone()
+    bad.view(3, -1)[1, 0] = torch.nextafter(bad.view(3, -1)[1, 0], torch.tensor(1e300, dtype=torch.float64, device="cuda"))
+    _, mism = bwd.launch(out.log_scale, g, bad)
+    torch.cuda.synchronize()
+    assert int(mism.item()) == 1
+    with pytest.raises(RuntimeError, match="differs from the forward checkpoint"):
+        b.scores_backward(out.log_scale, g, ckpt=bad, m=w.m)
+    values = b.values
+    values.requires_grad_(True)
+    scores, _ = api().Communicability.apply(values, b, {"m": w.m})
+    with torch.no_grad():
+        values[0] *= 1.5  # the weights the backward would recompute with are no longer the forward's
+    with pytest.raises(RuntimeError, match="differs from the forward checkpoint"):
+        scores[torch.as_tensor(b_targets(hb)).to("cuda")].sum().backward()
+
+
 def test_zero_cotangent_gives_zero_gradient(gpu_lib):
     torch = torch_mod()
     hb = weighted_dense_batch([[gs.random_graph(100, 0.1, 5)]], "f64")
