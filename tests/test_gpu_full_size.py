@@ -91,3 +91,26 @@ def test_full_uneven_slice_adaptive(gpu_lib):
     d = out.diag_numpy()
     assert d["m_used"].max() <= w.m_max and (d["flags"] & 4).max() == 0  # no non-finite results
     check_topk(b, out, ref, hb.K)
+
+
+def test_full_uneven_span_adaptive(gpu_lib):
+    # thirty graphs of the uneven workload at their full sizes with their eight realizations, ten per
+    # family spread over its n range (evenly spaced in the family's graphs sorted by n: n from about 1e4
+    # to 5e5, degrees 8 to 32, clique and sparse targets); adaptive m against the oracle graph by graph
+    # (scores, flags, theta*, Saad's estimate) and the top-K sets
+    w = C.workload(4)
+    pick = []
+    for fam in ("er", "ba", "ws"):
+        idx = sorted((i for i, g in enumerate(w.graphs) if g.family == fam), key=lambda i: w.graphs[i].n)
+        pick += [idx[round(k * (len(idx) - 1) / 9)] for k in range(10)]
+    w = dataclasses.replace(w, graphs=tuple(w.graphs[i] for i in sorted(pick)))
+    hb = C.build_parallel(w, workers=workers())
+    n = np.asarray(hb.n)
+    assert hb.R == 240 and n.min() < 30_000 and n.max() > 450_000
+    b, out, t = run_tuned(hb, 0, tol=w.tol, m_max=w.m_max)
+    ref, rep = check_against_oracle(hb, out, b, 0, "f32", K=100, tol=w.tol, m_max=w.m_max, check_m=False,
+                                    workers=workers())
+    d = out.diag_numpy()
+    assert d["m_used"].max() <= w.m_max and (d["flags"] & 4).max() == 0
+    check_topk(b, out, ref, hb.K)
+
