@@ -40,7 +40,7 @@ METRIC = "graph-realizations/s for Krylov exp(A)·1 + achieved HBM GB/s; batched
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c1.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1409_5000_amd", "csrc", f)
-                  for f in ("k_lanczos.hip", "k_spmv.hip", "device_common.h", "internal.h")]
+                  for f in ("k_lanczos.hip", "k_spmv.hip", "device_common.h", "internal.h", "step_device.h")]
 
 
 def log(msg: str) -> None:
