@@ -152,13 +152,13 @@ __device__ inline void block_dots(const T* __restrict__ Vr, int n, int lo, int j
   constexpr int RPT = kRowsPerBlock / NT;
   constexpr int CH = P < 8 ? P : 8;
   const int tid = threadIdx.x, cnt = j - lo + 1;
-#pragma unroll 1
-  for (int t0 = 0; t0 < NT; t0 += NREAL) {
+  // one pass of NREAL threads, forming the sums of threads t0 + tid of NT
+  auto pass = [&](int t0) {
     const int vt = t0 + tid;  // the thread of NT whose sums this pass forms
     constexpr int LP0 = 64 / P;
     if (NREAL < NT && t0 >= r1 - r0) {  // no rows in this pass: its partials are zeros
       if ((tid & 63) % LP0 == 0) red[(vt >> 6) * P + (tid & 63) / LP0] = 0.0;
-      continue;
+      return;
     }
     T p[P];
 #pragma unroll
@@ -191,6 +191,12 @@ __device__ inline void block_dots(const T* __restrict__ Vr, int n, int lo, int j
     ReduceScatter<P, 32>::run(pd, lane);
     constexpr int LP = 64 / P;  // lanes per value after the reduce-scatter: lane l holds value l / LP
     if (lane % LP == 0) red[wave * P + lane / LP] = pd[0];
+  };
+  if constexpr (NREAL == NT) {
+    pass(0);  // straight-line code for the usual case: a loop, even of one trip, costs the scheduling
+  } else {
+#pragma unroll 1
+    for (int t0 = 0; t0 < NT; t0 += NREAL) pass(t0);
   }
   __syncthreads();
   if (tid < P && tid < cnt) {
