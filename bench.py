@@ -288,7 +288,8 @@ def main() -> int:
     tuned = None
     if args.spmv == "tuned":
         tuned = b.tune(m=m, tol=tol, m_max=m_max, reorth=args.reorth)
-        log(f"tuned SpMV form: {tuned}")
+        forms = sorted(set(f[0] for f in tuned["graph_forms"]))
+        log(f"tuned SpMV form: {tuned['form']} (graphs: {', '.join(forms)}), ms per launch {tuned['ms_per_launch']}")
 
     if args.profile_run:
         # for counter runs: a 1 GiB device copy (calibration of the byte counters), then one eager
@@ -361,24 +362,6 @@ def main() -> int:
                    "backward_over_forward": round(bwd_ms / fwd_ms, 3), "budget": 3.0}
         log(f"adjoint: forward {fwd_ms:.3f} ms, backward {bwd_ms:.3f} ms, ratio {bwd_ms / fwd_ms:.2f}")
 
-    # plain per-realization loop on the same batch (--plain-steps 0 skips it)
-    plain = None
-    if args.plain_steps > 0:
-        runp = b.run(m=m, tol=tol, m_max=m_max, schedule="plain", hipgraph=False, diag=False, **form)
-        step(runp)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.plain_steps):
-            step(runp)
-        torch.cuda.synchronize()
-        plain_wall = time.perf_counter() - t0
-        plain_value = hb.R * args.plain_steps / plain_wall
-        log(f"plain: {1000 * plain_wall / args.plain_steps:.3f} ms/step, {plain_value:.1f} realizations/s")
-        plain = {"value": round(plain_value, 2), "ms_per_step": round(1000 * plain_wall / args.plain_steps, 3),
-                 "batched_over_plain": round(value / plain_value, 2)}
-        del runp
-        torch.cuda.empty_cache()
-
     # per-kernel durations with HIP events around each launch: one eager pass of the same launch
     # sequence on the timed run's workspace
     run.profile()
@@ -403,6 +386,27 @@ def main() -> int:
     log(f"spmv ms/launch by form: {spmv_modes}")
     d = run.launch().diag_numpy()
     torch.cuda.synchronize()
+    final_scores = run.scores
+    del run  # the timed run's workspace: the plain loop below plans its own
+    torch.cuda.empty_cache()
+    # plain per-realization loop on the same batch (--plain-steps 0 skips it)
+    plain = None
+    if args.plain_steps > 0:
+        runp = b.run(m=m, tol=tol, m_max=m_max, schedule="plain", hipgraph=False, diag=False, **form)
+        step(runp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            step(runp)
+        torch.cuda.synchronize()
+        plain_wall = time.perf_counter() - t0
+        plain_value = hb.R * args.plain_steps / plain_wall
+        log(f"plain: {1000 * plain_wall / args.plain_steps:.3f} ms/step, {plain_value:.1f} realizations/s")
+        plain = {"value": round(plain_value, 2), "ms_per_step": round(1000 * plain_wall / args.plain_steps, 3),
+                 "batched_over_plain": round(value / plain_value, 2)}
+        del runp
+        torch.cuda.empty_cache()
+
     m_used = d["m_used"]
     sp_bytes = dt_bytes = up_bytes = fs_bytes = 0.0
     passes = max(1, args.reorth)  # Gram-Schmidt passes per step
@@ -504,7 +508,7 @@ def main() -> int:
                                                          f"{one_wall:.2f}s"}}
         errs = []
         top_ok = True
-        idx_all, _ = b.topk(run.scores, K)
+        idx_all, _ = b.topk(final_scores, K)
         idx_all = idx_all.cpu().numpy()
         koff = np.concatenate([[0], np.cumsum(K)])
         for g, gsc in enumerate(ref):  # graphs 0 .. G_or - 1, in order
