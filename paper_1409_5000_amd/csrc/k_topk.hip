@@ -8,12 +8,42 @@
 //   2. one pass collects every entry above t, plus the lowest-id entries equal to t (an ordered
 //      block scan in id order when there are more ties than needed);
 //   3. a bitonic sort in LDS orders the K candidates by descending score, then ascending id.
+// A graph of at most kTopkSortAll nodes skips 1 and 2: all its entries are sorted and the first K kept.
 #include "internal.h"
 
 namespace ebtc {
 namespace {
 
 constexpr int kTopkThreads = 1024;
+// Graphs up to this many nodes are sorted whole (within the candidate arrays' EBTC_TOPK_LIMIT).
+constexpr int kTopkSortAll = 2048;
+static_assert(kTopkSortAll <= EBTC_TOPK_LIMIT, "candidate arrays");
+
+// Bitonic sort of P2 (a power of two) keys with their ids in LDS: larger key first, then smaller id.
+// Ends with a barrier.
+template <typename K>
+__device__ inline void bitonic_desc(K* ckey, int* cid, int P2) {
+  for (int size = 2; size <= P2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < P2; i += kTopkThreads) {
+        const int p = i ^ stride;
+        if (p > i) {
+          const bool desc = (i & size) == 0;
+          const K ka = ckey[i], kb = ckey[p];
+          const int ia = cid[i], ib = cid[p];
+          const bool a_first = (ka > kb) || (ka == kb && ia < ib);
+          if (a_first != desc) {
+            ckey[i] = kb;
+            ckey[p] = ka;
+            cid[i] = ib;
+            cid[p] = ia;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
 
 __device__ inline uint32_t key_of(float v) {
   const uint32_t b = __float_as_uint(v);
@@ -43,6 +73,22 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk(const GraphInfo* graphs, 
   const int n = gi.n;
   const T* s = scores + gi.score_off;
   constexpr int BITS = (int)sizeof(K) * 8;
+  const int64_t o = koff[g];
+  if (n <= kTopkSortAll) {  // a small graph: every entry sorted, the first K taken (no radix passes)
+    int P2 = 1;
+    while (P2 < n) P2 <<= 1;
+    for (int i = tid; i < P2; i += kTopkThreads) {
+      ckey[i] = i < n ? key_of(s[i]) : (K)0;
+      cid[i] = i < n ? i : 0x7fffffff;
+    }
+    __syncthreads();
+    bitonic_desc<K>(ckey, cid, P2);
+    for (int r = tid; r < K_; r += kTopkThreads) {
+      idx_out[o + r] = cid[r];
+      if (val_out) val_out[o + r] = s[cid[r]];
+    }
+    return;
+  }
   if (tid == 0) {
     s_prefix = 0;
     s_mask = 0;
@@ -78,18 +124,42 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk(const GraphInfo* graphs, 
       hist[tid] = c;
     }
     __syncthreads();
-    if (tid == 0) {
-      int cum = 0, b = 255;
-      for (; b > 0; --b) {
-        if (cum + (int)hist[b] >= s_remaining) break;
-        cum += (int)hist[b];
+    if (tid < 64) {
+      // the bin b of the K-th largest: the largest b whose count from b up reaches the entries still
+      // needed (bin 0 when none does). Lane l holds bins 4l..4l+3; a suffix sum over the lanes gives
+      // every bin's count from it up, and the bins that reach the need are counted.
+      const int rem = s_remaining;
+      int h[4], suf[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) h[q] = (int)hist[4 * tid + q];
+      const int mine = h[0] + h[1] + h[2] + h[3];
+      int incl = mine;  // inclusive suffix over lanes l..63
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_down(incl, o, 64);
+        if (tid + o < 64) incl += t;
       }
-      s_remaining -= cum;
-      s_prefix = prefix | ((K)b << shift);
-      s_mask = mask | ((K)255 << shift);
-      if (shift == 0) s_eq_total = (int)hist[b];
-      s_ngt = 0;
-      s_eq_seen = 0;
+      const int above = incl - mine;  // the bins of the lanes above this one
+      suf[3] = above + h[3];
+      suf[2] = suf[3] + h[2];
+      suf[1] = suf[2] + h[1];
+      suf[0] = suf[1] + h[0];
+      int reach = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) reach += (suf[q] >= rem) ? 1 : 0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) reach += __shfl_xor(reach, o, 64);
+      const int b = reach > 0 ? reach - 1 : 0;
+      if (tid == (b >> 2)) {
+        const int q = b & 3;
+        const int cum = suf[q] - h[q];  // the entries in the bins above b
+        s_remaining = rem - cum;
+        s_prefix = prefix | ((K)b << shift);
+        s_mask = mask | ((K)255 << shift);
+        if (shift == 0) s_eq_total = h[q];
+        s_ngt = 0;
+        s_eq_seen = 0;
+      }
     }
     __syncthreads();
   }
@@ -143,28 +213,7 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk(const GraphInfo* graphs, 
     cid[i] = 0x7fffffff;
   }
   __syncthreads();
-  // bitonic sort, "before" = larger key, then smaller id
-  for (int size = 2; size <= P2; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = tid; i < P2; i += kTopkThreads) {
-        const int p = i ^ stride;
-        if (p > i) {
-          const bool desc = (i & size) == 0;
-          const K ka = ckey[i], kb = ckey[p];
-          const int ia = cid[i], ib = cid[p];
-          const bool a_first = (ka > kb) || (ka == kb && ia < ib);
-          if (a_first != desc) {
-            ckey[i] = kb;
-            ckey[p] = ka;
-            cid[i] = ib;
-            cid[p] = ia;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  const int64_t o = koff[g];
+  bitonic_desc<K>(ckey, cid, P2);
   for (int r = tid; r < K_; r += kTopkThreads) {
     idx_out[o + r] = cid[r];
     if (val_out) val_out[o + r] = s[cid[r]];

@@ -452,15 +452,18 @@ def test_weighted_values(gpu_lib):
 
 # ------------------------------------------------------------------ top-K
 
-def test_topk_ties_and_sizes(gpu_lib):
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_topk_ties_and_sizes(gpu_lib, dtype):
+    # graphs of up to 2048 nodes are sorted whole, larger ones take the radix passes: sizes on both
+    # sides of that bound, K up to n, heavy ties
     torch = torch_mod()
     rng = np.random.default_rng(7)
-    sizes = [1, 5, 1000, 4097]
+    sizes = [1, 5, 1000, 2047, 2048, 2049, 4097]
 
     class B:  # empty graphs of the block sizes under test: only the graph table matters for top-K
         pass
     hb = B()
-    hb.dtype = np.float32
+    hb.dtype = dtype
     hb.n = np.array(sizes, np.int32)
     hb.nreal = np.ones(len(sizes), np.int32)
     hb.rowptr_off = np.concatenate([[0], np.cumsum(np.array(sizes) + 1)[:-1]]).astype(np.int64)
@@ -469,10 +472,11 @@ def test_topk_ties_and_sizes(gpu_lib):
     hb.col_idx = np.zeros(1, np.int32)
     hb.values = None
     b = api().Batch.from_host(hb)
-    blocks = [rng.integers(0, 7, size=n).astype(np.float32) for n in sizes]  # heavy ties
-    blocks[3][::3] = 1e30
+    blocks = [rng.integers(0, 7, size=n).astype(dtype) for n in sizes]  # heavy ties
+    blocks[6][::3] = 1e30
+    blocks[4] = -blocks[4]  # negative scores and -0.0 on the sorted path
     s = torch.as_tensor(np.concatenate(blocks)).to("cuda")
-    ks = [1, 5, 37, 1500]
+    ks = [1, 5, 37, 2047, 100, 2049, 1500]
     idx, val = b.topk(s, ks)
     idx = idx.cpu().numpy()
     o = 0
