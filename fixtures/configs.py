@@ -224,16 +224,19 @@ def build_parallel(w: Workload, workers: int = 8, with_values: bool = True,
     for g, (spec, d) in enumerate(zip(w.graphs, draws)):
         N = spec.N if realizations is None else min(spec.N, realizations)
         jobs += [(w.ci, g, k, d) for k in range(N)]
+    out = []
+    every = max(1, len(jobs) // 20)
     if workers > 1 and len(jobs) > 1:
-        out = []
-        every = max(1, len(jobs) // 20)
         with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
             for i, res in enumerate(pool.imap(_gen_one, jobs, chunksize=1)):
                 out.append(res)
                 if progress is not None and (i + 1) % every == 0:
                     progress(i + 1, len(jobs))
     else:
-        out = [_gen_one(j) for j in jobs]
+        for i, j in enumerate(jobs):
+            out.append(_gen_one(j))
+            if progress is not None and (i + 1) % every == 0:
+                progress(i + 1, len(jobs))
     parts = []
     i = 0
     for g, (spec, d) in enumerate(zip(w.graphs, draws)):
