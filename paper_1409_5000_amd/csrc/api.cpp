@@ -389,10 +389,13 @@ Layout make_layout(const ebtc_batch* b, const ebtc_opts* o, const BatchPlan& bp)
       off = align_up(off + sizeof(uint16_t) * (size_t)sp.smax * 17 * F.blocks);
       F.off_segblk = off;
       off = align_up(off + sizeof(SegBlock) * F.blocks);
+      // the entries, the zero padding of every (segment, wave band) run and the rounding of every
+      // block's first slot to a multiple of four
+      const size_t slots = z + (size_t)F.blocks * kSegSlack + 8;
       F.off_segcol = off;
-      off = align_up(off + sizeof(uint16_t) * z);
+      off = align_up(off + sizeof(uint16_t) * slots);
       F.off_segval = off;
-      if (b->values) off = align_up(off + es * z);
+      if (b->values) off = align_up(off + es * slots);
     }
     if (sp.form == EBTC_SPMV_PANELED) {
       const int64_t units = F.blocks * (kRowsPerBlock / sp.panunit);

@@ -48,10 +48,10 @@ static_assert(sizeof(Task) == 80, "Task layout");
 // need, so that they wait on one load instead of the chain workgroup map -> realization -> row
 // pointers -> band table.
 struct SegBlock {
-  int64_t entries;   // index of the block's first entry in seg_col / seg_val
+  int64_t entries;   // index of the block's first slot in seg_col / seg_val (a multiple of four)
   int64_t vec_off;   // Task::vec_off of its realization
   int32_t n;         // order of its realization
-  int32_t nnz;       // entries of the block
+  int32_t nnz;       // slots of the block: its entries and the zero padding of its wave bands
   int16_t rows;      // rows of the block
   int16_t flag;      // the block's seg_flag
   uint16_t wo0[17];  // band starts of segment 0 (the first 17 entries of its seg_woff table)
@@ -144,9 +144,12 @@ struct LzArgs {
   int32_t seg_cols;        // columns per segment
   int32_t seg_stride;      // bytes of per-(segment, row) counts per row block: max segments x kRowsPerBlock
   int32_t* seg_flag;       // [row blocks] 1 = sorted, 0 = the block uses the CSR-stream form
-  uint8_t* seg_cnt;        // [row blocks][seg_stride] entries of row r in segment s at [s * rows + r]
-  uint16_t* seg_col;       // [entries] column - s * seg_cols, a block's entries ordered by (segment, row)
-  void* seg_val;           // [entries] values in the same order (nullptr for pattern-only graphs)
+  uint8_t* seg_cnt;        // [row blocks][seg_stride] entries of row r in segment s at [s * rows2 + r],
+                           // rows2 = the block's rows rounded up to even (the pad row's count is 0)
+  uint16_t* seg_col;       // [slots] column - s * seg_cols, a block's entries ordered by (segment, row);
+                           // each (segment, wave band) run padded with zeros to a multiple of four
+                           // entries, each block's first slot a multiple of four
+  void* seg_val;           // [slots] values in the same order (nullptr for pattern-only graphs)
   int32_t seg_vec;         // 1: every n and seg_cols are multiples of 16 bytes / element size (16-byte
                            // slice loads and stores)
   uint16_t* seg_woff;      // [row blocks][seg_wstride] wave bands: entries of rows [128 w, 128 w + 128) in
@@ -235,6 +238,9 @@ int staged_max_seglen(int dtype);
 hipError_t prepare_staged_kernels();
 // Column-segmented SpMV: at most kSegMax segments per realization; largest segment that fits in LDS.
 constexpr int kSegMax = 32;
+// Slots of the column-segmented arenas per row block beyond its entries: up to three zeros after each
+// of its (segment, wave band) runs, and the rounding of its first slot up to a multiple of four.
+constexpr int kSegSlack = 3 * 16 * kSegMax + 8;
 int seg_max_cols(int dtype);
 hipError_t prepare_seg_kernels();
 // Sorts every row block's entries by column segment (a.seg_* arrays); smax = max segments in the launch.

@@ -572,20 +572,24 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
       w0[r] = (T)(acc * s0);
     }
   };
-  auto finish = [&](int f) {  // the block's flag and descriptor (band starts written by the caller)
+  // the block's first slot: its first entry's index in the form's arenas, moved past the padding
+  // slots of the blocks before it and rounded up to a multiple of four (8- and 16-byte accesses)
+  const int64_t base = (tk.aux_off + e0 + (int64_t)blk * kSegSlack + 3) & ~(int64_t)3;
+  auto finish = [&](int f, int slots) {  // the block's flag and descriptor (band starts written by the caller)
     if (tid == 0) {
       a.seg_flag[blk] = f;
-      desc->entries = tk.aux_off + e0;
+      desc->entries = base;
       desc->vec_off = tk.vec_off;
       desc->n = n;
-      desc->nnz = nz;
+      desc->nnz = slots;
       desc->rows = (int16_t)rows;
       desc->flag = (int16_t)f;
     }
   };
-  if (nz > 65535 || S > kSegMax) {  // offsets must fit 16 bits
+  // offsets must fit 16 bits, the padding included (at most three slots per wave band)
+  if (nz + 3 * kSegWaves * S > 65535 || S > kSegMax) {
     direct_sums(HAS_VAL ? (const T*)a.values + tk.nnz_off : nullptr);
-    finish(0);
+    finish(0, 0);
     return;
   }
   const int32_t* ci = a.col_idx + tk.nnz_off + e0;
@@ -613,11 +617,15 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
                                   });
   if (bad) {
     direct_sums(va);
-    finish(0);
+    finish(0, 0);
     return;
   }
+  // counts with the rows of a segment at an even stride (one 2-byte load reads a lane's two rows;
+  // the pad row of an odd block counts 0)
+  const int rows2 = (rows + 1) & ~1;
   uint8_t* cnt_out = a.seg_cnt + (size_t)blk * a.seg_stride;
-  for (int i = tid; i < tot; i += NT) cnt_out[i] = (uint8_t)cnt[i];
+  for (int sg = 0; sg < S; ++sg)
+    for (int r = tid; r < rows2; r += NT) cnt_out[sg * rows2 + r] = r < rows ? (uint8_t)cnt[sg * rows + r] : (uint8_t)0;
   // exclusive scan in (segment, row) order: thread t owns counters [b, e)
   const int per = (tot + NT - 1) / NT;
   const int b = min(tid * per, tot), e = min(b + per, tot);
@@ -631,13 +639,40 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
     run += c;
   }
   __syncthreads();
-  // wave bands: the entries of rows [128 w, 128 w + 128) in segment s are [wo[s][w], wo[s][w + 1]);
-  // wo[s][16] ends the segment. A band beyond the per-wave product capacity sends the block to the
-  // stream form.
+  // wave bands: the entries of rows [128 w, 128 w + 128) in segment s, in (segment, band) order. Each
+  // band's run is padded with zeros to a multiple of four entries, so that every band starts at a
+  // multiple of four slots; band t's entries move by the padding of the bands before it.
+  const int nbw = (rows + kBandRows - 1) / kBandRows, NB = S * nbw;  // NB <= 32 x 16 <= NT
+  __shared__ int bpad[kSegMax * kSegWaves];
+  int ustart = 0, ulen = 0;
+  if (tid < NB) {
+    const int sg = tid / nbw, w = tid - sg * nbw;
+    ustart = cnt[sg * rows + w * kBandRows];
+    const int uend = w + 1 < nbw ? cnt[sg * rows + (w + 1) * kBandRows] : (sg + 1 < S ? cnt[(sg + 1) * rows] : total);
+    ulen = uend - ustart;
+  }
+  int padtot;
+  const int pex = block_excl_scan<NT>(tid < NB ? ((ulen + 3) & ~3) - ulen : 0, wtot, &padtot);
+  if (tid < NB) bpad[tid] = pex;
+  __syncthreads();
+  const int slots = total + padtot;
+  if (b < e) {  // this thread's counters move by their bands' padding (one division, then steps)
+    int sg = b / rows, r = b - sg * rows;
+    for (int i = b; i < e; ++i) {
+      cnt[i] = (uint16_t)(cnt[i] + bpad[sg * nbw + (r >> 7)]);
+      if (++r == rows) {
+        r = 0;
+        ++sg;
+      }
+    }
+  }
+  __syncthreads();
+  // band table: wo[s][w] = start of band w of segment s; wo[s][w] for w >= the block's bands (and
+  // wo[s][16]) = the end of segment s. A band beyond the per-wave product capacity sends the block to
+  // the stream form.
   uint16_t* wo = a.seg_woff + (size_t)blk * a.seg_wstride;
   auto band_start = [&](int sg, int w) {
-    return (w < kSegWaves && w * kBandRows < rows) ? (int)cnt[sg * rows + w * kBandRows]
-                                                   : (sg + 1 < S ? (int)cnt[(sg + 1) * rows] : total);
+    return w < nbw ? (int)cnt[sg * rows + w * kBandRows] : (sg + 1 < S ? (int)cnt[(sg + 1) * rows] : slots);
   };
   for (int i = tid; i < S * (kSegWaves + 1); i += NT) {
     const int sg = i / (kSegWaves + 1), w = i - sg * (kSegWaves + 1);
@@ -649,11 +684,18 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
   __syncthreads();
   if (bad) {
     direct_sums(va);
-    finish(0);
+    finish(0, 0);
     return;
   }
-  uint16_t* pc = a.seg_col + tk.aux_off + e0;
-  T* pv = HAS_VAL ? (T*)a.seg_val + tk.aux_off + e0 : nullptr;
+  uint16_t* pc = a.seg_col + base;
+  T* pv = HAS_VAL ? (T*)a.seg_val + base : nullptr;
+  if (tid < NB) {  // the band's padding slots
+    const int p0 = ustart + pex + ulen, p1 = ustart + pex + ((ulen + 3) & ~3);
+    for (int p = p0; p < p1; ++p) {
+      pc[p] = 0;
+      if constexpr (HAS_VAL) pv[p] = (T)0;
+    }
+  }
   for_rows_staged<T, HAS_VAL, NT>(ci, va, rp_lds, rows, cap, lci, lva,
                                   [&](int r, const int* cs, const T* vs, int k, int e) {
                                     double acc = 0.0;
@@ -670,7 +712,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
                                     }
                                     if (first) w0[r] = (T)(acc * s0);
                                   });
-  finish(1);
+  finish(1, slots);
 }
 
 // Raw buffer resource over [p, p + bytes): loads through it take 32-bit byte offsets and return 0
@@ -742,11 +784,12 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
   const uint16_t* pc = a.seg_col + d->entries;
   const T* pv = HAS_VAL ? (const T*)a.seg_val + d->entries : nullptr;
   const int rr = 2 * tid;  // this lane's two rows: 128 wv + 2 lane and the next
+  const int rows2 = (rows + 1) & ~1;  // the counts' stride per segment
   // Buffer resources (scalar registers) over the block's entries, its counts and the vector: loads
   // take 32-bit byte offsets, and an offset past the end reads 0, which is what every guard wants.
   const __amdgpu_buffer_rsrc_t r_pc = make_rsrc(pc, 2 * E);
   const __amdgpu_buffer_rsrc_t r_pv = make_rsrc(pv, HAS_VAL ? (int)sizeof(T) * E : 0);
-  const __amdgpu_buffer_rsrc_t r_cnt = make_rsrc(cnt, S * rows);
+  const __amdgpu_buffer_rsrc_t r_cnt = make_rsrc(cnt, S * rows2);
   const __amdgpu_buffer_rsrc_t r_x = make_rsrc(x, (int)sizeof(T) * n);
   // registers holding the next segment: vector slice, two counts, the band's entries
   // VEC: 16-byte slice loads and LDS stores (the host selects it when every realization's n and the
@@ -775,15 +818,9 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
         xr[u] = i < len ? load_elem<T>(r_x, base + i) : (T)0;
       }
     }
-    // the two counts as one 16-bit word, unpacked when staged (an unpack here would wait for this
-    // load and every load before it); an even row count keeps the pair 2-byte aligned
-    if ((rows & 1) == 0) {
-      craw = rr < rows ? __builtin_amdgcn_raw_buffer_load_b16(r_cnt, s * rows + rr, 0, kStreamPolicy) : 0u;
-    } else {
-      const uint32_t lo = rr < rows ? __builtin_amdgcn_raw_buffer_load_b8(r_cnt, s * rows + rr, 0, 0) : 0u;
-      const uint32_t hi = rr + 1 < rows ? __builtin_amdgcn_raw_buffer_load_b8(r_cnt, s * rows + rr + 1, 0, 0) : 0u;
-      craw = lo | (hi << 8);
-    }
+    // the two counts as one 16-bit word (the even stride keeps it 2-byte aligned), unpacked when
+    // staged: an unpack here would wait for this load and every load before it
+    craw = rr < rows ? __builtin_amdgcn_raw_buffer_load_b16(r_cnt, s * rows2 + rr, 0, kStreamPolicy) : 0u;
     nb0 = b0;
     nb1 = b1;
     const int nbw = __builtin_amdgcn_readfirstlane(b1 - b0);  // the band's entries (wave-uniform)
@@ -874,16 +911,173 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
   if (rr + 1 < rows) w_out[rr + 1] = (T)(acc1 * sj);
 }
 
+// FP32 form of the same product with its loads reorganised. Every band starts at a multiple of four
+// slots (the sort pads the runs with zeros), so a lane loads four columns with one 8-byte load and
+// four values with one 16-byte load, and stores its four products with one 16-byte LDS store. Every
+// lane issues the same loads for every segment: its band's quad slots, its share of the slice and its
+// counts. Slots past the band, past the block, and segments past the last are pointed past the end of
+// their buffer resource and read zeros without touching memory (the range check). So where a
+// segment's registers are read, the compiler knows how many later loads may stay in
+// flight. The loads of segment s + 2 are issued as soon as segment s's products are formed and stay
+// in flight while segment s + 1 is staged, about two segments before they are used; two register
+// sets take the segments of even and odd index. The sums are those of the form above, bit for bit:
+// the same products added to the same FP64 row sums in the same order.
+template <bool HAS_VAL, bool VEC>
+__global__ __launch_bounds__(kSegThreads) void k_spmv_seg4(LzArgs a, int j) {
+  using T = float;
+  extern __shared__ __align__(16) unsigned char smem[];
+  using SS = SegShape<T>;
+  constexpr int NT = kSegThreads, XP = SS::XP, WCAP = SS::WCAP, UQ = WCAP / 256, WO = kSegWaves + 1;
+  static_assert(WCAP % 256 == 0 && XP % 4 == 0, "whole quad slots and vector slice loads");
+  __shared__ __align__(16) T prod[kSegWaves * WCAP];
+  __shared__ int p_lds[kRowsPerBlock + 1];  // stream fallback only
+  __shared__ uint16_t wo_lds[kSegMax * WO];
+  __shared__ double chunks[kMaxChunks];
+  __shared__ double red[NT / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lb = logical_block();
+  const int blk = a.blkmap != nullptr ? lb : a.tasks[a.single_task].aux_blk + lb;
+  const SegBlock* d = a.seg_blk + blk;
+  const int n = d->n, rows = d->rows, flag = d->flag, E = d->nnz;
+  const int SEG = a.seg_cols, S = (n + SEG - 1) / SEG, rows2 = (rows + 1) & ~1, QEND = (E + 3) >> 2;
+  T* pw = prod + wv * WCAP;
+  const T* x = (const T*)a.V + d->vec_off + vslot(a, j) * n;
+  const uint8_t* cnt = a.seg_cnt + (size_t)blk * a.seg_stride;
+  const uint16_t* wo = a.seg_woff + (size_t)blk * a.seg_wstride;
+  const int rr = 2 * tid;  // this lane's two rows
+  const __amdgpu_buffer_rsrc_t r_pc = make_rsrc(a.seg_col + d->entries, 2 * E);
+  const __amdgpu_buffer_rsrc_t r_pv =
+      make_rsrc(HAS_VAL ? (const T*)a.seg_val + d->entries : nullptr, HAS_VAL ? 4 * E : 0);
+  const __amdgpu_buffer_rsrc_t r_cnt = make_rsrc(cnt, S * rows2);
+  const __amdgpu_buffer_rsrc_t r_x = make_rsrc(x, 4 * n);
+  struct Set {
+    float4 xq[VEC ? XP / 4 : 1];  // the slice, 16 bytes per load
+    T xr[VEC ? 1 : XP];           // the slice, one element per load
+    uint32_t craw;                // the lane's two 8-bit counts
+    uint64_t cq[UQ];              // four 16-bit columns per quad slot
+    float4 vq[HAS_VAL ? UQ : 1];  // four values per quad slot
+  };
+  // the loads of segment s into p (zeros for s >= S); [q0, q1) = the wave's band in quads
+  auto load = [&](Set& p, int s, int q0, int q1) {
+    const int base = s * SEG;
+    if constexpr (VEC) {
+#pragma unroll
+      for (int u = 0; u < XP / 4; ++u)
+        p.xq[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r_x, (base + (tid + u * NT) * 4) * 4, 0, 0));
+    } else {
+#pragma unroll
+      for (int u = 0; u < XP; ++u) p.xr[u] = load_elem<T>(r_x, base + tid + u * NT);
+    }
+    p.craw = __builtin_amdgcn_raw_buffer_load_b16(r_cnt, s * rows2 + rr, 0, kStreamPolicy);
+#pragma unroll
+    for (int u = 0; u < UQ; ++u) {
+      const int q = q0 + lane + 64 * u < q1 ? q0 + lane + 64 * u : QEND;  // past the band: out of range
+      p.cq[u] = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r_pc, 8 * q, 0, kStreamPolicy));
+      if constexpr (HAS_VAL)
+        p.vq[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r_pv, 16 * q, 0, kStreamPolicy));
+    }
+  };
+  Set A, B;
+  if (flag) load(A, 0, d->wo0[wv] >> 2, d->wo0[wv + 1] >> 2);  // consumed only if the step runs
+  const Ref ref = resolve(a);
+  const Task tk = a.tasks[ref.task];
+  RState* st = a.state + ref.task;
+  const int r0 = ref.blk * kRowsPerBlock;
+  T* w_out = (T*)a.W + tk.w_off + r0;
+  const int32_t* rp = a.row_ptr + tk.rowptr_off;
+  double sj;
+  if (!open_step(a, tk, st, ref.blk, j, chunks, &sj)) return;
+  if (!flag) {
+    const T* va = HAS_VAL ? (const T*)a.values + tk.nnz_off : nullptr;
+    spmv_stream_rows<T, HAS_VAL, NT, kSegWaves * WCAP>(rp, a.col_idx + tk.nnz_off, va, x, r0, rows, sj, p_lds, prod,
+                                                      w_out, red);
+    return;
+  }
+  for (int i = tid; i < S * WO; i += NT) wo_lds[i] = wo[i];
+  load(B, 1, S > 1 ? (int)wo[WO + wv] >> 2 : QEND, S > 1 ? (int)wo[WO + wv + 1] >> 2 : QEND);
+  int c0 = 0, c1 = 0, ex = 0;  // the current segment's counts of the lane's two rows, their offset in pw
+  auto stage = [&](const Set& p, int s) {
+    const int len = min(SEG, n - s * SEG);
+    T* xb = (T*)smem + (s & 1) * SEG;
+    if constexpr (VEC) {
+#pragma unroll
+      for (int u = 0; u < XP / 4; ++u) {
+        const int i = (tid + u * NT) * 4;
+        if (i < len) *(float4*)(xb + i) = p.xq[u];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < XP; ++u) {
+        const int i = tid + u * NT;
+        if (i < len) xb[i] = p.xr[u];
+      }
+    }
+    const uint32_t cr = rr < rows ? p.craw : 0u;
+    c0 = (int)(cr & 0xFF);
+    c1 = (int)((cr >> 8) & 0xFF);
+    ex = wave_excl_scan(c0 + c1);
+  };
+  stage(A, 0);
+  __syncthreads();  // slice 0 and the band table published
+  double acc0 = 0.0, acc1 = 0.0;  // rows rr and rr + 1
+  // segment s: its products from set p, then p takes the loads of segment s + 2, the row sums, and
+  // segment s + 1 staged from set q
+  auto segment = [&](int s, Set& p, const Set& q) {
+    const T* xb = (const T*)smem + (s & 1) * SEG;
+    const int bn = __builtin_amdgcn_readfirstlane((int)wo_lds[s * WO + wv + 1] - (int)wo_lds[s * WO + wv]);
+#pragma unroll
+    for (int u = 0; u < UQ; ++u) {
+      if (u * 256 < bn) {  // wave-uniform: quad slots wholly past the band form no products
+        const uint64_t c4 = p.cq[u];
+        const T x0 = xb[(int)(c4 & 0xFFFF)], x1 = xb[(int)((c4 >> 16) & 0xFFFF)];
+        const T x2 = xb[(int)((c4 >> 32) & 0xFFFF)], x3 = xb[(int)(c4 >> 48)];
+        float4 pr;
+        if constexpr (HAS_VAL) {
+          pr.x = p.vq[u].x * x0;
+          pr.y = p.vq[u].y * x1;
+          pr.z = p.vq[u].z * x2;
+          pr.w = p.vq[u].w * x3;
+        } else {
+          pr = make_float4(x0, x1, x2, x3);
+        }
+        *(float4*)(pw + 4 * (lane + 64 * u)) = pr;
+      }
+    }
+    load(p, s + 2, s + 2 < S ? (int)wo_lds[(s + 2) * WO + wv] >> 2 : QEND,
+         s + 2 < S ? (int)wo_lds[(s + 2) * WO + wv + 1] >> 2 : QEND);
+    wave_lds_sync();
+    for (int k = ex; k < ex + c0; ++k) acc0 += (double)pw[k];
+    for (int k = ex + c0; k < ex + c0 + c1; ++k) acc1 += (double)pw[k];
+    wave_lds_sync();  // the band's next products overwrite pw
+    if (s + 1 < S) {
+      stage(q, s + 1);  // the other buffer's last readers were segment s - 1's products
+      __syncthreads();
+    }
+  };
+  // pairs of segments, then an odd last one: the loop's back edge always follows a segment of set B,
+  // so the count of loads in flight where set A is read is the same on every path into the loop head
+  int s = 0;
+  for (; s + 1 < S; s += 2) {
+    segment(s, A, B);
+    segment(s + 1, B, A);
+  }
+  if (s < S) segment(s, A, B);
+  if (rr < rows) w_out[rr] = (T)(acc0 * sj);
+  if (rr + 1 < rows) w_out[rr + 1] = (T)(acc1 * sj);
+}
+
 template <typename T>
 constexpr size_t seg_static_bytes() {
   return (size_t)kSegWaves * SegShape<T>::WCAP * sizeof(T) + (size_t)(kRowsPerBlock + 1) * 4 +
          (size_t)kSegMax * (kSegWaves + 1) * 2 + kMaxChunks * 8 + (kSegThreads / 64) * 8 + 512;
 }
 
+// Static LDS of k_seg_prepare (row pointers, band padding, scan scratch) with a margin.
+constexpr size_t kSegPrepStatic = (size_t)(kRowsPerBlock + 1) * 4 + (size_t)kSegMax * kSegWaves * 4 + 1024;
 // Staging capacity (entries) of k_seg_prepare next to smax x kRowsPerBlock 16-bit counters.
 template <typename T, bool HAS_VAL>
 int seg_prepare_cap(int smax) {
-  const size_t fixed = (size_t)(kRowsPerBlock + 1) * 4 + 1024;
+  const size_t fixed = kSegPrepStatic;
   const size_t cnt = ((size_t)smax * kRowsPerBlock * 2 + 15) / 16 * 16;
   const size_t per = 4 + (HAS_VAL ? sizeof(T) : 0);
   const size_t cap = (kLdsBytes - fixed - cnt) / per;
@@ -1304,12 +1498,18 @@ hipError_t step_any(int lanes, int j, const LzArgs& a, int64_t nb, hipStream_t s
     return hipGetLastError();
   }
   if (a.seg_cols > 0) {
-    if (a.seg_vec)
-      hipLaunchKernelGGL((k_spmv_seg<T, HAS_VAL, true>), dim3((unsigned)nb), dim3(kSegThreads),
-                         2 * (size_t)a.seg_cols * sizeof(T), s, a, j);
-    else
-      hipLaunchKernelGGL((k_spmv_seg<T, HAS_VAL, false>), dim3((unsigned)nb), dim3(kSegThreads),
-                         2 * (size_t)a.seg_cols * sizeof(T), s, a, j);
+    const size_t dyn = 2 * (size_t)a.seg_cols * sizeof(T);
+    if constexpr (sizeof(T) == 4) {
+      if (a.seg_vec)
+        hipLaunchKernelGGL((k_spmv_seg4<HAS_VAL, true>), dim3((unsigned)nb), dim3(kSegThreads), dyn, s, a, j);
+      else
+        hipLaunchKernelGGL((k_spmv_seg4<HAS_VAL, false>), dim3((unsigned)nb), dim3(kSegThreads), dyn, s, a, j);
+    } else {
+      if (a.seg_vec)
+        hipLaunchKernelGGL((k_spmv_seg<T, HAS_VAL, true>), dim3((unsigned)nb), dim3(kSegThreads), dyn, s, a, j);
+      else
+        hipLaunchKernelGGL((k_spmv_seg<T, HAS_VAL, false>), dim3((unsigned)nb), dim3(kSegThreads), dyn, s, a, j);
+    }
     return hipGetLastError();
   }
   if (a.seglen > 0) {
@@ -1366,11 +1566,19 @@ namespace {
 template <typename T>
 hipError_t prepare_seg_t() {
   const size_t dyn = kLdsBytes - seg_static_bytes<T>();
-  const size_t dyn_prep = kLdsBytes - (size_t)(kRowsPerBlock + 1) * 4 - 1024;
-  hipError_t e = allow_lds(k_spmv_seg<T, true, true>, dyn);
-  if (e == hipSuccess) e = allow_lds(k_spmv_seg<T, false, true>, dyn);
-  if (e == hipSuccess) e = allow_lds(k_spmv_seg<T, true, false>, dyn);
-  if (e == hipSuccess) e = allow_lds(k_spmv_seg<T, false, false>, dyn);
+  const size_t dyn_prep = kLdsBytes - kSegPrepStatic;
+  hipError_t e = hipSuccess;
+  if constexpr (sizeof(T) == 4) {
+    e = allow_lds(k_spmv_seg4<true, true>, dyn);
+    if (e == hipSuccess) e = allow_lds(k_spmv_seg4<false, true>, dyn);
+    if (e == hipSuccess) e = allow_lds(k_spmv_seg4<true, false>, dyn);
+    if (e == hipSuccess) e = allow_lds(k_spmv_seg4<false, false>, dyn);
+  } else {
+    e = allow_lds(k_spmv_seg<T, true, true>, dyn);
+    if (e == hipSuccess) e = allow_lds(k_spmv_seg<T, false, true>, dyn);
+    if (e == hipSuccess) e = allow_lds(k_spmv_seg<T, true, false>, dyn);
+    if (e == hipSuccess) e = allow_lds(k_spmv_seg<T, false, false>, dyn);
+  }
   if (e == hipSuccess) e = allow_lds(k_seg_prepare<T, true>, dyn_prep);
   if (e == hipSuccess) e = allow_lds(k_seg_prepare<T, false>, dyn_prep);
   return e;

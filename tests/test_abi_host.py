@@ -178,8 +178,9 @@ def test_plan_balanced_workspace_arithmetic(seg_len, per):
 def test_plan_segmented_workspace_arithmetic():
     # the column-segmented form appends: block flags (int32), per-(segment, row) counts (8 bits,
     # max segments x 2048 per block), wave-band offsets (16 bits, max segments x 17 per block),
-    # 64-byte block descriptors, in-segment columns (16 bits per entry); no value copy for a
-    # pattern-only batch
+    # 64-byte block descriptors, in-segment columns (16 bits per slot: the entries, then per block
+    # 3 x 16 x 32 + 8 slots for the zero padding of the wave bands' runs and the alignment of the
+    # block's first slot); no value copy for a pattern-only batch
     d, keep = make_desc(G=2, nreal=(2, 3), n=(3000, 70), nnz=(10, 10, 10, 10, 10))
     rc, h = create(d)
     rc, ws, _ = plan(h, m=30, spmv=4, seg_len=1000)
@@ -190,7 +191,7 @@ def test_plan_segmented_workspace_arithmetic():
     off = align(off + 3 * 2048 * blocks)      # per-(segment, row) counts
     off = align(off + 2 * 3 * 17 * blocks)    # per-(segment, wave band) entry offsets (16 bits)
     off = align(off + 64 * blocks)            # block descriptors
-    off = align(off + 2 * 50)
+    off = align(off + 2 * (50 + blocks * (3 * 16 * 32 + 8) + 8))
     assert ws == off
     rc, _, _ = plan(h, m=30, spmv=4, seg_len=50)  # 60 segments
     assert rc == A.EBTC_EINVAL and "segments" in A.lib().ebtc_last_error().decode()

@@ -31,9 +31,10 @@ def symmetric_weights(hb, seed=0):
 
 
 def seg_eligible(hb, seg_len, dtype):
-    """Fraction of row blocks that take the sorted path, by the rules of the prepare kernel: at most
-    65535 entries, 255 entries of one row in one segment, and a wave band's (128 rows') entries in one
-    segment within its product slots (768 FP32 / 384 FP64)."""
+    """Fraction of row blocks that take the sorted path, by the rules of the prepare kernel: its entries
+    and the padding of its wave bands (up to 3 slots per band) within 65535 slots, 255 entries of one
+    row in one segment, and a wave band's (128 rows') entries in one segment, padded to a multiple of
+    four, within its product slots (768 FP32 / 384 FP64)."""
     seg = seg_len or (6144 if dtype == "f64" else 12288)
     wcap = 384 if dtype == "f64" else 768
     ok = tot = 0
@@ -44,13 +45,13 @@ def seg_eligible(hb, seg_len, dtype):
             b1 = min(n, b0 + 2048)
             sl = slice(int(rp[b0]), int(rp[b1]))
             tot += 1
-            if rp[b1] - rp[b0] > 65535:
+            S = (n + seg - 1) // seg
+            if rp[b1] - rp[b0] + 3 * 16 * S > 65535:
                 continue
             sg, rw = ci[sl] // seg, rows_of[sl] - b0
-            S = (n + seg - 1) // seg
             per_row = np.bincount(sg * 2048 + rw, minlength=S * 2048)
             per_band = np.bincount(sg * 16 + rw // 128, minlength=S * 16)
-            ok += int(per_row.max(initial=0) <= 255 and per_band.max(initial=0) <= wcap)
+            ok += int(per_row.max(initial=0) <= 255 and ((per_band + 3) // 4 * 4).max(initial=0) <= wcap)
     return ok / tot
 
 
