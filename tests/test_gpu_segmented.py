@@ -90,6 +90,18 @@ def test_segmented_equals_stream_bitwise(gpu_lib, dtype, seg_len, weighted):
         check_against_oracle(hb, seg, b, w.m, dtype, K=50)
 
 
+@pytest.mark.parametrize("seg_len", [1001, 2003])
+def test_segmented_fp32_ragged_slices_bitwise(gpu_lib, seg_len):
+    # FP32 with an odd n and segment lengths that are not multiples of four: the vector slice loads
+    # and stores one element at a time, the last block (809 rows) is odd, its pad row counts nothing
+    w = dataclasses.replace(C.scaled(C.workload(1), n=9001, N=2), dtype="f32")
+    hb = C.build(w, with_values=True)
+    hb.values = symmetric_weights(hb, seed=3)
+    assert seg_eligible(hb, seg_len, "f32") == 1.0
+    b, ref, seg = run_pair(hb, w.m, seg_len=seg_len)
+    assert_bitwise(ref, seg)
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_segmented_large_segments_prefetched_bitwise(gpu_lib, dtype):
     # n = 40000, degree 8: the default segment (12288 FP32 / 6144 FP64 columns, two LDS buffers)
