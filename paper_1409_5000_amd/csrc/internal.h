@@ -55,7 +55,7 @@ struct SegBlock {
   int16_t rows;      // rows of the block
   int16_t flag;      // the block's seg_flag
   uint16_t wo0[17];  // band starts of segment 0 (the first 17 entries of its seg_woff table)
-  uint16_t pad;
+  uint16_t quads;    // quad slots (four entries each, 256 per wave) of its largest padded band, 1..3
 };
 static_assert(sizeof(SegBlock) == 64, "SegBlock layout");
 

@@ -541,6 +541,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
   __shared__ int rp_lds[kRowsPerBlock + 1];
   __shared__ int wtot[NT / 64];
   __shared__ int bad;
+  __shared__ int maxband;  // slots of the block's largest padded band
   const Ref ref = resolve(a);
   const Task tk = a.tasks[ref.task];
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, rows = min(n - r0, kRowsPerBlock);
@@ -553,7 +554,10 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
   const int32_t* rp = a.row_ptr + tk.rowptr_off;
   for (int i = tid; i <= rows; i += NT) rp_lds[i] = rp[r0 + i];
   for (int i = tid; i < tot; i += NT) cnt[i] = 0;
-  if (tid == 0) bad = 0;
+  if (tid == 0) {
+    bad = 0;
+    maxband = 0;
+  }
   __syncthreads();
   const int e0 = rp_lds[0];
   const int nz = rp_lds[rows] - e0;
@@ -584,6 +588,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
       desc->nnz = slots;
       desc->rows = (int16_t)rows;
       desc->flag = (int16_t)f;
+      desc->quads = (uint16_t)min(3, max(1, (maxband + 255) / 256));
     }
   };
   // offsets must fit 16 bits, the padding included (at most three slots per wave band)
@@ -679,7 +684,11 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
     const int v = band_start(sg, w);
     wo[i] = (uint16_t)v;
     if (i <= kSegWaves) desc->wo0[i] = (uint16_t)v;  // segment 0 (i = w)
-    if (w < kSegWaves && band_start(sg, w + 1) - v > SegShape<T>::WCAP) bad = 1;
+    if (w < kSegWaves) {
+      const int len = band_start(sg, w + 1) - v;
+      if (len > SegShape<T>::WCAP) bad = 1;
+      atomicMax(&maxband, len);
+    }
   }
   __syncthreads();
   if (bad) {
@@ -922,22 +931,17 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
 // in flight while segment s + 1 is staged, about two segments before they are used; two register
 // sets take the segments of even and odd index. The sums are those of the form above, bit for bit:
 // the same products added to the same FP64 row sums in the same order.
-template <bool HAS_VAL, bool VEC>
-__global__ __launch_bounds__(kSegThreads) void k_spmv_seg4(LzArgs a, int j) {
+// One row block with UQ quad slots per lane and segment (its largest band holds at most 256 UQ
+// slots). smem: the two slice buffers; prod: the waves' product slots; p_lds, chunks, red: scratch of
+// the stream arithmetic and the step's opening.
+template <bool HAS_VAL, bool VEC, int UQ>
+__device__ inline void seg4_block(const LzArgs& a, int j, int blk, const SegBlock* d, unsigned char* smem,
+                                  float* prod, int* p_lds, uint16_t* wo_lds, double* chunks, double* red) {
   using T = float;
-  extern __shared__ __align__(16) unsigned char smem[];
   using SS = SegShape<T>;
-  constexpr int NT = kSegThreads, XP = SS::XP, WCAP = SS::WCAP, UQ = WCAP / 256, WO = kSegWaves + 1;
-  static_assert(WCAP % 256 == 0 && XP % 4 == 0, "whole quad slots and vector slice loads");
-  __shared__ __align__(16) T prod[kSegWaves * WCAP];
-  __shared__ int p_lds[kRowsPerBlock + 1];  // stream fallback only
-  __shared__ uint16_t wo_lds[kSegMax * WO];
-  __shared__ double chunks[kMaxChunks];
-  __shared__ double red[NT / 64];
+  constexpr int NT = kSegThreads, XP = SS::XP, WCAP = SS::WCAP, WO = kSegWaves + 1;
+  static_assert(UQ >= 1 && 256 * UQ <= WCAP && XP % 4 == 0, "quad slots within the product slots");
   const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int lb = logical_block();
-  const int blk = a.blkmap != nullptr ? lb : a.tasks[a.single_task].aux_blk + lb;
-  const SegBlock* d = a.seg_blk + blk;
   const int n = d->n, rows = d->rows, flag = d->flag, E = d->nnz;
   const int SEG = a.seg_cols, S = (n + SEG - 1) / SEG, rows2 = (rows + 1) & ~1, QEND = (E + 3) >> 2;
   T* pw = prod + wv * WCAP;
@@ -1064,6 +1068,28 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg4(LzArgs a, int j) {
   if (s < S) segment(s, A, B);
   if (rr < rows) w_out[rr] = (T)(acc0 * sj);
   if (rr + 1 < rows) w_out[rr + 1] = (T)(acc1 * sj);
+}
+
+template <bool HAS_VAL, bool VEC>
+__global__ __launch_bounds__(kSegThreads) void k_spmv_seg4(LzArgs a, int j) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ __align__(16) float prod[kSegWaves * SegShape<float>::WCAP];
+  __shared__ int p_lds[kRowsPerBlock + 1];  // stream fallback only
+  __shared__ uint16_t wo_lds[kSegMax * (kSegWaves + 1)];
+  __shared__ double chunks[kMaxChunks];
+  __shared__ double red[kSegThreads / 64];
+  // the first segments' loads wait on the block's descriptor alone: in a batched launch the logical
+  // workgroup is the block's index in the form's arenas (the launch covers the form's blocks in order)
+  const int lb = logical_block();
+  const int blk = a.blkmap != nullptr ? lb : a.tasks[a.single_task].aux_blk + lb;
+  const SegBlock* d = a.seg_blk + blk;
+  // the block's quad slots per segment (one branch per workgroup: each count is its own loop, so the
+  // number of loads in flight stays fixed inside it)
+  switch (d->quads) {
+    case 1: seg4_block<HAS_VAL, VEC, 1>(a, j, blk, d, smem, prod, p_lds, wo_lds, chunks, red); break;
+    case 2: seg4_block<HAS_VAL, VEC, 2>(a, j, blk, d, smem, prod, p_lds, wo_lds, chunks, red); break;
+    default: seg4_block<HAS_VAL, VEC, 3>(a, j, blk, d, smem, prod, p_lds, wo_lds, chunks, red); break;
+  }
 }
 
 template <typename T>
