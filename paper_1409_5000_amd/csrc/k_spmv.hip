@@ -547,6 +547,15 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, rows = min(n - r0, kRowsPerBlock);
   const int blk = tk.aux_blk + ref.blk, tid = threadIdx.x;  // the block in the form's arenas
   const int SEG = a.seg_cols, S = (n + SEG - 1) / SEG, tot = S * rows;
+  // a column's segment c / SEG without an integer division per entry: the FP32 quotient, then one
+  // step of correction (c < 2^24, so the estimate is off by at most one)
+  const float inv_seg = 1.0f / (float)SEG;
+  auto seg_of = [&](int c) {
+    int q = (int)((float)c * inv_seg);
+    q -= q * SEG > c ? 1 : 0;
+    q += (q + 1) * SEG <= c ? 1 : 0;
+    return q;
+  };
   uint16_t* cnt = (uint16_t*)smem;  // [S * rows]: counts, then insertion cursors
   const size_t cnt_bytes = ((size_t)(a.seg_stride) * 2 + 15) / 16 * 16;
   int* lci = (int*)(smem + cnt_bytes);
@@ -612,7 +621,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
                                         bad = 1;
                                         return;
                                       }
-                                      const int idx = (c / SEG) * rows + r;
+                                      const int idx = seg_of(c) * rows + r;
                                       if (cnt[idx] == 255) {  // the step kernel reads 8-bit counts
                                         bad = 1;
                                         return;
@@ -710,7 +719,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
                                     double acc = 0.0;
                                     for (; k < e; ++k) {
                                       const int c = cs[k];
-                                      const int sg = c / SEG;
+                                      const int sg = seg_of(c);
                                       const int pos = cnt[sg * rows + r];
                                       cnt[sg * rows + r] = (uint16_t)(pos + 1);
                                       pc[pos] = (uint16_t)(c - sg * SEG);
