@@ -121,6 +121,7 @@ struct ebtc_batch {
   std::string fh_sig;
   std::vector<int32_t> topk_k;
   std::vector<int64_t> topk_off;
+  std::vector<int32_t> topk_cgraph, topk_cbegin;  // chunked top-K: each chunk's graph, each graph's first chunk
   std::vector<ExecEntry> execs;
   hipStream_t capture_stream = nullptr;
   // SpMV forms chosen by ebtc_tune (empty = not tuned), used when opts->spmv is EBTC_SPMV_AUTO:
@@ -130,6 +131,13 @@ struct ebtc_batch {
 };
 
 namespace {
+
+// Chunks of the chunked top-K: kTkChunk scores each, at least one per graph.
+int64_t topk_chunks(const ebtc_batch* b) {
+  int64_t c = 0;
+  for (int32_t g = 0; g < b->G; ++g) c += (b->n[g] + kTkChunk - 1) / kTkChunk;
+  return c;
+}
 
 int check_opts(const ebtc_opts* o) {
   if (!o) return fail(EBTC_EINVAL, "opts is NULL");
@@ -1682,6 +1690,11 @@ int ebtc_topk_ws_bytes(ebtc_batch* b, size_t* ws_bytes) {
   g_err.clear();
   if (!b || !ws_bytes) return fail(EBTC_EINVAL, "NULL batch or output");
   *ws_bytes = align_up(sizeof(GraphInfo) * b->G) + align_up(sizeof(int32_t) * b->G) + align_up(sizeof(int64_t) * b->G);
+  if (b->n_max >= kTopkMultiMin) {  // the chunked selection: chunk tables and its scratch
+    const int64_t nchunks = topk_chunks(b);
+    *ws_bytes += align_up(sizeof(int32_t) * (size_t)nchunks) + align_up(sizeof(int32_t) * ((size_t)b->G + 1)) +
+                 topk_multi_scratch_bytes(b->G, nchunks);
+  }
   return EBTC_OK;
 }
 
@@ -1710,8 +1723,29 @@ int ebtc_topk(ebtc_batch* b, const void* scores, const int32_t* k_per_graph, int
   EBTC_HIP(hipMemcpyAsync(w, b->graphs.data(), sizeof(GraphInfo) * b->G, hipMemcpyHostToDevice, s));
   EBTC_HIP(hipMemcpyAsync(w + o1, b->topk_k.data(), sizeof(int32_t) * b->G, hipMemcpyHostToDevice, s));
   EBTC_HIP(hipMemcpyAsync(w + o2, b->topk_off.data(), sizeof(int64_t) * b->G, hipMemcpyHostToDevice, s));
-  EBTC_LAUNCH(launch_topk(b->dtype, (const GraphInfo*)w, b->G, (const int32_t*)(w + o1), (const int64_t*)(w + o2),
-                          scores, idx_out, val_out, s));
+  const size_t o3 = o2 + align_up(sizeof(int64_t) * b->G);
+  if (b->n_max < kTopkMultiMin) {  // one workgroup per graph
+    EBTC_LAUNCH(launch_topk(b->dtype, (const GraphInfo*)w, b->G, (const int32_t*)(w + o1), (const int64_t*)(w + o2),
+                            scores, idx_out, val_out, s));
+    return EBTC_OK;
+  }
+  // chunks of kTkChunk scores, graph by graph (a graph's chunks follow its node ids)
+  const int64_t nchunks = topk_chunks(b);
+  b->topk_cgraph.resize((size_t)nchunks);
+  b->topk_cbegin.resize((size_t)b->G + 1);
+  int32_t c = 0;
+  for (int32_t g = 0; g < b->G; ++g) {
+    b->topk_cbegin[g] = c;
+    const int32_t nc = (b->n[g] + kTkChunk - 1) / kTkChunk;
+    for (int32_t i = 0; i < nc; ++i) b->topk_cgraph[c++] = g;
+  }
+  b->topk_cbegin[b->G] = c;
+  const size_t o4 = o3 + align_up(sizeof(int32_t) * (size_t)nchunks), o5 = o4 + align_up(sizeof(int32_t) * ((size_t)b->G + 1));
+  EBTC_HIP(hipMemcpyAsync(w + o3, b->topk_cgraph.data(), sizeof(int32_t) * (size_t)nchunks, hipMemcpyHostToDevice, s));
+  EBTC_HIP(hipMemcpyAsync(w + o4, b->topk_cbegin.data(), sizeof(int32_t) * ((size_t)b->G + 1), hipMemcpyHostToDevice, s));
+  EBTC_LAUNCH(launch_topk_multi(b->dtype, (const GraphInfo*)w, b->G, (const int32_t*)(w + o1), (const int64_t*)(w + o2),
+                                scores, idx_out, val_out, (const int32_t*)(w + o3), (const int32_t*)(w + o4), nchunks,
+                                w + o5, s));
   return EBTC_OK;
 }
 

@@ -268,6 +268,25 @@ hipError_t launch_tridiag_arrays(int32_t count, int32_t k, const double* alpha, 
 // ---- launchers (k_topk.hip)
 hipError_t launch_topk(int dtype, const GraphInfo* graphs, int32_t G, const int32_t* kvec, const int64_t* koff,
                        const void* scores, int32_t* idx_out, void* val_out, hipStream_t s);
+// Top-K with many workgroups per graph, for batches holding a graph of at least kTopkMultiMin nodes:
+// the radix passes count chunks of kTkChunk scores per workgroup into per-graph histograms, one wave
+// per graph picks each pass's digit, the candidates are collected by chunk and sorted per graph.
+constexpr int kTopkMultiMin = 32768;
+constexpr int kTkChunk = 16384;
+// Per-graph state of the chunked selection: the digits chosen so far (prefix under mask), the entries
+// still needed at the prefix, the ties at the final key, and the entries above it placed so far.
+struct TkState {
+  uint64_t prefix, mask;
+  int32_t remaining, eq_total, ngt, pad;
+};
+static_assert(sizeof(TkState) == 32, "TkState layout");
+// Scratch of the chunked top-K (device, 256-byte aligned sections): chunk_graph [nchunks] (graph of
+// each chunk, host-built), chunk_begin [G + 1] (first chunk of each graph, host-built), then the
+// kernels' own arrays. topk_multi_scratch_bytes gives the size of the part after the two host tables.
+size_t topk_multi_scratch_bytes(int32_t G, int64_t nchunks);
+hipError_t launch_topk_multi(int dtype, const GraphInfo* graphs, int32_t G, const int32_t* kvec, const int64_t* koff,
+                             const void* scores, int32_t* idx_out, void* val_out, const int32_t* chunk_graph,
+                             const int32_t* chunk_begin, int64_t nchunks, void* scratch, hipStream_t s);
 
 // ---- launchers (k_topk.hip, structural check)
 hipError_t launch_validate(const int32_t* row_ptr, const int32_t* col_idx, const Task* tasks, const int64_t* nnz,

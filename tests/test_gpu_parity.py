@@ -523,6 +523,45 @@ def test_topk_mixed_signs_and_dominant_bins(gpu_lib, dtype):
         o += k
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_topk_chunked_selection(gpu_lib, dtype):
+    # a batch holding a graph of at least 32768 nodes selects with many workgroups per graph (chunks of
+    # 16384 scores): every graph of the batch, small ones included, against brute force; heavy ties
+    # whose needed ranks cross chunk boundaries, K = 0, K = 4096, negative scores and zeros of both signs
+    torch = torch_mod()
+    rng = np.random.default_rng(23)
+    sizes = [1, 5, 2049, 40000, 70001, 100003]
+
+    class B:
+        pass
+    hb = B()
+    hb.dtype = dtype
+    hb.n = np.array(sizes, np.int32)
+    hb.nreal = np.ones(len(sizes), np.int32)
+    hb.rowptr_off = np.concatenate([[0], np.cumsum(np.array(sizes) + 1)[:-1]]).astype(np.int64)
+    hb.nnz_off = np.zeros(len(sizes) + 1, np.int64)
+    hb.row_ptr = np.zeros(int(np.sum(np.array(sizes) + 1)), np.int32)
+    hb.col_idx = np.zeros(1, np.int32)
+    hb.values = None
+    b = api().Batch.from_host(hb)
+    blocks = [rng.integers(0, 7, size=n).astype(dtype) for n in sizes]  # about n / 7 ties per value
+    blocks[3] = -blocks[3]
+    blocks[3][::11] = -0.0
+    blocks[4][rng.integers(0, sizes[4], 50)] = 1e30
+    blocks[5] = rng.standard_normal(sizes[5]).astype(dtype)
+    blocks[5][::9] = blocks[5][5]
+    s = torch.as_tensor(np.concatenate(blocks)).to("cuda")
+    ks = [1, 0, 2049, 4096, 4096, 3000]
+    idx, val = b.topk(s, ks)
+    idx, val = idx.cpu().numpy(), val.cpu().numpy()
+    o = 0
+    for blk, k in zip(blocks, ks):
+        order = np.lexsort((np.arange(blk.size), -blk.astype(np.float64)))[:k]
+        assert idx[o:o + k].tolist() == order.tolist()
+        assert np.array_equal(val[o:o + k], blk[order])
+        o += k
+
+
 def test_validate_detects_bad_realization(gpu_lib):
     good = gs.random_graph(300, 0.05, 1)
     bad = gs.random_graph(300, 0.05, 2)
