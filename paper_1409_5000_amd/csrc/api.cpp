@@ -66,7 +66,7 @@ struct FormHost {
 struct Layout {
   int m_slots = 0;
   size_t off_tasks = 0, off_graphs = 0, off_blkmap = 0, off_state = 0, off_part = 0, off_npart = 0, off_V = 0,
-         off_W = 0, off_U = 0;
+         off_W = 0, off_U = 0, off_live = 0;
   std::vector<FormLayout> fl;  // per SpMV form of the plan
   size_t total = 0;
   int64_t total_blocks = 0;
@@ -364,6 +364,8 @@ Layout make_layout(const ebtc_batch* b, const ebtc_opts* o, const BatchPlan& bp)
   off = align_up(off + sizeof(double) * kPartStride * blocks);
   L.off_npart = off;
   off = align_up(off + sizeof(double) * blocks);
+  L.off_live = off;
+  off = align_up(off + sizeof(int32_t) * kMLimit);
   L.off_V = off;
   off = align_up(off + es * (size_t)L.m_slots * rows);
   L.off_W = off;
@@ -584,6 +586,7 @@ LzArgs make_args(const ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout
   a.eps = b->dtype == EBTC_F64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
   a.window = o->reorth == 0 ? 2 : 0;
   a.stop_mused = 0;
+  a.live = nullptr;
   return a;
 }
 
@@ -825,8 +828,12 @@ int run_pass2(const ebtc_batch* b, const ebtc_opts* o, const LzArgs& a1, const s
               int64_t nblocks, hipStream_t s, Prof* prof) {
   LzArgs a = a1;
   a.stop_mused = 1;
+  a.live = nullptr;  // the live counts belong to the first pass
   std::vector<FArgs> fa = fa1;
-  for (FArgs& x : fa) x.a.stop_mused = 1;
+  for (FArgs& x : fa) {
+    x.a.stop_mused = 1;
+    x.a.live = nullptr;
+  }
   const bool has_val = b->values != nullptr;
   const int steps = o->m > 0 ? o->m : o->m_max;
   EBTC_PHASE(prof, EBTC_PHASE_START, launch_restart(b->dtype, a, nblocks, s));
@@ -852,6 +859,9 @@ int enqueue_batched(ebtc_batch* b, const ebtc_opts* o, char* ws, const Layout& L
   LzArgs a = make_args(b, o, ws, L);
   a.unit_start = 1;  // k_start (and k_restart) set v_0 = 1
   a.diag = diag;
+  // adaptive m: the checks count the realizations still running, and once none is, the launches of
+  // the remaining steps up to the cap return at once
+  if (o->m == 0 && sched != EBTC_SCHED_SINGLE) a.live = (int32_t*)(ws + L.off_live);
   const std::vector<FArgs> fa = form_args(b, a, ws, L, bp);
   EBTC_LAUNCH(launch_blkmap(a.tasks, b->R, (int32_t*)(ws + L.off_blkmap), s));
   const int32_t maxblk = (b->n_max + kRowsPerBlock - 1) / kRowsPerBlock;

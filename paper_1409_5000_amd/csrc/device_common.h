@@ -28,6 +28,12 @@ __device__ inline bool step_skipped(const LzArgs& a, const RState* st, int j) {
   return st->done || (a.stop_mused && j + 1 >= st->m_used);
 }
 
+// True when every realization of the launch stopped at step j - 1's adaptive check: the launch's
+// workgroups return before reading anything else (the captured sequence runs to the step cap).
+__device__ inline bool all_stopped(const LzArgs& a, int j) {
+  return a.live != nullptr && j > 0 && a.live[j - 1] == 0;
+}
+
 __device__ inline Ref resolve(const LzArgs& a) {
   const int lb = logical_block();
   if (a.blkmap == nullptr) return {a.single_task, lb};

@@ -182,6 +182,9 @@ struct LzArgs {
   // raw basis kept in a ring of window + 1 slots (vector i in slot i % (window + 1))
   int32_t window;
   int32_t stop_mused;      // second pass of the memory-bounded form: steps j >= m_used - 1 are skipped
+  // adaptive batched pass: live[j] = realizations still running after step j's check (zeroed by the
+  // start kernel, counted by the check); every kernel of step j + 1 returns at once when it is 0
+  int32_t* live;
   int32_t unit_start;      // 1: v_0 is the raw all-ones vector, so step 0's product is A's row sums
   int32_t first_in_prepare;  // 1: the column-segmented sort also writes step 0's product (weighted
                              // graphs), so the step sequence launches none for it

@@ -27,6 +27,7 @@ namespace {
 // vector on (at most P of them: a window wider than kDotsWindow takes one launch per kDotsWindow).
 template <typename T, int P, int RING>
 __global__ __launch_bounds__(dots_threads(P, sizeof(T))) void k_dots_step(LzArgs a, int j, int c0) {
+  if (all_stopped(a, j)) return;
   constexpr int NT = dots_threads(P, sizeof(T));
   __shared__ double red[(NT / 64) * P];
   const Ref ref = resolve(a);
@@ -43,6 +44,7 @@ __global__ __launch_bounds__(dots_threads(P, sizeof(T))) void k_dots_step(LzArgs
 // Second Gram-Schmidt pass: dots of the once-orthogonalised vector (stored in the slot of j+1).
 template <typename T, int P, int RING>
 __global__ __launch_bounds__(kBlock) void k_dots_again(LzArgs a, int j, int c0) {
+  if (all_stopped(a, j)) return;
   __shared__ double red[kWaves * P];
   const Ref ref = resolve(a);
   const Task tk = a.tasks[ref.task];
@@ -58,6 +60,7 @@ __global__ __launch_bounds__(kBlock) void k_dots_again(LzArgs a, int j, int c0) 
 
 template <typename T, int P, int RING>
 __global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, int final_pass, int second) {
+  if (all_stopped(a, j)) return;
   __shared__ double cs[P];
   __shared__ double csum[P][kMaxChunks];
   __shared__ double red[kWaves];
@@ -76,6 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_update(LzArgs a, int j, int from_w, 
 // paths a batch takes.
 template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_dots_update_1(LzArgs a, int j) {
+  if (all_stopped(a, j)) return;
   constexpr int NT = dots_threads(P, sizeof(T));
   __shared__ double red_d[(NT / 64) * P];
   __shared__ double cs[P];
@@ -93,6 +97,8 @@ __global__ __launch_bounds__(kBlock) void k_dots_update_1(LzArgs a, int j) {
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_start(LzArgs a) {
+  if (a.live != nullptr && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < kMLimit; i += kBlock) a.live[i] = 0;
   const Ref ref = resolve(a);
   const Task tk = a.tasks[ref.task];
   const int n = tk.n, r0 = ref.blk * kRowsPerBlock, r1 = min(n, r0 + kRowsPerBlock);

@@ -108,6 +108,7 @@ __device__ inline void spmv_direct_block(const int32_t* __restrict__ rp, const i
 
 template <typename T, bool HAS_VAL, int L>
 __global__ __launch_bounds__(kBlock) void k_spmv_step(LzArgs a, int j) {
+  if (all_stopped(a, j)) return;
   __shared__ int rp_lds[kRowsPerBlock + 1];
   __shared__ T w_lds[kRowsPerBlock];
   __shared__ short hubs[kRowsPerBlock];
@@ -141,6 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_step(LzArgs a, int j) {
 // w / 8 (q = w % 8); the realization of that block comes from the usual workgroup map.
 template <typename T, bool HAS_VAL>
 __global__ __launch_bounds__(kBlock) void k_spmv_stream(LzArgs a, int j) {
+  if (all_stopped(a, j)) return;
   constexpr int SUB = kRowsPerBlock / kStreamRows;
   __shared__ int rp_lds[kStreamRows + 1];
   __shared__ T prod[StreamShape<T>::CAP];
@@ -218,6 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_bal_rows(LzArgs a, int t0) {
 // matches the CSR-stream form bit for bit.
 template <typename T, bool HAS_VAL, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_spmv_bal(LzArgs a, int j) {
+  if (all_stopped(a, j)) return;
   __shared__ int rp_lds[kStreamRows + 1];
   __shared__ T prod[StreamShape<T>::CAP];
   __shared__ double chunks[kMaxChunks];
@@ -345,6 +348,7 @@ __device__ inline void spmv_staged_block(const int32_t* __restrict__ rp, const i
 
 template <typename T, bool HAS_VAL>
 __global__ __launch_bounds__(kStagedThreads) void k_spmv_staged(LzArgs a, int j) {
+  if (all_stopped(a, j)) return;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int rp_lds[kRowsPerBlock + 1];
   __shared__ T w_lds[kRowsPerBlock];
@@ -779,6 +783,7 @@ __device__ inline void wave_lds_sync() {
 // are issued before the step is opened.
 template <typename T, bool HAS_VAL, bool VEC>
 __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
+  if (all_stopped(a, j)) return;
   extern __shared__ __align__(16) unsigned char smem[];
   using SS = SegShape<T>;
   constexpr int NT = kSegThreads, UE = SS::UE, XP = SS::XP, WCAP = SS::WCAP;
@@ -1081,6 +1086,7 @@ __device__ inline void seg4_block(const LzArgs& a, int j, int blk, const SegBloc
 
 template <bool HAS_VAL, bool VEC>
 __global__ __launch_bounds__(kSegThreads) void k_spmv_seg4(LzArgs a, int j) {
+  if (all_stopped(a, j)) return;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ __align__(16) float prod[kSegWaves * SegShape<float>::WCAP];
   __shared__ int p_lds[kRowsPerBlock + 1];  // stream fallback only
@@ -1273,6 +1279,7 @@ __global__ __launch_bounds__(kPanPrepThreads) void k_pan_place(LzArgs a) {
 // Products of one work item: panel `panel` of units [b0, b1), one contiguous range of entries.
 template <typename T, bool HAS_VAL>
 __global__ __launch_bounds__(kPanProdThreads) void k_pan_products(LzArgs a, int j) {
+  if (all_stopped(a, j)) return;
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NT = kPanProdThreads, U = 8;
   T* slice = (T*)smem;
@@ -1361,6 +1368,7 @@ __global__ __launch_bounds__(kPanProdThreads) void k_pan_products(LzArgs a, int 
 
 template <typename T, bool HAS_VAL>
 __global__ __launch_bounds__(kPanRowThreads) void k_pan_rows(LzArgs a, int j) {
+  if (all_stopped(a, j)) return;
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NT = kPanRowThreads, U = 16;
   T* pl = (T*)smem;  // the unit's products in CSR order

@@ -22,6 +22,7 @@ namespace {
 // mode 0: final; mode 1: adaptive check after step j (tridiag_prepare). One wave per realization.
 __global__ __launch_bounds__(64) void k_tridiag_state(LzArgs args, int64_t first, int mode, int j, int m_steps,
                                                       int shift, double tol, ebtc_diag* diag, double* ckpt) {
+  if (mode == 1 && all_stopped(args, j)) return;
   __shared__ double a[kMLimit];
   __shared__ double b[kMLimit];
   __shared__ double chunks[kMaxChunks];

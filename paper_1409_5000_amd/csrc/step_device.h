@@ -569,6 +569,8 @@ __device__ inline void tridiag_finish(const LzArgs& args, RState* st, int64_t r,
         st->flags = flags;
         st->done = 1;
         st->m_used = k;
+      } else if (args.live != nullptr) {
+        atomicAdd(&args.live[j], 1);
       }
     }
     return;

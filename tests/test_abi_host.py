@@ -128,6 +128,7 @@ def expected_ws(G, nreal, n, m_slots, es, rstate_bytes):
     off = align(off + rstate_bytes * R)
     off = align(off + 8 * A.M_LIMIT * blocks)  # dot partials: one per basis vector and row block
     off = align(off + 8 * blocks)
+    off = align(off + 4 * A.M_LIMIT)  # realizations still running after each step (adaptive runs)
     off = align(off + es * m_slots * rows)
     off = align(off + es * rows)
     off = align(off + es * rows)
