@@ -4,6 +4,8 @@ Bars: FP64 mode 1e-12 (normwise and on the oracle's top-2K), FP32 mode 1e-5, ide
 (tie band rule in tests/parity.py), identical m_used for fixed m. Integer work (SpMV on 0/1
 patterns in FP64, top-K indices) is compared exactly.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -315,6 +317,31 @@ def test_schedules_agree_bitwise(gpu_lib):
         outs.append(o.scores.cpu().numpy().copy())
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])  # fixed-order reductions: deterministic across schedules
+
+
+def test_adaptive_runs_agree_across_schedules(gpu_lib):
+    # adaptive m: realizations of different graphs stop at different steps, all well before the cap,
+    # so the batched runs' launches after the last stop return at once; the plain loop (which runs
+    # every launch) and the batched sequence, eager and replayed, give the same bits and diagnostics
+    torch = torch_mod()
+    w = C.scaled(C.workload(4), graphs=slice(0, 4))
+    specs = [dict(n=3000, N=3), dict(n=5001, N=2), dict(n=2500, N=2), dict(n=7000, N=1)]
+    w = dataclasses.replace(w, graphs=tuple(dataclasses.replace(s, **kw) if s.family != "er" else
+                                            dataclasses.replace(s, bg=s.bg * (s.n - 1) / (kw["n"] - 1), **kw)
+                                            for s, kw in zip(w.graphs, specs)))
+    hb = C.build(w)
+    b = api().Batch.from_host(hb)
+    outs = []
+    for sched, hg in (("plain", False), ("batched", False), ("batched", True), ("batched", True)):
+        o = b.scores(m=0, tol=1e-6, m_max=60, schedule=sched, hipgraph=hg)
+        torch.cuda.synchronize()
+        outs.append((o.scores.cpu().numpy().copy(), o.log_scale.cpu().numpy().copy(), o.diag_numpy()))
+    m_used = outs[0][2]["m_used"]
+    assert m_used.max() < 60 and len(set(m_used.tolist())) > 1  # stops before the cap, at several steps
+    for sc, ls, dg in outs[1:]:
+        assert np.array_equal(sc, outs[0][0]) and np.array_equal(ls, outs[0][1])
+        for key in ("m_used", "flags", "theta", "est"):
+            assert np.array_equal(dg[key], outs[0][2][key]), key
 
 
 @pytest.mark.parametrize("form,seg_len,lanes", [("lanes", 0, 0), ("lanes", 0, 16), ("staged", 3001, 0),
