@@ -103,6 +103,30 @@ def test_segmented_fp32_ragged_slices_bitwise(gpu_lib, seg_len):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_segmented_rows_not_ascending(gpu_lib, dtype):
+    # rows stored with their columns in no order: the sort keeps each row's stored order within a
+    # segment, so the sums (segment by segment) differ from the stream form's in their order only and
+    # agree with it and with the oracle to the working precision
+    w = dataclasses.replace(C.scaled(C.workload(1), n=9000, N=2), dtype=dtype)
+    hb = C.build(w, with_values=True)
+    hb.values = symmetric_weights(hb, seed=7)
+    rng = np.random.default_rng(5)
+    for r in range(hb.R):
+        n, rp, ci, _ = hb.csr(r)
+        a = int(hb.nnz_off[r])
+        for i in range(n):
+            k0, k1 = a + int(rp[i]), a + int(rp[i + 1])
+            perm = k0 + rng.permutation(k1 - k0)
+            hb.col_idx[k0:k1] = hb.col_idx[perm]
+            hb.values[k0:k1] = hb.values[perm]
+    b, ref, seg = run_pair(hb, w.m, seg_len=1000)
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    r_, s_ = ref.scores.cpu().numpy(), seg.scores.cpu().numpy()
+    assert np.max(np.abs(r_ - s_)) <= tol * np.max(np.abs(r_))
+    check_against_oracle(hb, seg, b, w.m, dtype, K=50)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_segmented_large_segments_prefetched_bitwise(gpu_lib, dtype):
     # n = 40000, degree 8: the default segment (12288 FP32 / 6144 FP64 columns, two LDS buffers)
     # holds about 315 / 157 entries of a wave's 128 rows, within its product slots
