@@ -940,11 +940,11 @@ __global__ __launch_bounds__(kSegThreads) void k_spmv_seg(LzArgs a, int j) {
 // lane issues the same loads for every segment: its band's quad slots, its share of the slice and its
 // counts. Slots past the band, past the block, and segments past the last are pointed past the end of
 // their buffer resource and read zeros without touching memory (the range check). So where a
-// segment's registers are read, the compiler knows how many later loads may stay in
-// flight. The loads of segment s + 2 are issued as soon as segment s's products are formed and stay
-// in flight while segment s + 1 is staged, about two segments before they are used; two register
-// sets take the segments of even and odd index. The sums are those of the form above, bit for bit:
-// the same products added to the same FP64 row sums in the same order.
+// segment's registers are read, the compiler knows how many later loads may stay in flight. The
+// loads of segment s + 2 are issued as soon as segment s's products are formed and stay in flight
+// while segment s + 1 is staged, about two segments before they are used; two register sets take the
+// segments of even and odd index. The sums are those of the form above, bit for bit: the same
+// products added to the same FP64 row sums in the same order.
 // One row block with UQ quad slots per lane and segment (its largest band holds at most 256 UQ
 // slots). smem: the two slice buffers; prod: the waves' product slots; p_lds, chunks, red: scratch of
 // the stream arithmetic and the step's opening.
