@@ -743,6 +743,29 @@ __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
 }
 
+// A row block's descriptor with its fields in scalar registers. The buffer resources built from them
+// must be wave-uniform; a field read with a vector load (the compiler's choice) would put them in
+// vector registers, and every load through them would then loop over the wave's distinct values.
+struct SegDesc {
+  int64_t entries, vec_off;
+  int n, nnz, rows, flag;
+};
+__device__ inline int64_t wave_uniform(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ inline SegDesc seg_desc(const SegBlock* d) {
+  SegDesc r;
+  r.entries = wave_uniform(d->entries);
+  r.vec_off = wave_uniform(d->vec_off);
+  r.n = __builtin_amdgcn_readfirstlane(d->n);
+  r.nnz = __builtin_amdgcn_readfirstlane(d->nnz);
+  r.rows = __builtin_amdgcn_readfirstlane((int)d->rows);
+  r.flag = __builtin_amdgcn_readfirstlane((int)d->flag);
+  return r;
+}
+
 // Cache-policy operand of a buffer load that streams the matrix (read once per product): the
 // non-temporal bit, so that the L2 keeps the lines of the vector slices instead (measured: 4% off the
 // segmented product, and the dot kernel that reads its output gains as well).
@@ -956,16 +979,17 @@ __device__ inline void seg4_block(const LzArgs& a, int j, int blk, const SegBloc
   constexpr int NT = kSegThreads, XP = SS::XP, WCAP = SS::WCAP, WO = kSegWaves + 1;
   static_assert(UQ >= 1 && 256 * UQ <= WCAP && XP % 4 == 0, "quad slots within the product slots");
   const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int n = d->n, rows = d->rows, flag = d->flag, E = d->nnz;
+  const SegDesc dd = seg_desc(d);
+  const int n = dd.n, rows = dd.rows, flag = dd.flag, E = dd.nnz;
   const int SEG = a.seg_cols, S = (n + SEG - 1) / SEG, rows2 = (rows + 1) & ~1, QEND = (E + 3) >> 2;
   T* pw = prod + wv * WCAP;
-  const T* x = (const T*)a.V + d->vec_off + vslot(a, j) * n;
+  const T* x = (const T*)a.V + dd.vec_off + vslot(a, j) * n;
   const uint8_t* cnt = a.seg_cnt + (size_t)blk * a.seg_stride;
   const uint16_t* wo = a.seg_woff + (size_t)blk * a.seg_wstride;
   const int rr = 2 * tid;  // this lane's two rows
-  const __amdgpu_buffer_rsrc_t r_pc = make_rsrc(a.seg_col + d->entries, 2 * E);
+  const __amdgpu_buffer_rsrc_t r_pc = make_rsrc(a.seg_col + dd.entries, 2 * E);
   const __amdgpu_buffer_rsrc_t r_pv =
-      make_rsrc(HAS_VAL ? (const T*)a.seg_val + d->entries : nullptr, HAS_VAL ? 4 * E : 0);
+      make_rsrc(HAS_VAL ? (const T*)a.seg_val + dd.entries : nullptr, HAS_VAL ? 4 * E : 0);
   const __amdgpu_buffer_rsrc_t r_cnt = make_rsrc(cnt, S * rows2);
   const __amdgpu_buffer_rsrc_t r_x = make_rsrc(x, 4 * n);
   struct Set {
