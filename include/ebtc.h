@@ -403,9 +403,9 @@ typedef struct {
   const int32_t* pattern; /* host [pattern_edges][2]: local ends a != b in [0, t)                 */
 } ebtc_gen_spec;
 
-/* Workspace bytes for one ebtc_generate_count / ebtc_generate_fill pair (host call; the radix sort's
- * temporary storage depends on the current device's architecture, so a device must be present,
- * else EBTC_EHIP after the spec has been validated). Validates the spec: EBTC_EINVAL for out-of-range fields, repeated targets or bad pattern ends; EBTC_ENOTSUPPORTED
+/* Workspace bytes for one ebtc_generate_count / ebtc_generate_fill pair (host call; needs no device:
+ * the sizes, the radix sort's and scan's temporary storage included, follow from the spec alone).
+ * Validates the spec: EBTC_EINVAL for out-of-range fields, repeated targets or bad pattern ends; EBTC_ENOTSUPPORTED
  * when the keys (realization, a, b) would not fit 63 bits (count n^2 >= 2^63: draw fewer
  * realizations per call). For G(n, p) the candidate buffer holds the mean edge count plus 8
  * standard deviations per realization. */

@@ -8,14 +8,11 @@
 //      are appended;
 //   2. radix sort over the bits the keys use, unique compaction (repeats and invalid keys dropped),
 //      per-row degrees (integer atomics: the counts do not depend on their order), exclusive scan
-//      into the row pointers;
+//      into the row pointers (the scan and the sort are this file's own kernels, below);
 //   3. both directions of every edge, radix-sorted: the CSR entries in order (rows ascending,
 //      columns ascending within a row).
 // ebtc_generate_fill scatters the sorted entries' columns to the caller's col_idx. Every random
 // draw is a Philox4x32-10 block of its own counter, so the result is a function of the spec alone.
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
-
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -324,9 +321,202 @@ __global__ __launch_bounds__(kGenBlock) void k_scatter_cols(const uint64_t* dir_
   col_idx[dest[rl] + (t - S[rl * n])] = (int32_t)(key % (uint64_t)n);
 }
 
+// ------------------------------------------------------------------------- scan and radix sort
+// A device-wide exclusive scan of 32-bit counts into 64-bit offsets (tile sums, their scan in one
+// workgroup, each tile scanned from its offset), and an LSD radix sort of 64-bit keys: one pass per
+// 8-bit digit of the bits the keys use, each a per-tile digit histogram, a scan of the counts in
+// (digit, tile) order and a scatter. Every pass is stable, as an LSD sort needs: a tile's keys are
+// ranked in index order, within a wave by ballots over the digit's bits, then wave after wave and
+// round after round, so keys of one digit leave a tile in the order they came.
+constexpr int kScanThreads = 1024, kScanItems = 8, kScanTile = kScanThreads * kScanItems;
+constexpr int kSortThreads = 1024, kSortRounds = 4, kSortTile = kSortThreads * kSortRounds, kRadix = 256;
+
+// Exclusive prefix sum of one int64 per thread over a workgroup of NT threads; *total = the sum of
+// all. wtot: NT / 64 words. Ends with a barrier, so wtot may be reused.
+template <int NT>
+__device__ inline int64_t block_excl_scan64(int64_t v, int64_t* wtot, int64_t* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) wtot[w] = inc;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+  for (int i = 0; i < NT / 64; ++i) {
+    const int64_t t = wtot[i];
+    before += i < w ? t : 0;
+    all += t;
+  }
+  __syncthreads();
+  *total = all;
+  return before + inc - v;
+}
+
+// tsum[b] = the sum of tile b (kScanTile values)
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int32_t* in, int64_t n, int64_t* tsum) {
+  __shared__ int64_t wtot[kScanThreads / 64];
+  const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+  int64_t v = 0;
+  for (int u = 0; u < kScanItems; ++u) {
+    const int64_t i = t0 + (int64_t)u * kScanThreads + threadIdx.x;
+    if (i < n) v += in[i];
+  }
+  int64_t total;
+  block_excl_scan64<kScanThreads>(v, wtot, &total);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = total;
+}
+
+// the tile sums' exclusive scan in place: one workgroup, kScanThreads sums at a time with a carry
+__global__ __launch_bounds__(kScanThreads) void k_scan_carry(int64_t* tsum, int64_t nt) {
+  __shared__ int64_t wtot[kScanThreads / 64];
+  int64_t carry = 0;
+  for (int64_t c0 = 0; c0 < nt; c0 += kScanThreads) {
+    const int64_t i = c0 + threadIdx.x;
+    const int64_t v = i < nt ? tsum[i] : 0;
+    int64_t total;
+    const int64_t ex = block_excl_scan64<kScanThreads>(v, wtot, &total);
+    if (i < nt) tsum[i] = carry + ex;
+    carry += total;
+  }
+}
+
+// out[i] = tile offset + the sum of the tile's values before i; thread t takes kScanItems adjacent
+// values of its tile
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* in, int64_t* out, int64_t n,
+                                                             const int64_t* tsum) {
+  __shared__ int64_t wtot[kScanThreads / 64];
+  const int64_t b = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int32_t v[kScanItems];
+  int64_t sum = 0;
+#pragma unroll
+  for (int u = 0; u < kScanItems; ++u) {
+    v[u] = b + u < n ? in[b + u] : 0;
+    sum += v[u];
+  }
+  int64_t total;
+  int64_t run = tsum[blockIdx.x] + block_excl_scan64<kScanThreads>(sum, wtot, &total);
+#pragma unroll
+  for (int u = 0; u < kScanItems; ++u) {
+    if (b + u < n) out[b + u] = run;
+    run += v[u];
+  }
+}
+
+// cnt[d * nt + b] = keys of tile b whose digit at `shift` is d
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* keys, int64_t n, int shift, int32_t* cnt,
+                                                             int64_t nt) {
+  __shared__ int h[kRadix];
+  for (int d = threadIdx.x; d < kRadix; d += kSortThreads) h[d] = 0;
+  __syncthreads();
+  const int64_t t0 = (int64_t)blockIdx.x * kSortTile;
+  for (int u = 0; u < kSortRounds; ++u) {
+    const int64_t i = t0 + (int64_t)u * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(int)((keys[i] >> shift) & (kRadix - 1))], 1);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < kRadix; d += kSortThreads) cnt[(int64_t)d * nt + blockIdx.x] = h[d];
+}
+
+// Stable scatter of tile b by the digit at `shift`: off[d * nt + b] = where tile b's first key of
+// digit d goes (the scanned histogram). Each round takes kSortThreads consecutive keys.
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* in, uint64_t* out, int64_t n, int shift,
+                                                                const int64_t* off, int64_t nt) {
+  constexpr int NW = kSortThreads / 64;
+  __shared__ int64_t base[kRadix];  // where the tile's next key of each digit goes
+  __shared__ int wc[NW][kRadix];    // the round's counts per wave and digit, then their offsets
+  __shared__ int tot[kRadix];       // the round's counts per digit
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int d = tid; d < kRadix; d += kSortThreads) base[d] = off[(int64_t)d * nt + blockIdx.x];
+  const int64_t t0 = (int64_t)blockIdx.x * kSortTile;
+  const uint64_t below = (1ull << lane) - 1ull;  // the lanes before this one
+  for (int u = 0; u < kSortRounds; ++u) {
+    const int64_t i = t0 + (int64_t)u * kSortThreads + tid;
+    const bool valid = i < n;
+    const uint64_t key = valid ? in[i] : 0ull;
+    const int d = (int)((key >> shift) & (kRadix - 1));
+    uint64_t peers = __ballot(valid);  // the wave's lanes holding a key of the same digit
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1;
+      const uint64_t m = __ballot(on);
+      peers &= on ? m : ~m;
+    }
+    const int rank = __popcll(peers & below);
+    for (int x = lane; x < kRadix; x += 64) wc[w][x] = 0;
+    __syncthreads();
+    if (valid && rank == 0) wc[w][d] = __popcll(peers);
+    __syncthreads();
+    if (tid < kRadix) {
+      int run = 0;
+      for (int v = 0; v < NW; ++v) {
+        const int c = wc[v][tid];
+        wc[v][tid] = run;
+        run += c;
+      }
+      tot[tid] = run;
+    }
+    __syncthreads();
+    if (valid) out[base[d] + wc[w][d] + rank] = key;
+    __syncthreads();
+    if (tid < kRadix) base[tid] += tot[tid];
+  }
+}
+
 // ------------------------------------------------------------------------------------ host side
 size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 unsigned grid(int64_t threads) { return (unsigned)((threads + kGenBlock - 1) / kGenBlock); }
+
+int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+int64_t sort_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+size_t scan_tmp_bytes(int64_t n) { return align_up(sizeof(int64_t) * (size_t)std::max<int64_t>(1, scan_tiles(n))); }
+// the alternate key buffer, the digit counts and their offsets, the offsets' scan
+size_t sort_tmp_bytes(int64_t n) {
+  const size_t nt = (size_t)std::max<int64_t>(1, sort_tiles(n));
+  return align_up(sizeof(uint64_t) * (size_t)std::max<int64_t>(1, n)) + align_up(sizeof(int32_t) * kRadix * nt) +
+         align_up(sizeof(int64_t) * kRadix * nt) + scan_tmp_bytes((int64_t)(kRadix * nt));
+}
+
+// out[i] = in[0] + ... + in[i - 1] for i < n (tmp: scan_tmp_bytes(n))
+hipError_t scan_i32_i64(void* tmp, const int32_t* in, int64_t* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nt = scan_tiles(n);
+  int64_t* tsum = (int64_t*)tmp;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(kScanThreads), 0, s, in, n, tsum);
+  hipLaunchKernelGGL(k_scan_carry, dim3(1), dim3(kScanThreads), 0, s, tsum, nt);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(kScanThreads), 0, s, in, out, n, (const int64_t*)tsum);
+  return hipGetLastError();
+}
+
+// out = in sorted by bits [0, end_bit) of the keys, whole keys moved (tmp: sort_tmp_bytes(n)); in is
+// not written
+hipError_t radix_sort_u64(void* tmp, const uint64_t* in, uint64_t* out, int64_t n, int end_bit, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nt = sort_tiles(n);
+  char* t = (char*)tmp;
+  uint64_t* buf = (uint64_t*)t;
+  t += align_up(sizeof(uint64_t) * (size_t)n);
+  int32_t* cnt = (int32_t*)t;
+  t += align_up(sizeof(int32_t) * kRadix * (size_t)nt);
+  int64_t* off = (int64_t*)t;
+  t += align_up(sizeof(int64_t) * kRadix * (size_t)nt);
+  const int passes = std::max(1, (end_bit + 7) / 8);
+  const uint64_t* src = in;
+  for (int p = 0; p < passes; ++p) {
+    uint64_t* dst = (passes - 1 - p) % 2 == 0 ? out : buf;  // the last pass writes out
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nt), dim3(kSortThreads), 0, s, src, n, 8 * p, cnt, nt);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = scan_i32_i64(t, cnt, off, kRadix * nt, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nt), dim3(kSortThreads), 0, s, src, dst, n, 8 * p,
+                       (const int64_t*)off, nt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    src = dst;
+  }
+  return hipSuccess;
+}
 
 struct GenPlan {
   int64_t rows = 0;        // count * n
@@ -399,21 +589,9 @@ int make_plan(const ebtc_gen_spec* s, GenPlan* P) {
   P->cap = P->cap_bg + (int64_t)s->count * s->pattern_edges;
   P->limit = (uint64_t)s->count * (uint64_t)s->n * (uint64_t)s->n;
   P->end_bit = 64 - __builtin_clzll(P->limit | 1);
-  size_t tb = 0, need = 0;
   const size_t cap = (size_t)std::max<int64_t>(P->cap, 1), rows = (size_t)std::max<int64_t>(P->rows, 1);
-  if (rocprim::radix_sort_keys(nullptr, tb, (uint64_t*)nullptr, (uint64_t*)nullptr, cap, 0, P->end_bit) !=
-      hipSuccess)
-    return report_error(EBTC_EHIP, "radix sort size query failed");
-  need = std::max(need, tb);
-  if (rocprim::radix_sort_keys(nullptr, tb, (uint64_t*)nullptr, (uint64_t*)nullptr, 2 * cap, 0, P->end_bit) !=
-      hipSuccess)
-    return report_error(EBTC_EHIP, "radix sort size query failed");
-  need = std::max(need, tb);
-  const size_t scan_n = std::max(cap, rows);
-  if (rocprim::exclusive_scan(nullptr, tb, (const int32_t*)nullptr, (int64_t*)nullptr, int64_t(0), scan_n,
-                              rocprim::plus<int64_t>()) != hipSuccess)
-    return report_error(EBTC_EHIP, "scan size query failed");
-  need = std::max(need, tb);
+  const size_t need = std::max({sort_tmp_bytes((int64_t)cap), sort_tmp_bytes(2 * (int64_t)cap),
+                                scan_tmp_bytes((int64_t)std::max(cap, rows))});
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -515,12 +693,10 @@ extern "C" int ebtc_generate_count(const ebtc_gen_spec* spec, void* ws, size_t w
     GEN_LAUNCH(k_mark, dim3(1), dim3(kGenBlock), 0, s, (const int32_t*)(w + P.off_host), spec->t,
                (uint8_t*)(w + P.off_inside));
   }
-  size_t tb = P.tmp_bytes;
   if (spec->family == EBTC_GEN_ER) {
     GEN_LAUNCH(k_er_rows<false>, dim3(grid(P.rows)), dim3(kGenBlock), 0, s, a, cnt, (const int64_t*)nullptr,
                (uint64_t*)nullptr, (int64_t)0);
-    GEN_HIP(rocprim::exclusive_scan(tmp, tb, (const int32_t*)cnt, S, int64_t(0), (size_t)P.rows,
-                                    rocprim::plus<int64_t>(), s));
+    GEN_HIP(scan_i32_i64(tmp, (const int32_t*)cnt, S, P.rows, s));
     GEN_LAUNCH(k_er_total, dim3(1), dim3(1), 0, s, (const int32_t*)cnt, (const int64_t*)S, P.rows, P.cap_bg, hdr);
     GEN_LAUNCH(k_er_rows<true>, dim3(grid(P.rows)), dim3(kGenBlock), 0, s, a, cnt, (const int64_t*)S, A, P.cap_bg);
     if (P.cap_bg > 0) GEN_LAUNCH(k_er_tail, dim3(grid(P.cap_bg)), dim3(kGenBlock), 0, s, (const int64_t*)hdr, A, P.cap_bg);
@@ -536,11 +712,9 @@ extern "C" int ebtc_generate_count(const ebtc_gen_spec* spec, void* ws, size_t w
   }
   const size_t cap = (size_t)P.cap;
   if (cap > 0) {
-    tb = P.tmp_bytes;
-    GEN_HIP(rocprim::radix_sort_keys(tmp, tb, A, Aout, cap, 0, P.end_bit, s));
+    GEN_HIP(radix_sort_u64(tmp, A, Aout, P.cap, P.end_bit, s));
     GEN_LAUNCH(k_unique_flags, dim3(grid(P.cap)), dim3(kGenBlock), 0, s, (const uint64_t*)Aout, P.cap, P.limit, flags);
-    tb = P.tmp_bytes;
-    GEN_HIP(rocprim::exclusive_scan(tmp, tb, (const int32_t*)flags, pos, int64_t(0), cap, rocprim::plus<int64_t>(), s));
+    GEN_HIP(scan_i32_i64(tmp, (const int32_t*)flags, pos, P.cap, s));
     GEN_LAUNCH(k_unique_scatter, dim3(grid(P.cap)), dim3(kGenBlock), 0, s, (const uint64_t*)Aout,
                (const int32_t*)flags, (const int64_t*)pos, P.cap, A, hdr);
   }
@@ -548,16 +722,13 @@ extern "C" int ebtc_generate_count(const ebtc_gen_spec* spec, void* ws, size_t w
   if (cap > 0)
     GEN_LAUNCH(k_degrees, dim3(grid(P.cap)), dim3(kGenBlock), 0, s, (const uint64_t*)A, (const int64_t*)hdr, P.cap, n,
                cnt);
-  tb = P.tmp_bytes;
-  GEN_HIP(rocprim::exclusive_scan(tmp, tb, (const int32_t*)cnt, S, int64_t(0), (size_t)P.rows,
-                                  rocprim::plus<int64_t>(), s));
+  GEN_HIP(scan_i32_i64(tmp, (const int32_t*)cnt, S, P.rows, s));
   GEN_LAUNCH(k_row_ptr, dim3(grid((int64_t)spec->count * (n + 1))), dim3(kGenBlock), 0, s, (const int32_t*)cnt,
              (const int64_t*)S, n, spec->count, (const int64_t*)hdr, row_ptr, nnz, (int32_t*)(w + P.off_ok));
   if (cap > 0) {
     GEN_LAUNCH(k_directed, dim3(grid(P.cap)), dim3(kGenBlock), 0, s, (const uint64_t*)A, (const int64_t*)hdr, P.cap,
                n, C);
-    tb = P.tmp_bytes;
-    GEN_HIP(rocprim::radix_sort_keys(tmp, tb, C, Cout, 2 * cap, 0, P.end_bit, s));
+    GEN_HIP(radix_sort_u64(tmp, C, Cout, 2 * P.cap, P.end_bit, s));
   }
   return EBTC_OK;
 }

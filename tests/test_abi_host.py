@@ -446,6 +446,19 @@ def test_generate_plan_validates(kw, code, text):
     assert A.lib().ebtc_generate_plan(ctypes.byref(spec), None) == A.EBTC_EINVAL
 
 
+def test_generate_plan_needs_no_device():
+    # the workspace, the sort's and scan's temporary storage included, follows from the spec alone;
+    # it grows with the realizations per call
+    from paper_1409_5000_amd.api import _gen_spec
+    sizes = []
+    for count in (1, 4):
+        spec, keep = _gen_spec(family="er", n=20000, p=1e-3, count=count, seed=7)
+        ws = ctypes.c_size_t()
+        assert A.lib().ebtc_generate_plan(ctypes.byref(spec), ctypes.byref(ws)) == 0
+        sizes.append(ws.value)
+    assert 0 < sizes[0] < sizes[1]
+
+
 def test_generate_spec_layout():
     # the C struct: int32 family, n; double p; int32 k, count; double beta; uint64 seed; int64 first;
     # int32 t, pattern_edges; two pointers
