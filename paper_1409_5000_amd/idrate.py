@@ -100,7 +100,8 @@ def identification_rates(col: Column, runs: int, seed: int, dtype: str = "f64", 
     flags = out.diag_numpy()["flags"]
     return {"column": col, "workload": w, "batch": hb, "idx": idx, "rates": rates, "mean": float(rates.mean()),
             "stderr": float(rates.std(ddof=1) / np.sqrt(len(rates))) if len(rates) > 1 else 0.0,
-            "perfect_runs": float(np.mean(rates == 1.0)), "nonfinite": int((flags & 4).sum()),
+            "perfect_runs": float(np.mean(rates == 1.0)), "best_run": float(rates.max()),
+            "nonfinite": int((flags & 4).sum()),
             "realizations": int(hb.R), "gen_s": t_gen, "gpu_s": t_gpu}
 
 
@@ -122,15 +123,18 @@ def main(argv=None) -> int:
         row = {"table": col.table, "background": col.family.upper(), "nodes": col.n, "degree": col.degree,
                "backgrounds": col.N, "target": col.target, "runs": args.runs,
                "rate_percent": round(100 * r["mean"], 1), "stderr_percent": round(100 * r["stderr"], 1),
-               "perfect_runs_percent": round(100 * r["perfect_runs"], 1), "paper_percent": col.paper_rate,
+               "perfect_runs_percent": round(100 * r["perfect_runs"], 1), "best_run_percent": round(100 * r["best_run"], 1),
+               "paper_percent": col.paper_rate,
                "realizations": r["realizations"], "gpu_s": round(r["gpu_s"], 3), "nonfinite": r["nonfinite"]}
         rows.append(row)
         print(json.dumps(row), flush=True)
-    print("\n| table | background | nodes | av. deg. | backgrounds | target | rate % (± s.e.) | runs at 100 % | paper % |")
-    print("|---|---|---|---|---|---|---|---|---|")
+    print("\n| table | background | nodes | av. deg. | backgrounds | target | rate % (± s.e.) | runs at 100 % | best run % "
+          "| paper % |")
+    print("|---|---|---|---|---|---|---|---|---|---|")
     for r in rows:
         print(f"| {r['table']} | {r['background']} | {r['nodes']} | {r['degree']} | {r['backgrounds']} | {r['target']} | "
-              f"{r['rate_percent']} ± {r['stderr_percent']} | {r['perfect_runs_percent']} | {r['paper_percent']} |")
+              f"{r['rate_percent']} ± {r['stderr_percent']} | {r['perfect_runs_percent']} | {r['best_run_percent']} | "
+              f"{r['paper_percent']} |")
     return 0
 
 
