@@ -1021,10 +1021,10 @@ int ebtc_batch_create(const ebtc_batch_desc* d, ebtc_batch** out) {
   b->dtype = d->dtype;
   b->G = d->num_graphs;
   b->R = d->num_realizations;
+  // the per-realization arrays are read only after R has been checked against graph_nreal, so an
+  // inconsistent count is reported instead of read past the caller's arrays
   b->n.assign(d->graph_n, d->graph_n + b->G);
   b->nreal.assign(d->graph_nreal, d->graph_nreal + b->G);
-  b->rowptr_off.assign(d->rowptr_off, d->rowptr_off + b->R);
-  b->nnz_off.assign(d->nnz_off, d->nnz_off + b->R + 1);
   b->row_ptr = d->row_ptr;
   b->col_idx = d->col_idx;
   b->values = d->values;
@@ -1052,6 +1052,8 @@ int ebtc_batch_create(const ebtc_batch_desc* d, ebtc_batch** out) {
     delete b;
     return fail(EBTC_EBADGRAPH, "num_realizations differs from the sum of graph_nreal");
   }
+  b->rowptr_off.assign(d->rowptr_off, d->rowptr_off + b->R);
+  b->nnz_off.assign(d->nnz_off, d->nnz_off + b->R + 1);
   if (blocks >= (int64_t)1 << 31) {
     delete b;
     return fail(EBTC_ENOTSUPPORTED, "too many row blocks for one launch");
