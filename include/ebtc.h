@@ -330,7 +330,8 @@ int ebtc_set_forms(ebtc_batch* batch, const int32_t* form, const int32_t* lanes,
  * (cap bytes; buf NULL: only *len, the text's length without the NUL, is set); ebtc_tune_cache_put
  * merges such text (later lines win; a saved cache restored in a new process skips the timing of the
  * compositions it holds); ebtc_tune_cache_clear empties it. Thread-safe.
- * Errors: EINVAL (NULL len or text, buffer too small, a malformed line). */
+ * Errors: EINVAL (NULL len or text, buffer too small, a malformed line: a form outside the enum, lanes
+ * other than 0, 4, 8, 16 or 32, a negative seg_len; the whole text is then refused). */
 int ebtc_tune_cache_get(char* buf, size_t cap, size_t* len);
 int ebtc_tune_cache_put(const char* text);
 int ebtc_tune_cache_clear(void);

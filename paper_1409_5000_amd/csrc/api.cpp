@@ -206,6 +206,8 @@ bool member(const Members* m, int32_t g) { return m == nullptr || (*m)[g] != 0; 
 std::vector<int64_t> bal_shares(const ebtc_batch* b, int e, const Members* m);
 
 int check_form(const ebtc_batch* b, const SpmvPlan& p, const Members* m) {
+  if (p.form == EBTC_SPMV_LANE_GROUPS && p.lanes != 4 && p.lanes != 8 && p.lanes != 16 && p.lanes != 32)
+    return fail(EBTC_EINVAL, "the lane-group SpMV takes 4, 8, 16 or 32 lanes per row");
   if (p.form == EBTC_SPMV_BALANCED) {
     if (p.balent < 256 || p.balent > (1 << 24))
       return fail(EBTC_EINVAL, "the entry-balanced SpMV takes shares of 256 to 2^24 entries (seg_len)");
@@ -1522,7 +1524,8 @@ int ebtc_tune_cache_put(const char* text) {
     std::istringstream in(line);
     std::string key, rest;
     int f = 0, l = 0, q = 0;
-    if (!(in >> key >> f >> l >> q) || (in >> rest) || f < EBTC_SPMV_STREAM || f > EBTC_SPMV_PANELED || l < 0 || q < 0)
+    if (!(in >> key >> f >> l >> q) || (in >> rest) || f < EBTC_SPMV_STREAM || f > EBTC_SPMV_PANELED ||
+        (l != 0 && l != 4 && l != 8 && l != 16 && l != 32) || q < 0)
       return fail(EBTC_EINVAL, "bad tune-cache line: " + line);
     add[key] = {f, l, q};
   }

@@ -266,7 +266,7 @@ def test_tune_cache_text_roundtrip_and_errors():
     # later lines win; malformed lines are refused whole
     assert L.ebtc_tune_cache_put(b"f32v-n16-d8-h2-s4 1 0 0\n") == 0
     assert "f32v-n16-d8-h2-s4 1 0 0" in _cache_text()
-    for bad in (b"key 9 0 0", b"key 4 0", b"key 4 -1 0", b"key x 0 0"):
+    for bad in (b"key 9 0 0", b"key 4 0", b"key 4 -1 0", b"key x 0 0", b"key 1 3 0", b"key 1 64 0"):
         assert L.ebtc_tune_cache_put(bad) == A.EBTC_EINVAL and "tune-cache line" in L.ebtc_last_error().decode()
     assert L.ebtc_tune_cache_put(None) == A.EBTC_EINVAL
     assert L.ebtc_tune_cache_get(None, 0, None) == A.EBTC_EINVAL
