@@ -616,8 +616,9 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
   for (int i = tid; i <= rows; i += NT) rp_lds[i] -= e0;
   __syncthreads();
   // counts per (segment, row): a row is visited by one thread, so no counter has two writers (the
-  // columns alone are staged: the values are not needed to count)
-  for_rows_staged<T, false, NT>(ci, nullptr, rp_lds, rows, cap, lci, lva,
+  // columns alone are staged, in the values' share of the staging area as well: the values are not
+  // needed to count, so a chunk holds (4 + sizeof(T)) / 4 times the entries of a placement chunk)
+  for_rows_staged<T, false, NT>(ci, nullptr, rp_lds, rows, HAS_VAL ? cap / 4 * (4 + (int)sizeof(T)) : cap, lci, lva,
                                   [&](int r, const int* cs, const T*, int k, int e) {
                                     for (; k < e; ++k) {
                                       const int c = cs[k];
