@@ -34,6 +34,14 @@ def test_er_with_target_bitwise(gpu_lib):
     check_against_oracle("er", 3000, 4, first=7, p=0.004, targets=t, pattern=pattern)
 
 
+@pytest.mark.parametrize("n,passes", [(9, 1), (10, 2), (147, 2), (148, 3)])
+def test_sort_pass_boundaries_bitwise(gpu_lib, n, passes):
+    # the keys (realization, a, b) take the bits of count n^2 - 1: 3 n^2 = 243, 300, 64827, 65712
+    # give 8, 9, 16 and 17 bits, i.e. one, two, two and three 8-bit passes of the radix sort
+    assert ((3 * n * n | 1).bit_length() + 7) // 8 == passes
+    check_against_oracle("er", n, 3, p=0.3)
+
+
 @pytest.mark.parametrize("n,p", [(60, 1.0), (10, 0.0), (1, 0.5), (2, 0.5), (500, 1e-17), (257, 0.9)])
 def test_er_limits_bitwise(gpu_lib, n, p):
     _, _, nnz = check_against_oracle("er", n, 3, p=p)
