@@ -6,8 +6,10 @@
 //            partial dot products <v_i, w>, i <= j;
 //   phase B  reduces the dot partials, v~_{j+1} = w - sum_i h_i v_i (classical Gram-Schmidt against
 //            the whole basis) and the per-workgroup partial squared norm.
-// Workgroups never wait for each other inside a kernel and use no device-scope fences or atomics:
-// partial sums go to memory and the next kernel (after the launch boundary) reduces them. Every
+// Workgroups never wait for each other inside a kernel and use no device-scope fences or atomics
+// (the adaptive check alone counts the running realizations with an integer atomic, which the next
+// step's kernels read): partial sums go to memory and the next kernel (after the launch boundary)
+// reduces them. Every
 // reader uses the same canonical summation order, so all of them see bit-identical totals.
 // Every workgroup owns kRowsPerBlock consecutive rows of one realization. Launches either cover
 // one realization (plain loop) or every realization of the batch at once (batched), in which case

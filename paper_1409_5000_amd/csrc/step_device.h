@@ -570,6 +570,8 @@ __device__ inline void tridiag_finish(const LzArgs& args, RState* st, int64_t r,
         st->done = 1;
         st->m_used = k;
       } else if (args.live != nullptr) {
+        // the count of realizations still running after step j (an integer, so its value does not
+        // depend on the order of the adds); the next step's kernels read it after the launch boundary
         atomicAdd(&args.live[j], 1);
       }
     }
