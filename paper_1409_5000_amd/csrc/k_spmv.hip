@@ -536,6 +536,48 @@ __device__ inline void for_rows_staged(const int32_t* __restrict__ ci, const T* 
   }
 }
 
+// for_rows_staged with each entry staged as one byte, f(column), instead of its column, so a chunk
+// holds four times the entries: row_fn(r, s, first, last) sees the row's bytes at s[first, last). A
+// row longer than cap is passed with s = nullptr and [first, last) its entries' positions in ci.
+template <int NT, typename G, typename F>
+__device__ inline void for_rows_staged_u8(const int32_t* __restrict__ ci, const int* rp_lds, int rows, int cap,
+                                          uint8_t* ls, G f, F row_fn) {
+  const int tid = threadIdx.x;
+  int ra = 0;
+  while (ra < rows) {
+    const int k0 = rp_lds[ra];
+    if (rp_lds[ra + 1] - k0 > cap) {
+      if (tid == 0) row_fn(ra, (const uint8_t*)nullptr, k0, rp_lds[ra + 1]);
+      __syncthreads();
+      ++ra;
+      continue;
+    }
+    int lo = ra + 1, hi = rows;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (rp_lds[mid] - k0 <= cap) lo = mid; else hi = mid - 1;
+    }
+    const int rb = lo, ce = rp_lds[rb] - k0;
+    for (int q0 = tid; q0 < ce; q0 += NT * 8) {
+      int c[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = q0 + u * NT;
+        c[u] = k < ce ? ci[k0 + k] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = q0 + u * NT;
+        if (k < ce) ls[k] = f(c[u]);
+      }
+    }
+    __syncthreads();
+    for (int r = ra + tid; r < rb; r += NT) row_fn(r, (const uint8_t*)ls, rp_lds[r] - k0, rp_lds[r + 1] - k0);
+    __syncthreads();
+    ra = rb;
+  }
+}
+
 // One workgroup per row block. Dynamic LDS: the per-(segment, row) counters (16-bit, smax x 2048),
 // then a staging area for `cap` entries (columns, and values for weighted graphs).
 template <typename T, bool HAS_VAL>
@@ -615,25 +657,37 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_prepare(LzArgs a, int cap) 
   __syncthreads();  // every thread has read rp_lds[0] and rp_lds[rows]
   for (int i = tid; i <= rows; i += NT) rp_lds[i] -= e0;
   __syncthreads();
-  // counts per (segment, row): a row is visited by one thread, so no counter has two writers (the
-  // columns alone are staged, in the values' share of the staging area as well: the values are not
-  // needed to count, so a chunk holds (4 + sizeof(T)) / 4 times the entries of a placement chunk)
-  for_rows_staged<T, false, NT>(ci, nullptr, rp_lds, rows, HAS_VAL ? cap / 4 * (4 + (int)sizeof(T)) : cap, lci, lva,
-                                  [&](int r, const int* cs, const T*, int k, int e) {
-                                    for (; k < e; ++k) {
-                                      const int c = cs[k];
-                                      if ((unsigned)c >= (unsigned)n) {
-                                        bad = 1;
-                                        return;
-                                      }
-                                      const int idx = seg_of(c) * rows + r;
-                                      if (cnt[idx] == 255) {  // the step kernel reads 8-bit counts
-                                        bad = 1;
-                                        return;
-                                      }
-                                      cnt[idx] = (uint16_t)(cnt[idx] + 1);
-                                    }
-                                  });
+  // counts per (segment, row): a row is visited by one thread, so no counter has two writers. Only
+  // each entry's segment is needed to count, so the entries are staged as their segment numbers, one
+  // byte each (255: a column out of range), across the whole staging area: a chunk holds
+  // 4 + sizeof(T) times the entries of a placement chunk (one chunk for a row block of the n=1e5,
+  // degree-20 graph).
+  const int cap8 = cap * (4 + (HAS_VAL ? (int)sizeof(T) : 0));
+  const int32_t* ci_count = ci;
+  for_rows_staged_u8<NT>(
+      ci, rp_lds, rows, cap8, (uint8_t*)lci,
+      [&](int c) { return (unsigned)c < (unsigned)n ? (uint8_t)seg_of(c) : (uint8_t)255; },
+      [&](int r, const uint8_t* sg, int k, int e) {
+        for (; k < e; ++k) {
+          int q;
+          if (sg != nullptr) {
+            q = sg[k];
+          } else {  // a row longer than the staging area: its columns from memory
+            const int c = ci_count[k];
+            q = (unsigned)c < (unsigned)n ? seg_of(c) : 255;
+          }
+          if (q == 255) {
+            bad = 1;
+            return;
+          }
+          const int idx = q * rows + r;
+          if (cnt[idx] == 255) {  // the step kernel reads 8-bit counts
+            bad = 1;
+            return;
+          }
+          cnt[idx] = (uint16_t)(cnt[idx] + 1);
+        }
+      });
   if (bad) {
     direct_sums(va);
     finish(0, 0);
